@@ -1,0 +1,158 @@
+"""Spectrum bounds and the wanted threshold from a few Lanczos steps.
+
+Algorithm 1 starts with a few Lanczos steps to bound the spectrum (Sec. 4.1),
+and Algorithm 2 with a norm estimate alpha of ||A||_2 (Sec. 4.2).  The paper's
+interface is threshold-based (negative eigenvalues; singular values above
+s ||A||_2).  To serve a *fraction* of the spectrum, the same Lanczos runs are
+read as a stochastic Lanczos quadrature of the spectral counting function, and
+the threshold is placed so that an estimated k_t >= k eigenvalues lie above it.
+The paper is silent on this mapping; the reading below is used by both the
+oracle and the HIP path, and the solver checks the result a posteriori (the
+number of Rayleigh-Ritz values above the threshold must be at least k, which by
+interlacing certifies that the top-k values are among those captured).
+
+Lanczos definition (both sides):
+  * nv independent runs of m steps; run i starts from the Philox Gaussian
+    stream i, normalised;
+  * three-term recurrence with full re-orthogonalisation (classical
+    Gram-Schmidt applied twice);
+  * if beta_j <= 1e-10 * max_{i<=j}(|alpha_i| + beta_{i-1}) the run restarts
+    from the Philox stream nv + i*m + j, orthogonalised twice against the run's
+    basis, and beta_j is set to 0;
+  * T = tridiag(alpha, beta_1..beta_{m-1}); Ritz values theta, quadrature
+    weights (first eigenvector component)^2, residual bounds |beta_m y_m|.
+"""
+import math
+import numpy as np
+import scipy.linalg as sla
+
+from .philox import gaussian
+
+NV_DEFAULT = 8
+M_DEFAULT = 64
+
+
+def lanczos_steps(n, m_default=M_DEFAULT):
+    return max(1, min(m_default, n - 1))
+
+
+def lanczos_slq(op, n, seed, nv=NV_DEFAULT, m=None):
+    """Run ``nv`` Lanczos processes of ``m`` steps on the symmetric operator ``op``.
+
+    Returns dict with per-run alpha (nv, m), beta (nv, m) (beta[:, m-1] is the
+    final residual norm) and the pooled Ritz nodes, weights and residual bounds.
+    """
+    m = lanczos_steps(n) if m is None else m
+    alpha = np.zeros((nv, m))
+    beta = np.zeros((nv, m))
+    for i in range(nv):
+        Q = np.zeros((n, m))
+        g = gaussian(seed, i, n)
+        Q[:, 0] = g / np.linalg.norm(g)
+        amax = 0.0
+        for j in range(m):
+            w = op(Q[:, j])
+            a = float(Q[:, j] @ w)
+            w = w - a * Q[:, j]
+            if j > 0:
+                w = w - beta[i, j - 1] * Q[:, j - 1]
+            for _ in range(2):
+                w = w - Q[:, :j + 1] @ (Q[:, :j + 1].T @ w)
+            bj = float(np.linalg.norm(w))
+            alpha[i, j] = a
+            amax = max(amax, abs(a) + (beta[i, j - 1] if j > 0 else 0.0))
+            if j == m - 1:
+                beta[i, j] = bj
+                break
+            if bj <= 1e-10 * amax:
+                g = gaussian(seed, nv + i * m + j, n)
+                for _ in range(2):
+                    g = g - Q[:, :j + 1] @ (Q[:, :j + 1].T @ g)
+                Q[:, j + 1] = g / np.linalg.norm(g)
+                beta[i, j] = 0.0
+            else:
+                Q[:, j + 1] = w / bj
+                beta[i, j] = bj
+    nodes, weights, resid = [], [], []
+    for i in range(nv):
+        if m == 1:
+            th, Y = alpha[i, :1].copy(), np.ones((1, 1))
+        else:
+            th, Y = sla.eigh_tridiagonal(alpha[i], beta[i, :m - 1])
+        nodes.append(th)
+        weights.append(Y[0, :] ** 2)
+        resid.append(np.abs(beta[i, m - 1] * Y[m - 1, :]))
+    nodes = np.concatenate(nodes)
+    weights = np.concatenate(weights)
+    resid = np.concatenate(resid)
+    return dict(alpha=alpha, beta=beta, nodes=nodes, weights=weights, resid=resid,
+                nv=nv, m=m, n=n,
+                lmax=float(np.max(nodes + resid)), lmin=float(np.min(nodes - resid)))
+
+
+def count_above(est, t):
+    """Quadrature estimate of #{eigenvalues >= t}."""
+    return est["n"] / est["nv"] * float(np.sum(est["weights"][est["nodes"] >= t]))
+
+
+def target_count(n, k, boost=1):
+    """k_t = k + max(16, ceil(k/10)), multiplied by ``boost`` on a retry, capped at n."""
+    return min(n, boost * (k + max(16, int(math.ceil(0.1 * k)))))
+
+
+def _cut_below(est, kt):
+    """Threshold below the node at which the estimated count first reaches kt.
+
+    Nodes are pooled over the runs and sorted downwards; the cut is placed
+    halfway between that node and the next node that is distinct from it
+    (more than 1e-6 of the estimated spectral spread below), so a cluster that
+    several runs resolve as one node is kept whole.  Returns None if the count
+    never reaches kt (everything wanted).
+    """
+    order = np.argsort(-est["nodes"], kind="stable")
+    th = est["nodes"][order]
+    cum = est["n"] / est["nv"] * np.cumsum(est["weights"][order])
+    hit = np.nonzero(cum >= kt - 1e-9)[0]
+    if len(hit) == 0 or kt >= est["n"]:
+        return None
+    j = int(hit[0])
+    spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
+    below = th[j + 1:][th[j + 1:] < th[j] - 1e-6 * spread]
+    if len(below) == 0:
+        return None
+    return 0.5 * (th[j] + float(below[0]))
+
+
+def choose_tau(est, k, boost=1):
+    """EIG threshold tau and scaling for the wanted top-k (Algorithm 1 setup).
+
+    Returns (tau, mu, rho): |mu| = lambda_max_hat - tau scales the wanted part
+    onto [-1, 0] (Sec. 4.1 scales by a Lanczos bound), rho = (tau - lambda_min_hat)/|mu|
+    bounds the largest unwanted scaled value.
+    """
+    n = est["n"]
+    kt = target_count(n, k, boost)
+    cut = _cut_below(est, kt)
+    tau = est["lmin"] if cut is None else cut
+    spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
+    mu = max(est["lmax"] - tau, 1e-3 * spread)
+    rho = max(0.0, (tau - est["lmin"]) / mu)
+    return tau, mu, rho
+
+
+def choose_svd_threshold(est, k, boost=1):
+    """SVD norm estimate alpha and relative threshold s (Algorithm 2 setup).
+
+    ``est`` comes from Lanczos on A^T A, so nodes are squared singular values.
+    alpha = sqrt(lambda_max_hat(A^T A)); s = sqrt(t)/alpha with t the cut for
+    the wanted count, clamped to [1e-15, 1].
+    """
+    n = est["n"]
+    alpha = math.sqrt(max(est["lmax"], 0.0))
+    if alpha == 0.0:
+        alpha = 1e-300
+    kt = target_count(n, k, boost)
+    cut = _cut_below(est, kt)
+    t = 0.0 if cut is None else max(cut, 0.0)
+    s = min(1.0, max(1e-15, math.sqrt(t) / alpha))
+    return alpha, s

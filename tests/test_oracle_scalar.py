@@ -1,0 +1,157 @@
+"""Pins of the oracle's scalar layer and random stream against the paper and
+against mathematics independent of the code under test."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.dwh import dwh_weights, dwh_map, compose, iteration_count, eig_schedule, svd_schedule, U_ROUND
+from oracle.philox import philox4x32_10, gaussian
+
+LS = [1e-16, 1e-12, 1e-8, 1e-3, 0.01, 0.1, 0.2, 0.25, 0.5, 0.875, 0.99]
+
+
+def _grid(l, npts=200001):
+    return np.unique(np.concatenate([np.geomspace(l, 1.0, npts), np.linspace(l, 1.0, npts)]))
+
+
+@pytest.mark.parametrize("l", LS)
+def test_weights_equioscillate(l):
+    """Zolotarev (3,2) scaled best approximation of sign on [l, 1] (Sec. 3.1):
+    r <= 1 on [l, 1] with the maximum 1 attained at x = 1 and at an interior
+    point, and the minimum attained at x = l."""
+    a, b, c = dwh_weights(l)
+    x = _grid(l)
+    r = dwh_map(x, a, b, c)
+    assert abs(dwh_map(1.0, a, b, c) - 1.0) < 4 * U_ROUND
+    assert r.max() <= 1.0 + 8 * U_ROUND
+    i = int(np.argmax(r[:-1]))
+    # refine the interior maximum on a fine local grid
+    lo, hi = x[max(i - 1, 0)], x[min(i + 1, len(x) - 1)]
+    xf = np.linspace(lo, hi, 20001)
+    assert abs(dwh_map(xf, a, b, c).max() - 1.0) < 1e-12
+    assert lo > l and hi < 1.0
+    assert r.min() >= dwh_map(l, a, b, c) * (1 - 1e-14)
+
+
+@pytest.mark.parametrize("l", [1e-8, 1e-3, 0.1, 0.5])
+def test_weights_are_optimal(l):
+    """Among odd rational (3,2) maps rescaled to max 1 on [l,1], the DWH weights
+    maximise the new lower bound min r (the optimality that defines them)."""
+    a, b, c = dwh_weights(l)
+    x = _grid(l, 40001)
+    best = dwh_map(x, a, b, c)
+    best_lo = best.min() / best.max()
+    g = np.random.default_rng(5)
+    for _ in range(200):
+        pa, pb, pc = np.array([a, b, c]) * (1 + 1e-2 * g.standard_normal(3))
+        r = dwh_map(x, pa, pb, pc)
+        assert r.min() / r.max() <= best_lo * (1 + 1e-9)
+
+
+def test_halley_at_one(golden):
+    a, b, c = dwh_weights(1.0)
+    assert (a, b, c) == tuple(float(v) for v in golden["halley_weights_at_l_1"]["value"])
+    # clamp: a bound that rounding pushed above 1 gives the same weights
+    assert dwh_weights(1.0 + 2.2e-16) == (a, b, c)
+
+
+def test_iteration_counts(golden):
+    kmax = golden["max_iterations_for_kappa_1e15"]
+    assert iteration_count(1.0 / kmax["kappa"]) <= kmax["value"]
+    assert iteration_count(1e-16) <= kmax["value"]
+    # fewer iterations as l0 grows
+    counts = [iteration_count(l) for l in [1e-16, 1e-10, 1e-5, 1e-2, 0.2, 0.9]]
+    assert counts == sorted(counts, reverse=True)
+
+
+def _eig_image(x_prime, s, iters):
+    """r(Btil) for scaled eigenvalue x' of the matrix whose wanted part is [-1, 0]."""
+    l = s
+    ws = []
+    for _ in range(iters):
+        a, b, c = dwh_weights(l)
+        ws.append((a, b, c))
+        l = dwh_map(min(l, 1.0), a, b, c)
+    return compose((1 - s) * x_prime - s, ws)
+
+
+@pytest.mark.parametrize("key", ["eig_s_three_iterations", "eig_s_two_iterations"])
+def test_shift_choice_maps_wanted_to_minus_one(golden, key):
+    """Sec. 4.1: s = 0.2 with three and s = 0.875 with two iterations give
+    |r + 1| = O(u) on the wanted interval [-1, 0]."""
+    f = golden[key]
+    x = np.linspace(-1.0, 0.0, 100001)
+    err = np.abs(_eig_image(x, f["value"], f["iterations"]) + 1.0)
+    assert err.max() < 16 * U_ROUND
+
+
+def test_two_iterations_at_s_0_2_are_not_enough(golden):
+    x = np.linspace(-1.0, 0.0, 10001)
+    err = np.abs(_eig_image(x, golden["eig_s_three_iterations"]["value"], 2) + 1.0)
+    assert err.max() > 1e-8
+
+
+def test_positive_extent_of_band(golden):
+    """Sec. 4.1: r + 1 becomes O(1) from x ~ 0.1 (three iterations, s = 0.2) and
+    only from x ~ 5 (two iterations, s = 0.875).  'O(1)' is read as r + 1 >= 0.02
+    (the tol of 0.01 applied to (r + 1)/2); the crossing must be within a factor
+    of 3 of the printed value."""
+    f = golden["eig_positive_extent"]
+    for s, it, about in [(0.2, 3, f["three_iterations_about"]), (0.875, 2, f["two_iterations_about"])]:
+        x = np.linspace(0.0, 20.0, 400001)
+        y = _eig_image(x, s, it) + 1.0
+        cross = x[np.argmax(y >= 0.02)]
+        assert about / 3 <= cross <= about * 3, (s, it, cross)
+
+
+def test_eig_schedule_kinds():
+    # bounded positive side: every step Cholesky (Sec. 4.1 'safe in all iterations')
+    sched = eig_schedule(0.2, 1.0)
+    assert [st["kind"] for st in sched] == ["chol"] * 3
+    # huge positive side forces QR steps
+    sched = eig_schedule(0.2, 1e6)
+    assert sched[0]["kind"] == "qr"
+    assert all(st["x"] >= 1.0 for st in sched)
+
+
+def test_svd_schedule_stops_at_unit_bound():
+    for s in [1e-10, 1e-3, 0.1, 0.25, 0.9]:
+        sched = svd_schedule(s)
+        l = s
+        for st in sched:
+            l = dwh_map(min(l, 1.0), st["a"], st["b"], st["c"])
+        assert abs(l - 1.0) < 5 * U_ROUND
+        assert sched[0]["kind"] == "qr"
+        assert all(st["kind"] == "chol" for st in sched[1:] if 1 + st["c"] <= 100.0)
+
+
+def test_singular_values_stay_in_bound():
+    """Sec. 3.1: the singular values of X_k lie in [l_k, 1]."""
+    for s in [1e-6, 0.05, 0.3]:
+        x = np.geomspace(s, 1.0, 5001)
+        l = s
+        for st in svd_schedule(s):
+            x = dwh_map(x, st["a"], st["b"], st["c"])
+            l = dwh_map(min(l, 1.0), st["a"], st["b"], st["c"])
+            assert x.min() >= l * (1 - 1e-13) and x.max() <= 1 + 8 * U_ROUND
+
+
+def test_philox_known_answers():
+    """Known-answer vectors published with Philox4x32-10 (Random123)."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF,) * 2, (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+    ]
+    for ctr, key, want in cases:
+        got = philox4x32_10(np.array([ctr], np.uint64), np.array([key], np.uint64))[0]
+        assert tuple(int(v) for v in got) == want
+
+
+def test_gaussian_moments_and_streams():
+    z = gaussian(123, 0, 200000)
+    assert abs(z.mean()) < 0.01 and abs(z.std() - 1) < 0.01
+    assert not np.allclose(gaussian(123, 1, 100), gaussian(123, 0, 100))
+    assert np.array_equal(gaussian(123, 2, 101)[:100], gaussian(123, 2, 100))
