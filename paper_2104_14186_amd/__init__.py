@@ -1,0 +1,273 @@
+"""Python binding of libqdwhp.so (QDWHpartial-EIG / -SVD on MI355X).
+
+Argument marshalling only: torch supplies device memory and the current
+stream; every step of the solve runs in the HIP library.  Importing this
+package does not need a GPU; calling it does, and fails loudly when the
+library has not been built.
+"""
+import ctypes
+import math
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libqdwhp.so")
+_lib = None
+
+LARGEST, SMALLEST = 0, 1
+FP64, MIXED_FP32 = 0, 1
+KIND_AUTO, KIND_QR, KIND_CHOL = 0, 1, 2
+STATUS = {0: "OK", 1: "NONFINITE", 2: "NO_SUBSPACE", 3: "CHOL", 4: "WORKSPACE",
+          5: "HIP", 6: "NOCONV"}
+
+
+class QdwhpError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({STATUS.get(status, 'invalid argument')})")
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("s_eig", ctypes.c_double),
+                ("eig_iters", ctypes.c_int), ("kappa_max", ctypes.c_double),
+                ("svd_qr_first", ctypes.c_int), ("precision", ctypes.c_int),
+                ("polish_steps", ctypes.c_int), ("seed", ctypes.c_uint64),
+                ("lanczos_vectors", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
+                ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("s_svd", ctypes.c_double),
+                ("kinds", ctypes.c_int * 16)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("ell", ctypes.c_int64), ("ind", ctypes.c_int64),
+                ("n_above", ctypes.c_int64),
+                ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("s", ctypes.c_double),
+                ("lmax", ctypes.c_double), ("lmin", ctypes.c_double),
+                ("n_iter", ctypes.c_int), ("kinds", ctypes.c_int * 16),
+                ("weights", (ctypes.c_double * 3) * 16), ("retries", ctypes.c_int),
+                ("jacobi_sweeps", ctypes.c_int), ("ms", ctypes.c_double * 8),
+                ("flops_table1", ctypes.c_double), ("status", ctypes.c_int)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_
+             if f not in ("kinds", "weights", "ms")}
+        d["kinds"] = ["qr" if x == KIND_QR else "chol" for x in list(self.kinds)[:self.n_iter]]
+        d["weights"] = [tuple(self.weights[i]) for i in range(self.n_iter)]
+        d["ms"] = list(self.ms)
+        return d
+
+
+_P, _I64, _D, _I, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
+_SIGS = {
+    "qdwhp_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "qdwhp_strerror": (ctypes.c_char_p, [_I]),
+    "qdwhp_eig_workspace": (_SZ, [_I64, _D, ctypes.POINTER(Opts)]),
+    "qdwhp_svd_workspace": (_SZ, [_I64, _I64, _I64, ctypes.POINTER(Opts)]),
+    "qdwhp_eig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
+                       ctypes.POINTER(Opts), _P, ctypes.POINTER(Info)]),
+    "qdwhp_svd": (_I, [_P, _I64, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _SZ,
+                       ctypes.POINTER(Opts), _P, ctypes.POINTER(Info)]),
+    "qdwhp_dgemm": (_I, [_I, _I, _I64, _I64, _I64, _D, _P, _I64, _P, _I64, _D, _P, _I64, _I, _P]),
+    "qdwhp_spd_inverse_workspace": (_SZ, [_I64]),
+    "qdwhp_spd_inverse": (_I, [_P, _I64, _I64, _P, _SZ, _P]),
+    "qdwhp_geqrf_workspace": (_SZ, [_I64, _I64]),
+    "qdwhp_geqrf": (_I, [_P, _I64, _I64, _I64, _P, _P, _SZ, _P]),
+    "qdwhp_orgqr": (_I, [_P, _I64, _I64, _I64, _P, _I64, _I64, _P, _I64, _P, _SZ, _P]),
+    "qdwhp_syev_workspace": (_SZ, [_I64]),
+    "qdwhp_syev": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
+    "qdwhp_gesvj_workspace": (_SZ, [_I64]),
+    "qdwhp_gesvj": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
+}
+
+
+def lib():
+    """Load libqdwhp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() "
+                               "(hipcc for gfx950) first; there is no fallback path")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def default_opts(**kw):
+    o = Opts()
+    lib().qdwhp_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "kinds":
+            for i, x in enumerate(v):
+                o.kinds[i] = {"qr": KIND_QR, "chol": KIND_CHOL, "auto": KIND_AUTO}.get(x, x)
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _check(st, where):
+    if st != 0:
+        raise QdwhpError(st, where)
+
+
+def _colmajor(A):
+    """Column-major copy of a 2-D float64 CUDA tensor: returns (buffer, ld)
+    where buffer is a contiguous (cols, rows) tensor holding A column by column."""
+    return A.t().contiguous(), A.shape[0]
+
+
+def _workspace(torch, nbytes, device):
+    return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
+
+
+def dgemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, upper=False):
+    """C = alpha op(A) op(B) + beta C on column-major views.
+
+    A, B, C are 2-D float64 CUDA tensors given as column-major buffers, i.e.
+    contiguous tensors of shape (cols, rows) (the transpose of the logical
+    matrix).  Returns C in the same convention.
+    """
+    import torch
+    ka, ma = A.shape          # logical A is ma x ka (column-major buffer of shape (ka, ma))
+    kb, mb = B.shape
+    m, k = (ka, ma) if transa else (ma, ka)
+    kk, n = (kb, mb) if transb else (mb, kb)
+    assert k == kk
+    if C is None:
+        C = torch.zeros((n, m), dtype=torch.float64, device=A.device)
+    st = lib().qdwhp_dgemm(int(transa), int(transb), m, n, k, alpha, _ptr(A), ma, _ptr(B), mb,
+                           beta, _ptr(C), m, int(upper), _stream(torch))
+    _check(st, "qdwhp_dgemm")
+    return C
+
+
+def _info_dict(info):
+    return info.as_dict()
+
+
+def eig(A, fraction=None, k=None, which="largest", opts=None, return_info=False, stream=None):
+    """Wanted eigenpairs of the symmetric n x n float64 CUDA tensor A (QDWHpartial-EIG).
+
+    Returns (w, V) with w (k,) most wanted first and V (n, k); with
+    return_info=True also the solver report as a dict.
+    """
+    import torch
+    n = A.shape[0]
+    assert A.shape == (n, n) and A.dtype == torch.float64 and A.is_cuda
+    if fraction is None:
+        fraction = float(k) / n
+    kk = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    o = opts if opts is not None else default_opts()
+    Acm = A.t().contiguous()
+    nbytes = lib().qdwhp_eig_workspace(n, fraction, ctypes.byref(o))
+    ws = _workspace(torch, nbytes, A.device)
+    w = torch.empty(kk, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((kk, n), dtype=torch.float64, device=A.device)
+    info = Info()
+    st = lib().qdwhp_eig(_ptr(Acm), n, n, fraction, SMALLEST if which == "smallest" else LARGEST,
+                         _ptr(w), _ptr(Vb), n, _ptr(ws), nbytes, ctypes.byref(o),
+                         stream if stream is not None else _stream(torch), ctypes.byref(info))
+    _check(st, "qdwhp_eig")
+    out = (w, Vb.t())
+    return out + (info.as_dict(),) if return_info else out
+
+
+def svd(A, k, opts=None, return_info=False, stream=None):
+    """Top-k singular triplets of the m x n float64 CUDA tensor A (QDWHpartial-SVD).
+
+    Returns (U (m,k), S (k,), V (n,k)) [+ info dict]."""
+    import torch
+    m, n = A.shape
+    assert A.dtype == torch.float64 and A.is_cuda
+    o = opts if opts is not None else default_opts()
+    Acm = A.t().contiguous()
+    nbytes = lib().qdwhp_svd_workspace(m, n, k, ctypes.byref(o))
+    ws = _workspace(torch, nbytes, A.device)
+    Ub = torch.empty((k, m), dtype=torch.float64, device=A.device)
+    Vb = torch.empty((k, n), dtype=torch.float64, device=A.device)
+    S = torch.empty(k, dtype=torch.float64, device=A.device)
+    info = Info()
+    st = lib().qdwhp_svd(_ptr(Acm), m, n, m, k, _ptr(Ub), m, _ptr(S), _ptr(Vb), n, _ptr(ws), nbytes,
+                         ctypes.byref(o), stream if stream is not None else _stream(torch),
+                         ctypes.byref(info))
+    _check(st, "qdwhp_svd")
+    out = (Ub.t(), S, Vb.t())
+    return out + (info.as_dict(),) if return_info else out
+
+
+def spd_inverse(Z):
+    """Inverse of the SPD float64 CUDA matrix Z (a new tensor)."""
+    import torch
+    n = Z.shape[0]
+    Zc = Z.t().contiguous()
+    nbytes = lib().qdwhp_spd_inverse_workspace(n)
+    ws = _workspace(torch, nbytes, Z.device)
+    _check(lib().qdwhp_spd_inverse(_ptr(Zc), n, n, _ptr(ws), nbytes, _stream(torch)), "qdwhp_spd_inverse")
+    return Zc.t()
+
+
+def qr(A, c0=0, q=None):
+    """Householder QR of the m x n (m >= n) float64 CUDA tensor A.
+
+    Returns (Qcols, R, tau): Qcols = columns c0 .. c0+q-1 of Q, R the n x n
+    triangle."""
+    import torch
+    m, n = A.shape
+    q = n if q is None else q
+    Ac = A.t().contiguous()
+    tau = torch.empty(n, dtype=torch.float64, device=A.device)
+    nbytes = lib().qdwhp_geqrf_workspace(m, n)
+    ws = _workspace(torch, nbytes, A.device)
+    _check(lib().qdwhp_geqrf(_ptr(Ac), m, n, m, _ptr(tau), _ptr(ws), nbytes, _stream(torch)), "qdwhp_geqrf")
+    Qb = torch.empty((max(q, 1), m), dtype=torch.float64, device=A.device)
+    _check(lib().qdwhp_orgqr(_ptr(Ac), m, n, m, _ptr(tau), c0, q, _ptr(Qb), m, _ptr(ws), nbytes,
+                             _stream(torch)), "qdwhp_orgqr")
+    R = torch.triu(Ac.t()[:n, :])
+    return Qb.t()[:, :q], R, tau
+
+
+def syev(H):
+    """All eigenpairs of the symmetric float64 CUDA matrix H (block Jacobi):
+    (w descending, W, sweeps)."""
+    import torch
+    n = H.shape[0]
+    Hc = H.t().contiguous()
+    w = torch.empty(n, dtype=torch.float64, device=H.device)
+    Wb = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    nbytes = lib().qdwhp_syev_workspace(n)
+    ws = _workspace(torch, nbytes, H.device)
+    sw = ctypes.c_int(0)
+    _check(lib().qdwhp_syev(_ptr(Hc), n, n, _ptr(w), _ptr(Wb), n, _ptr(ws), nbytes, _stream(torch),
+                            ctypes.byref(sw)), "qdwhp_syev")
+    return w, Wb.t(), sw.value
+
+
+def gesvj(R):
+    """All singular triplets of the square float64 CUDA matrix R (one-sided
+    block Jacobi): (U, S descending, V, sweeps)."""
+    import torch
+    n = R.shape[0]
+    Rc = R.t().contiguous()
+    S = torch.empty(n, dtype=torch.float64, device=R.device)
+    Vb = torch.empty((n, n), dtype=torch.float64, device=R.device)
+    nbytes = lib().qdwhp_gesvj_workspace(n)
+    ws = _workspace(torch, nbytes, R.device)
+    sw = ctypes.c_int(0)
+    _check(lib().qdwhp_gesvj(_ptr(Rc), n, n, _ptr(S), _ptr(Vb), n, _ptr(ws), nbytes, _stream(torch),
+                             ctypes.byref(sw)), "qdwhp_gesvj")
+    return Rc.t(), S, Vb.t(), sw.value

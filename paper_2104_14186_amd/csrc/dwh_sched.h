@@ -1,0 +1,33 @@
+// Host-side scalar layer: DWH weights, step schedules, threshold placement.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+namespace qdwhp {
+
+struct DwhStep {
+  double a, b, c;    // weights of r(x) = x (a + b x^2) / (1 + c x^2)
+  double l;          // lower bound l_k before the step
+  double x;          // bound on the largest singular value before the step
+  int kind;          // 1 = QR-based (Eq. (2)), 2 = Cholesky-based (Eq. (3))
+};
+
+// Weights of the scaled Zolotarev (3,2) approximation of sign on [l, 1]
+// (Sec. 3.1; closed form as in Algorithm 3), with l clamped to <= 1.
+void dwh_weights(double l, double* a, double* b, double* c);
+double dwh_map(double x, double a, double b, double c);
+
+// Algorithm 1: `iters` steps from l_0 = s; kinds from the bound
+// 1 + c_k x_k^2 on cond(Z_k) against kappa_max.
+std::vector<DwhStep> eig_schedule(double s, double rho, int iters, double kappa_max);
+// Algorithm 2: steps from l_0 = s until |l_k - 1| < 5u; step 0 QR-based when
+// qr_first, later steps QR-based while 1 + c_k > kappa_max.
+std::vector<DwhStep> svd_schedule(double s, double kappa_max, bool qr_first);
+
+// Threshold below the pooled Lanczos quadrature node at which the estimated
+// count first reaches kt; returns false when the count never reaches kt.
+bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weights, int64_t n,
+               int nv, double lmax, double lmin, int64_t kt, double* cut);
+int64_t target_count(int64_t n, int64_t k, int boost);
+
+}  // namespace qdwhp

@@ -1,0 +1,29 @@
+// Householder QR building blocks (see qr.hip).
+#pragma once
+#include "common.h"
+
+namespace qdwhp {
+
+constexpr int QB = 128;   // panel width and T-factor block
+
+struct QrScratch {
+  double* part; double* piv; double* G; double* W1; double* W2;
+  double* ws; int64_t ws_doubles;
+};
+
+int64_t qr_scratch_doubles(int64_t m, int64_t n);
+QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n);
+inline int64_t qr_t_doubles(int64_t n) { return cdiv(n > 0 ? n : 1, QB) * QB * QB; }
+
+// In-place QR of A (m x n, m >= n): R above, reflectors below, tau[n];
+// per-panel T factors in Tall (QB x QB each, zero below the diagonal).
+void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
+           const QrScratch& sc, hipStream_t s);
+// Q (m x q) = H_1 ... H_upto E, E = columns c0 .. c0+q-1 of the identity.
+// C (m x q) <- H_1 ... H_upto C.
+void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
+             double* C, int64_t q, int64_t ldc, const QrScratch& sc, hipStream_t s);
+void orgqr(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
+           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s);
+
+}  // namespace qdwhp

@@ -1,0 +1,278 @@
+// Householder QR without pivoting (geqrf layout) and explicit Q columns.
+//
+// Used for the stacked matrix [sqrt(c) X; I] of the QR-based step (Eq. (2))
+// and for the spectral projector whose R diagonal reveals the subspace size
+// (Sec. 4.1, Theorem 1 and "Choosing the subspace size").
+//
+// Blocked right-looking factorization with panels of QB = 128 columns:
+//  * panel: one launch per column over the whole grid.  Launch j forms
+//    reflector j from column statistics reduced from the previous launch
+//    (norm of the column below the pivot, its dot products with the other
+//    panel columns, and the pivot row), applies it to this workgroup's rows,
+//    and accumulates the statistics of column j+1 -- so a column costs one
+//    pass over the panel and one launch, with no atomics (partials are
+//    summed in a fixed order, results are bitwise reproducible);
+//  * T factor of the compact WY form I - V T V^T from G = V^T V
+//    (split-K GEMM) and the forward recurrence T(0:j,j) = -tau_j T(0:j,0:j) G(0:j,j);
+//  * trailing update C <- (I - V T^T V^T) C as three GEMMs with V read in
+//    place from below the diagonal (unit-lower operand mask).
+#include "common.h"
+#include "qr.h"
+
+namespace qdwhp {
+namespace {
+
+constexpr int CH = 32;          // columns per register chunk
+constexpr int RPT_MAX = 4;      // rows per thread
+
+struct Panel {
+  double* P; int64_t ld; int64_t h; int w;
+  double* tau;
+  double* part;     // [2][256][QB] partial statistics (double-buffered by launch parity)
+  double* piv;      // [2][QB] pivot-row values
+  int nwg; int rpt;
+};
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void qr_col_kernel(Panel a, int j) {
+  __shared__ double sh_s[QB];
+  __shared__ double sh_w[QB];
+  __shared__ double sh_red[4][CH];
+  const int t = threadIdx.x, g = blockIdx.x, lane = t & 63, wv = t >> 6;
+  const int w = a.w;
+  const int64_t ld = a.ld;
+  double* P = a.P;
+  const double* part_in = a.part + (int64_t)((j + 2) & 1) * 256 * QB;
+  double* part_out = a.part + (int64_t)((j + 1) & 1) * 256 * QB;
+  const double* piv_in = a.piv + ((j + 2) & 1) * QB;
+  double* piv_out = a.piv + ((j + 1) & 1) * QB;
+
+  double tau = 0.0, scale = 0.0, beta = 0.0;
+  if (j >= 0) {
+    for (int c = t; c < w; c += 256) {
+      double s = 0.0;
+      if (c >= j)
+        for (int q = 0; q < a.nwg; ++q) s += part_in[(int64_t)q * QB + c];
+      sh_s[c] = s;
+    }
+    __syncthreads();
+    const double x0 = piv_in[j];
+    const double tail2 = sh_s[j];
+    if (tail2 == 0.0) {
+      tau = 0.0; beta = x0; scale = 0.0;
+    } else {
+      const double nrm = hypot(x0, sqrt(tail2));
+      beta = (x0 >= 0.0) ? -nrm : nrm;
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    for (int c = t; c < w; c += 256)
+      if (c > j) sh_w[c] = piv_in[c] + scale * sh_s[c];
+    if (g == 0 && t == 0) a.tau[j] = tau;
+    __syncthreads();
+  }
+
+  const int64_t rbase = (int64_t)g * 256 * a.rpt;
+  double vr[RPT_MAX], xn[RPT_MAX];
+  int64_t rr[RPT_MAX];
+#pragma unroll
+  for (int q = 0; q < RPT_MAX; ++q) {
+    rr[q] = rbase + (int64_t)q * 256 + t;
+    vr[q] = 0.0; xn[q] = 0.0;
+    if (q >= a.rpt || rr[q] >= a.h) { rr[q] = -1; continue; }
+    const int64_t r = rr[q];
+    if (j >= 0) {
+      if (r > j) {
+        vr[q] = P[r + j * ld] * scale;
+        P[r + j * ld] = vr[q];
+      } else if (r == j) {
+        P[j + j * ld] = beta;
+      }
+    }
+  }
+
+  const int jn = j + 1;      // column whose statistics this launch gathers
+  // value of column jn after reflector j, per owned row (multiplier of the statistics)
+  if (jn < w) {
+#pragma unroll
+    for (int q = 0; q < RPT_MAX; ++q) {
+      const int64_t r = rr[q];
+      if (r < 0) continue;
+      double x = P[r + (int64_t)jn * ld];
+      if (j >= 0 && r > j) x -= tau * vr[q] * sh_w[jn];
+      else if (j >= 0 && r == j) x -= tau * sh_w[jn];
+      xn[q] = x;
+    }
+  }
+  for (int cb = jn; cb < w; cb += CH) {
+    double acc[CH];
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) acc[cc] = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPT_MAX; ++q) {
+      const int64_t r = rr[q];
+      if (r < 0) continue;
+      const bool below = (j >= 0 && r > j), pivrow = (j >= 0 && r == j);
+      if (r < jn && !pivrow) continue;          // rows above the next pivot: untouched
+      const double x = xn[q];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) {
+        const int c = cb + cc;
+        if (c < w) {
+          double p = P[r + (int64_t)c * ld];
+          if (below) p -= tau * vr[q] * sh_w[c];
+          else if (pivrow) p -= tau * sh_w[c];
+          if (below || pivrow) P[r + (int64_t)c * ld] = p;
+          if (r > jn) acc[cc] += x * p;
+          if (r == jn) piv_out[c] = p;
+        }
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) {
+      const double v = wave_sum(acc[cc]);
+      if (lane == 0) sh_red[wv][cc] = v;
+    }
+    __syncthreads();
+    if (t < CH && cb + t < w)
+      part_out[(int64_t)g * QB + cb + t] = sh_red[0][t] + sh_red[1][t] + sh_red[2][t] + sh_red[3][t];
+    __syncthreads();
+  }
+}
+
+// T (w x w, upper) of the compact WY form from G = V^T V and tau.
+__global__ __launch_bounds__(256) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
+                                                      double* T, int64_t ldt, int w) {
+  __shared__ double S[QB][QB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < QB * QB; e += 256) S[e % QB][e / QB] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < w; ++j) {
+    const double tj = tau[j];
+    if (t < j) {
+      double acc = 0.0;
+      for (int k = t; k < j; ++k) acc += S[t][k] * G[k + (int64_t)j * ldg];
+      S[t][j] = -tj * acc;
+    }
+    if (t == 0) S[j][j] = tj;
+    __syncthreads();
+  }
+  for (int e = t; e < QB * QB; e += 256) {
+    const int r = e % QB, c = e / QB;
+    if (r < w && c < w) T[r + (int64_t)c * ldt] = S[r][c];
+  }
+}
+
+__global__ void eye_cols_kernel(double* Q, int64_t m, int64_t q, int64_t ldq, int64_t c0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t j = blockIdx.y; j < q; j += gridDim.y)
+    if (i < m) Q[i + j * ldq] = (i == c0 + j) ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+int64_t qr_scratch_doubles(int64_t m, int64_t n) {
+  (void)m;
+  const int64_t nn = n > 1 ? n : 1;
+  return 2 * 256 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256;
+}
+
+QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
+  (void)m;
+  const int64_t nn = n > 1 ? n : 1;
+  QrScratch s;
+  s.part = w; w += 2 * 256 * QB;
+  s.piv = w; w += 2 * QB;
+  s.G = w; w += QB * QB;
+  s.W1 = w; w += QB * nn;
+  s.W2 = w; w += QB * nn;
+  s.ws = w; s.ws_doubles = 64 * QB * QB + 8 * QB * nn;
+  return s;
+}
+
+void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
+           const QrScratch& sc, hipStream_t s) {
+  for (int64_t c0 = 0; c0 < n; c0 += QB) {
+    const int w = (int)((n - c0) < QB ? (n - c0) : QB);
+    const int64_t h = m - c0;
+    Panel p;
+    p.P = A + c0 + c0 * lda; p.ld = lda; p.h = h; p.w = w;
+    p.tau = tau + c0; p.part = sc.part; p.piv = sc.piv;
+    p.rpt = (int)cdiv(h, 256 * 256);
+    if (p.rpt > RPT_MAX) p.rpt = RPT_MAX;
+    p.nwg = (int)cdiv(h, 256 * p.rpt);
+    if (p.nwg > 256) throw HipError{hipErrorInvalidValue};
+    for (int j = -1; j < w; ++j) {
+      qr_col_kernel<<<p.nwg, 256, 0, s>>>(p, j);
+      QDWHP_LAUNCH_CHECK();
+    }
+    // G = V^T V, then T
+    Gemm g;
+    g.M = w; g.N = w; g.K = h; g.A = p.P; g.lda = lda; g.ta = true; g.a_unit_lower = true;
+    g.B = p.P; g.ldb = lda; g.b_unit_lower = true; g.C = sc.G; g.ldc = QB;
+    g.ws = sc.ws; g.ws_doubles = sc.ws_doubles;
+    dgemm(g, s);
+    double* T = Tall + (c0 / QB) * QB * QB;
+    build_t_kernel<<<1, 256, 0, s>>>(sc.G, QB, tau + c0, T, QB, w);
+    QDWHP_LAUNCH_CHECK();
+    const int64_t nc = n - c0 - w;
+    if (nc > 0) {
+      double* Cm = A + c0 + (c0 + w) * lda;
+      Gemm g1;   // W1 = V^T C
+      g1.M = w; g1.N = nc; g1.K = h; g1.A = p.P; g1.lda = lda; g1.ta = true; g1.a_unit_lower = true;
+      g1.B = Cm; g1.ldb = lda; g1.C = sc.W1; g1.ldc = QB; g1.ws = sc.ws; g1.ws_doubles = sc.ws_doubles;
+      dgemm(g1, s);
+      Gemm g2;   // W2 = T^T W1
+      g2.M = w; g2.N = nc; g2.K = w; g2.A = T; g2.lda = QB; g2.ta = true;
+      g2.B = sc.W1; g2.ldb = QB; g2.C = sc.W2; g2.ldc = QB;
+      dgemm(g2, s);
+      Gemm g3;   // C -= V W2
+      g3.M = h; g3.N = nc; g3.K = w; g3.alpha = -1.0; g3.beta = 1.0;
+      g3.A = p.P; g3.lda = lda; g3.a_unit_lower = true; g3.B = sc.W2; g3.ldb = QB;
+      g3.C = Cm; g3.ldc = lda;
+      dgemm(g3, s);
+    }
+  }
+}
+
+void orgqr(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
+           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s) {
+  if (q <= 0) return;
+  dim3 grid((unsigned)cdiv(m, 256), (unsigned)(q < 65535 ? q : 65535));
+  eye_cols_kernel<<<grid, 256, 0, s>>>(Q, m, q, ldq, c0);
+  QDWHP_LAUNCH_CHECK();
+  apply_q(A, m, lda, Tall, upto, Q, q, ldq, sc, s);
+}
+
+void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
+             double* Q, int64_t q, int64_t ldq, const QrScratch& sc, hipStream_t s) {
+  if (upto <= 0 || q <= 0) return;
+  const int64_t np = cdiv(upto, QB);
+  for (int64_t pi = np - 1; pi >= 0; --pi) {
+    const int64_t pc0 = pi * QB;
+    const int w = (int)((upto - pc0) < QB ? (upto - pc0) : QB);
+    const int64_t h = m - pc0;
+    const double* V = A + pc0 + pc0 * lda;
+    const double* T = Tall + pi * QB * QB;
+    double* Qp = Q + pc0;
+    Gemm g1;   // W1 = V^T Qp
+    g1.M = w; g1.N = q; g1.K = h; g1.A = V; g1.lda = lda; g1.ta = true; g1.a_unit_lower = true;
+    g1.B = Qp; g1.ldb = ldq; g1.C = sc.W1; g1.ldc = QB; g1.ws = sc.ws; g1.ws_doubles = sc.ws_doubles;
+    dgemm(g1, s);
+    Gemm g2;   // W2 = T W1
+    g2.M = w; g2.N = q; g2.K = w; g2.A = T; g2.lda = QB; g2.B = sc.W1; g2.ldb = QB;
+    g2.C = sc.W2; g2.ldc = QB;
+    dgemm(g2, s);
+    Gemm g3;   // Qp -= V W2
+    g3.M = h; g3.N = q; g3.K = w; g3.alpha = -1.0; g3.beta = 1.0;
+    g3.A = V; g3.lda = lda; g3.a_unit_lower = true; g3.B = sc.W2; g3.ldb = QB; g3.C = Qp; g3.ldc = ldq;
+    dgemm(g3, s);
+  }
+}
+
+}  // namespace qdwhp

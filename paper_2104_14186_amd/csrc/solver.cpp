@@ -1,0 +1,697 @@
+// QDWHpartial-EIG (Algorithm 1) and QDWHpartial-SVD (Algorithm 2) drivers and
+// the building-block entry points of the C ABI.
+//
+// Every matrix step runs in the library's HIP kernels; the host computes the
+// scalar schedule (Sec. 3.1 weights), places the threshold from the Lanczos
+// quadrature nodes, and reads back two data-dependent quantities: the
+// estimator's Ritz data (to fix tau / s and the step kinds) and diag(R) of the
+// projector QR (to fix ind and ell, Sec. 4.1 "Choosing the subspace size").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "qdwhp.h"
+#include "common.h"
+#include "dwh_sched.h"
+#include "elem.h"
+#include "jacobi.h"
+#include "lanczos.h"
+#include "qr.h"
+
+using namespace qdwhp;
+
+namespace {
+
+struct WorkspaceError {};
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures, so the size query and the solve share one carving routine.
+struct Arena {
+  char* base; size_t cap; size_t off = 0;
+  Arena(void* b, size_t c) : base((char*)b), cap(c) {}
+  double* take(int64_t count) {
+    const size_t bytes = ((size_t)(count > 0 ? count : 1) * 8 + 255) / 256 * 256;
+    if (base && off + bytes > cap) throw WorkspaceError{};
+    double* p = base ? (double*)(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct Events {
+  hipEvent_t ev[9];
+  bool on = false;
+  int used = 0;
+  explicit Events(bool enable) {
+    if (!enable) return;
+    for (auto& e : ev) QDWHP_HIP(hipEventCreate(&e));
+    on = true;
+  }
+  ~Events() {
+    if (on) for (auto& e : ev) (void)hipEventDestroy(e);
+  }
+  void mark(int i, hipStream_t s) {
+    if (on) { QDWHP_HIP(hipEventRecord(ev[i], s)); used = std::max(used, i + 1); }
+  }
+  void fill(double* ms) {
+    if (!on) return;
+    QDWHP_HIP(hipEventSynchronize(ev[used - 1]));
+    for (int i = 0; i + 1 < used && i < 7; ++i) {
+      float t = 0.f;
+      QDWHP_HIP(hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] = t;
+    }
+    float tot = 0.f;
+    QDWHP_HIP(hipEventElapsedTime(&tot, ev[0], ev[used - 1]));
+    ms[7] = tot;
+  }
+};
+
+bool is_nan(double x) { return std::isnan(x); }
+
+int64_t lz_steps(const qdwhp_opts& o, int64_t n) {
+  int64_t m = o.lanczos_steps > 0 ? o.lanczos_steps : 64;
+  if (m > 126) m = 126;
+  if (m > n - 1) m = n - 1;
+  return m < 1 ? 1 : m;
+}
+int lz_vectors(const qdwhp_opts& o) { return o.lanczos_vectors > 0 ? std::min(o.lanczos_vectors, 32) : 8; }
+
+// ---------------------------------------------------------------------------
+// DWH steps on X (m x n, ld m).  X and Xn are exchanged by the Cholesky step.
+struct StepBufs {
+  double* Z;        // n x n
+  double* spd;      // spd_inverse_doubles(n)
+  double* W;        // (m + n) x n stacked matrix
+  double* Q;        // (m + n) x n thin Q
+  double* tau;      // m + n
+  double* Tall;     // qr_t_doubles(n)
+  QrScratch qrs;
+  int* flag;
+};
+
+// Eq. (3): Z = I + c X^T X = W^T W, X+ = (b/c) X + (a - b/c) (X W^{-1}) W^{-T}.
+// W^{-1} comes from the recursive Cholesky-inversion; the two solves are
+// triangular products (W^{-1} upper: X W^{-1} only needs k <= column,
+// (.) W^{-T} only k >= column).  For symmetric X (EIG) only the upper tiles
+// of the result are formed and then mirrored.
+void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b, double c, bool sym,
+               const StepBufs& B, hipStream_t s) {
+  Gemm g;
+  g.M = n; g.N = n; g.K = m; g.alpha = c; g.beta = 0.0; g.diag = 1.0;
+  g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.Z; g.ldc = n;
+  g.tiles = TILES_UPPER;
+  dgemm(g, s);
+  chol_inverse_factor(B.Z, n, n, B.spd, B.flag, s);
+  const double* Wi = B.spd;
+  double* T = B.spd + spd_inverse_doubles(n);
+  Gemm t;
+  t.M = m; t.N = n; t.K = n; t.A = X; t.lda = m; t.B = Wi; t.ldb = n; t.C = T; t.ldc = m;
+  t.khi = KHI_COL;
+  dgemm(t, s);
+  Gemm u;
+  u.M = m; u.N = n; u.K = n; u.alpha = a - b / c; u.beta = b / c;
+  u.A = T; u.lda = m; u.B = Wi; u.ldb = n; u.tb = true; u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
+  u.klo = KLO_COL;
+  if (sym) u.tiles = TILES_UPPER;
+  dgemm(u, s);
+  if (sym) mirror_upper(Xn, n, m, s);
+  std::swap(X, Xn);
+}
+
+// Eq. (2): [sqrt(c) X; I] = [Q1; Q2] R, X+ = (b/c) X + (a - b/c)/sqrt(c) Q1 Q2^T.
+void qr_step(double* X, int64_t m, int64_t n, double a, double b, double c, bool sym,
+             const StepBufs& B, hipStream_t s) {
+  const int64_t mn = m + n;
+  stacked(X, m, B.W, mn, m, n, std::sqrt(c), s);
+  geqrf(B.W, mn, n, mn, B.tau, B.Tall, B.qrs, s);
+  orgqr(B.W, mn, mn, B.Tall, n, 0, n, B.Q, mn, B.qrs, s);
+  Gemm g;
+  g.M = m; g.N = n; g.K = n; g.alpha = (a - b / c) / std::sqrt(c); g.beta = b / c;
+  g.A = B.Q; g.lda = mn; g.B = B.Q + m; g.ldb = mn; g.tb = true; g.C = X; g.ldc = m;
+  dgemm(g, s);
+  if (sym) symmetrize(X, n, m, s);
+}
+
+// ---------------------------------------------------------------------------
+struct Plan {
+  double *X, *Xn, *Z, *big;
+  int64_t big_doubles;
+  double *tau, *Tall, *diag, *vals, *lz;
+  QrScratch qrs;
+  int* flags;       // [0] Cholesky breakdown, [1] non-finite input
+};
+
+Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd) {
+  Plan p;
+  const int64_t np = jacobi_padded(nn);
+  p.X = ar.take(mm * nn);
+  p.Xn = ar.take(mm * nn);
+  p.Z = ar.take(nn * nn);
+  int64_t big = std::max<int64_t>(spd_inverse_doubles(nn) + mm * nn, 2 * (mm + nn) * nn);
+  if (svd) big = std::max<int64_t>(big, gesvj_scratch_doubles(nn, nn) + nn * nn);
+  else big = std::max<int64_t>(big, nn * nn + syev_scratch_doubles(nn));
+  big = std::max<int64_t>(big, np * np);
+  p.big = ar.take(big);
+  p.big_doubles = big;
+  p.tau = ar.take(mm + nn);
+  p.Tall = ar.take(qr_t_doubles(mm + nn));
+  p.diag = ar.take(mm + nn);
+  p.vals = ar.take(np);
+  double* q = ar.take(qr_scratch_doubles(mm + nn, nn));
+  p.qrs = ar.base ? carve_qr_scratch(q, mm + nn, nn) : QrScratch{};
+  p.lz = ar.take(lanczos_doubles(nn, mm, nv, (int)msteps));
+  p.flags = (int*)ar.take(8);
+  return p;
+}
+
+StepBufs step_bufs(const Plan& p, int64_t m, int64_t n) {
+  StepBufs b;
+  b.Z = p.Z; b.spd = p.big; b.W = p.big; b.Q = p.big + (m + n) * n;
+  b.tau = p.tau; b.Tall = p.Tall; b.qrs = p.qrs; b.flag = p.flags;
+  return b;
+}
+
+void fill_info(qdwhp_info* info, const std::vector<DwhStep>& sched) {
+  info->n_iter = (int)sched.size();
+  for (size_t i = 0; i < sched.size() && i < 16; ++i) {
+    info->kinds[i] = sched[i].kind;
+    info->weights[i][0] = sched[i].a;
+    info->weights[i][1] = sched[i].b;
+    info->weights[i][2] = sched[i].c;
+  }
+}
+
+// first 1-based i with |R_ii| < tol, n + 1 if none
+int64_t find_ind(const std::vector<double>& d, double tol) {
+  for (size_t i = 0; i < d.size(); ++i)
+    if (std::fabs(d[i]) < tol) return (int64_t)i + 1;
+  return (int64_t)d.size() + 1;
+}
+
+bool any_nonfinite(const std::vector<double>& d) {
+  for (double v : d) if (!std::isfinite(v)) return true;
+  return false;
+}
+
+double table1_iter_flops(const std::vector<DwhStep>& sched, double m, double n) {
+  double f = 0.0;
+  for (const auto& st : sched)
+    f += (st.kind == 1) ? 6.0 * m * n * n + 8.0 / 3.0 * n * n * n : 4.0 * m * n * n + n * n * n / 3.0;
+  return f;
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_opts* opts) {
+  (void)fraction;
+  if (n < 1) return 0;
+  qdwhp_opts o;
+  if (opts) o = *opts; else qdwhp_opts_default(&o);
+  Arena ar(nullptr, 0);
+  carve(ar, n, n, lz_vectors(o), lz_steps(o, n), false);
+  return ar.off;
+}
+
+extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fraction, int which,
+                         double* w, double* V, int64_t ldv, void* work, size_t lwork,
+                         const qdwhp_opts* opts, void* stream, qdwhp_info* info) {
+  qdwhp_info dummy;
+  if (!info) info = &dummy;
+  std::memset(info, 0, sizeof(*info));
+  auto ret = [&](int st) { info->status = st; return st; };
+  if (!A) return ret(-1);
+  if (n < 1) return ret(-2);
+  if (lda < n) return ret(-3);
+  if (!(fraction > 0.0) || fraction > 1.0) return ret(-4);
+  if (which != QDWHP_LARGEST && which != QDWHP_SMALLEST) return ret(-5);
+  if (!w) return ret(-6);
+  if (!V) return ret(-7);
+  if (ldv < n) return ret(-8);
+  if (!work) return ret(-9);
+  qdwhp_opts o;
+  if (opts) o = *opts; else qdwhp_opts_default(&o);
+  if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16)
+    return ret(-11);
+  hipStream_t s = (hipStream_t)stream;
+  int64_t k = (int64_t)std::floor(fraction * (double)n + 0.5);
+  k = std::min<int64_t>(n, std::max<int64_t>(1, k));
+  info->k = k;
+  const int nv = lz_vectors(o);
+  const int64_t msteps = lz_steps(o, n);
+  const double sgn = (which == QDWHP_SMALLEST) ? -1.0 : 1.0;
+  try {
+    Arena ar(work, lwork);
+    Plan P = carve(ar, n, n, nv, msteps, false);
+    Events ev(true);
+    ev.mark(0, s);
+    QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
+    nonfinite(A, lda, n, n, P.flags + 1, s);
+    // ---- estimator (Algorithm 1 opens with a few Lanczos steps)
+    const bool replay = !is_nan(o.tau) && !is_nan(o.mu) && !is_nan(o.rho);
+    LanczosResult lz;
+    double lmax = 0.0, lmin = 0.0;
+    if (!replay) {
+      LanczosOp op;
+      op.rows_tmp = 1;
+      op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
+        Gemm g;
+        g.M = n; g.N = nv; g.K = n; g.alpha = sgn; g.A = A; g.lda = lda; g.B = in; g.ldb = ldi;
+        g.C = out; g.ldc = ldo;
+        dgemm(g, st);
+      };
+      lz = lanczos(op, n, nv, (int)msteps, o.seed, P.lz, s);
+      lmax = -std::numeric_limits<double>::infinity();
+      lmin = std::numeric_limits<double>::infinity();
+      for (size_t i = 0; i < lz.nodes.size(); ++i) {
+        lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
+        lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
+      }
+    }
+    info->lmax = lmax; info->lmin = lmin;
+    ev.mark(1, s);
+    const double sfix = o.s_eig;
+    std::vector<DwhStep> sched;
+    std::vector<double> theta;
+    int64_t ell = 0, ind = 0, n_above = 0;
+    double tau = 0.0, mu = 1.0, rho = 0.0;
+    double* Q2 = nullptr;
+    double* Wv = nullptr;
+    int status = QDWHP_OK;
+    for (int boost = 1; boost <= 2; ++boost) {
+      if (replay) {
+        tau = o.tau; mu = o.mu; rho = o.rho;
+      } else {
+        const double spread = std::max({lmax - lmin, std::fabs(lmax), std::fabs(lmin), 1e-300});
+        if (!is_nan(o.tau)) {
+          tau = sgn * o.tau;
+        } else {
+          double cut;
+          tau = cut_below(lz.nodes, lz.weights, n, nv, lmax, lmin, target_count(n, k, boost), &cut)
+                    ? cut : lmin;
+        }
+        mu = std::max(lmax - tau, 1e-3 * spread);
+        rho = std::max(0.0, (tau - lmin) / mu);
+      }
+      sched = eig_schedule(sfix, rho, o.eig_iters, o.kappa_max);
+      for (size_t i = 0; i < sched.size() && i < 16; ++i)
+        if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) sched[i].kind = o.kinds[i];
+      info->retries = boost - 1;
+      // ---- iterations on the scaled, shifted matrix (Sec. 4.1)
+      double* X = P.X;
+      double* Xn = P.Xn;
+      eig_x0(A, lda, X, n, n, (1.0 - sfix) / mu, tau, sgn, sfix, s);
+      const StepBufs sb = step_bufs(P, n, n);
+      for (const auto& st : sched) {
+        if (st.kind == 1) qr_step(X, n, n, st.a, st.b, st.c, true, sb, s);
+        else chol_step(X, Xn, n, n, st.a, st.b, st.c, true, sb, s);
+      }
+      ev.mark(2, s);
+      // ---- projector (X + I)/2, QR, ind (Algorithm 1)
+      half_plus_identity(X, n, P.Z, n, n, s);
+      geqrf(P.Z, n, n, n, P.tau, P.Tall, P.qrs, s);
+      diagonal(P.Z, n, n, P.diag, s);
+      std::vector<double> d(n);
+      int hflags[8];
+      QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipStreamSynchronize(s));
+      ev.mark(3, s);
+      if (hflags[1]) return ret(QDWHP_ERR_NONFINITE);
+      if (hflags[0]) return ret(QDWHP_ERR_CHOL);
+      if (any_nonfinite(d)) return ret(QDWHP_ERR_NONFINITE);
+      ind = find_ind(d, o.tol);
+      ell = n - ind + 1;
+      if (ell <= 0) { status = QDWHP_ERR_NO_SUBSPACE; if (replay) break; continue; }
+      // ---- Q2 = H_1 ... H_{ind-1} [0; I_ell]
+      Q2 = (X == P.X) ? P.Xn : P.X;
+      double* Y = X;
+      orgqr(P.Z, n, n, P.Tall, ind - 1, ind - 1, ell, Q2, n, P.qrs, s);
+      ev.mark(4, s);
+      // ---- Rayleigh-Ritz on the original matrix: H = Q2^T (sgn A) Q2
+      Gemm g1;
+      g1.M = n; g1.N = ell; g1.K = n; g1.alpha = sgn; g1.A = A; g1.lda = lda; g1.B = Q2; g1.ldb = n;
+      g1.C = Y; g1.ldc = n;
+      dgemm(g1, s);
+      double* H = P.big;
+      Gemm g2;
+      g2.M = ell; g2.N = ell; g2.K = n; g2.A = Q2; g2.lda = n; g2.ta = true; g2.B = Y; g2.ldb = n;
+      g2.C = H; g2.ldc = ell;
+      dgemm(g2, s);
+      symmetrize(H, ell, ell, s);
+      ev.mark(5, s);
+      Wv = P.Z;
+      const int sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
+      info->jacobi_sweeps = sweeps;
+      if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);
+      theta.resize(ell);
+      QDWHP_HIP(hipMemcpyAsync(theta.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipStreamSynchronize(s));
+      ev.mark(6, s);
+      n_above = 0;
+      for (double t : theta) n_above += (t >= tau);
+      status = QDWHP_OK;
+      if (n_above >= k || ell >= n || replay) break;
+      status = QDWHP_ERR_NO_SUBSPACE;
+    }
+    info->tau = sgn * tau; info->mu = mu; info->rho = rho;
+    info->ell = ell; info->ind = ind; info->n_above = n_above;
+    fill_info(info, sched);
+    if (status != QDWHP_OK) return ret(status);
+    if (ell < k) return ret(QDWHP_ERR_NO_SUBSPACE);
+    // ---- V = Q2 W(:, 1:k), w = sgn theta(1:k)
+    Gemm g3;
+    g3.M = n; g3.N = k; g3.K = ell; g3.A = Q2; g3.lda = n; g3.B = Wv; g3.ldb = ell; g3.C = V; g3.ldc = ldv;
+    dgemm(g3, s);
+    scale_vec(P.vals, w, k, sgn, s);
+    sign_normalize(V, ldv, n, k, nullptr, 0, 0, s);
+    ev.mark(7, s);
+    ev.fill(info->ms);
+    const double dn = (double)n, dl = (double)ell, dk = (double)k;
+    info->flops_table1 = table1_iter_flops(sched, dn, dn) + 4.0 / 3.0 * dn * dn * dn +
+                         2.0 * dn * dn * dl + 2.0 * dn * dl * dl + 9.0 * dl * dl * dl + 2.0 * dn * dl * dk;
+  } catch (const WorkspaceError&) {
+    return ret(QDWHP_ERR_WORKSPACE);
+  } catch (const HipError&) {
+    return ret(QDWHP_ERR_HIP);
+  }
+  return ret(QDWHP_OK);
+}
+
+// ===========================================================================
+extern "C" size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdwhp_opts* opts) {
+  (void)k;
+  if (m < 1 || n < 1) return 0;
+  qdwhp_opts o;
+  if (opts) o = *opts; else qdwhp_opts_default(&o);
+  const int64_t mm = std::max(m, n), nn = std::min(m, n);
+  Arena ar(nullptr, 0);
+  carve(ar, mm, nn, lz_vectors(o), lz_steps(o, nn), true);
+  return ar.off;
+}
+
+extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                         double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                         void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
+                         qdwhp_info* info) {
+  qdwhp_info dummy;
+  if (!info) info = &dummy;
+  std::memset(info, 0, sizeof(*info));
+  auto ret = [&](int st) { info->status = st; return st; };
+  if (!A) return ret(-1);
+  if (m < 1) return ret(-2);
+  if (n < 1) return ret(-3);
+  if (lda < m) return ret(-4);
+  if (k < 1 || k > std::min(m, n)) return ret(-5);
+  if (!U) return ret(-6);
+  if (ldu < m) return ret(-7);
+  if (!S) return ret(-8);
+  if (!V) return ret(-9);
+  if (ldv < n) return ret(-10);
+  if (!work) return ret(-11);
+  qdwhp_opts o;
+  if (opts) o = *opts; else qdwhp_opts_default(&o);
+  if (!(o.tol > 0.0)) return ret(-13);
+  hipStream_t s = (hipStream_t)stream;
+  const bool tr = m < n;                       // process M = A^T when A is wide
+  const int64_t mm = std::max(m, n), nn = std::min(m, n);
+  info->k = k;
+  const int nv = lz_vectors(o);
+  const int64_t msteps = lz_steps(o, nn);
+  try {
+    Arena ar(work, lwork);
+    Plan P = carve(ar, mm, nn, nv, msteps, true);
+    Events ev(true);
+    ev.mark(0, s);
+    QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
+    nonfinite(A, lda, m, n, P.flags + 1, s);
+    const bool replay = !is_nan(o.alpha) && !is_nan(o.s_svd);
+    LanczosResult lz;
+    double lmax = 0.0, lmin = 0.0;
+    if (!replay || is_nan(o.alpha)) {
+      // operator M^T M on nn-vectors; M = A (tall) or A^T (wide)
+      LanczosOp op;
+      op.rows_tmp = mm;
+      op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double* tmp, hipStream_t st) {
+        Gemm g;   // tmp = M in   (mm x nv)
+        g.M = mm; g.N = nv; g.K = nn; g.A = A; g.lda = lda; g.ta = tr; g.B = in; g.ldb = ldi;
+        g.C = tmp; g.ldc = mm;
+        dgemm(g, st);
+        Gemm h;   // out = M^T tmp (nn x nv)
+        h.M = nn; h.N = nv; h.K = mm; h.A = A; h.lda = lda; h.ta = !tr; h.B = tmp; h.ldb = mm;
+        h.C = out; h.ldc = ldo;
+        dgemm(h, st);
+      };
+      lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
+      lmax = -std::numeric_limits<double>::infinity();
+      lmin = std::numeric_limits<double>::infinity();
+      for (size_t i = 0; i < lz.nodes.size(); ++i) {
+        lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
+        lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
+      }
+    }
+    info->lmax = lmax; info->lmin = lmin;
+    ev.mark(1, s);
+    std::vector<DwhStep> sched;
+    std::vector<double> sig;
+    int64_t ell = 0, ind = 0, n_above = 0;
+    double alpha = 1.0, sthr = 0.5;
+    double *Q2 = nullptr, *Y = nullptr, *Vt = nullptr, *Ut = nullptr;
+    int status = QDWHP_OK;
+    for (int boost = 1; boost <= 2; ++boost) {
+      if (replay) {
+        alpha = o.alpha; sthr = o.s_svd;
+      } else {
+        alpha = std::sqrt(std::max(lmax, 0.0));
+        if (!(alpha > 0.0)) alpha = 1e-300;
+        if (!is_nan(o.alpha)) alpha = o.alpha;
+        if (!is_nan(o.s_svd)) {
+          sthr = o.s_svd;
+        } else {
+          double cut;
+          const double t = cut_below(lz.nodes, lz.weights, nn, nv, lmax, lmin,
+                                     target_count(nn, k, boost), &cut) ? std::max(cut, 0.0) : 0.0;
+          sthr = std::min(1.0, std::max(1e-15, std::sqrt(t) / alpha));
+        }
+      }
+      sched = svd_schedule(sthr, o.kappa_max, o.svd_qr_first != 0);
+      for (size_t i = 0; i < sched.size() && i < 16; ++i)
+        if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) sched[i].kind = o.kinds[i];
+      info->retries = boost - 1;
+      double* X = P.X;
+      double* Xn = P.Xn;
+      scale_copy(A, lda, X, mm, mm, nn, 1.0 / alpha, tr, s);
+      const StepBufs sb = step_bufs(P, mm, nn);
+      for (const auto& st : sched) {
+        if (st.kind == 1) qr_step(X, mm, nn, st.a, st.b, st.c, false, sb, s);
+        else chol_step(X, Xn, mm, nn, st.a, st.b, st.c, false, sb, s);
+      }
+      ev.mark(2, s);
+      // ---- projector I - X^T X, QR, ind (Algorithm 2)
+      Gemm gb;
+      gb.M = nn; gb.N = nn; gb.K = mm; gb.alpha = -1.0; gb.diag = 1.0; gb.A = X; gb.lda = mm; gb.ta = true;
+      gb.B = X; gb.ldb = mm; gb.C = P.Z; gb.ldc = nn; gb.tiles = TILES_UPPER;
+      dgemm(gb, s);
+      mirror_upper(P.Z, nn, nn, s);
+      geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s);
+      diagonal(P.Z, nn, nn, P.diag, s);
+      std::vector<double> d(nn);
+      int hflags[8];
+      QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipStreamSynchronize(s));
+      ev.mark(3, s);
+      if (hflags[1]) return ret(QDWHP_ERR_NONFINITE);
+      if (hflags[0]) return ret(QDWHP_ERR_CHOL);
+      if (any_nonfinite(d)) return ret(QDWHP_ERR_NONFINITE);
+      ind = find_ind(d, o.tol);
+      ell = nn - ind + 1;
+      if (ell <= 0) { status = QDWHP_ERR_NO_SUBSPACE; if (replay) break; continue; }
+      Q2 = (X == P.X) ? P.Xn : P.X;
+      Y = X;
+      orgqr(P.Z, nn, nn, P.Tall, ind - 1, ind - 1, ell, Q2, nn, P.qrs, s);
+      ev.mark(4, s);
+      // ---- Y = M Q2 = Q_Y R_Y, SVD of R_Y (Algorithm 2 projection step)
+      Gemm gy;
+      gy.M = mm; gy.N = ell; gy.K = nn; gy.A = A; gy.lda = lda; gy.ta = tr; gy.B = Q2; gy.ldb = nn;
+      gy.C = Y; gy.ldc = mm;
+      dgemm(gy, s);
+      geqrf(Y, mm, ell, mm, P.tau, P.Tall, P.qrs, s);
+      Ut = P.Z;
+      upper_copy(Y, mm, Ut, ell, ell, s);
+      ev.mark(5, s);
+      Vt = P.big + gesvj_scratch_doubles(ell, ell);
+      const int sweeps = gesvj(Ut, ell, ell, ell, P.vals, Vt, ell, P.big, s);
+      info->jacobi_sweeps = sweeps;
+      if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);
+      sig.resize(ell);
+      QDWHP_HIP(hipMemcpyAsync(sig.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipStreamSynchronize(s));
+      ev.mark(6, s);
+      n_above = 0;
+      for (double v : sig) n_above += (v >= sthr * alpha);
+      status = QDWHP_OK;
+      if (n_above >= k || ell >= nn || replay) break;
+      status = QDWHP_ERR_NO_SUBSPACE;
+    }
+    info->alpha = alpha; info->s = sthr;
+    info->ell = ell; info->ind = ind; info->n_above = n_above;
+    fill_info(info, sched);
+    if (status != QDWHP_OK) return ret(status);
+    if (ell < k) return ret(QDWHP_ERR_NO_SUBSPACE);
+    // ---- U_M = Q_Y [U~_k; 0], V_M = Q2 V~_k; A = M or M^T
+    double* Um = tr ? V : U;
+    const int64_t ldum = tr ? ldv : ldu;
+    double* Vm = tr ? U : V;
+    const int64_t ldvm = tr ? ldu : ldv;
+    fill(Um, mm, k, ldum, 0.0, 0.0, s);
+    copy(Ut, ell, Um, ldum, ell, k, s);
+    apply_q(Y, mm, mm, P.Tall, ell, Um, k, ldum, P.qrs, s);
+    Gemm gv;
+    gv.M = nn; gv.N = k; gv.K = ell; gv.A = Q2; gv.lda = nn; gv.B = Vt; gv.ldb = ell; gv.C = Vm; gv.ldc = ldvm;
+    dgemm(gv, s);
+    scale_vec(P.vals, S, k, 1.0, s);
+    sign_normalize(V, ldv, n, k, U, ldu, m, s);
+    ev.mark(7, s);
+    ev.fill(info->ms);
+    const double dm = (double)mm, dn = (double)nn, dl = (double)ell, dk = (double)k;
+    info->flops_table1 = table1_iter_flops(sched, dm, dn) + dm * dn * dn + 4.0 / 3.0 * dn * dn * dn +
+                         2.0 * dm * dn * dl + 2.0 * dm * dl * dl + 17.0 * dl * dl * dl +
+                         2.0 * dm * dl * dk + 2.0 * dn * dl * dk;
+  } catch (const WorkspaceError&) {
+    return ret(QDWHP_ERR_WORKSPACE);
+  } catch (const HipError&) {
+    return ret(QDWHP_ERR_HIP);
+  }
+  return ret(QDWHP_OK);
+}
+
+// ===========================================================================
+// Building blocks.
+
+extern "C" size_t qdwhp_spd_inverse_workspace(int64_t n) {
+  return n < 1 ? 0 : (size_t)(spd_inverse_doubles(n) + 64) * 8;
+}
+
+extern "C" int qdwhp_spd_inverse(double* Z, int64_t n, int64_t ldz, void* work, size_t lwork, void* stream) {
+  if (!Z) return -1;
+  if (n < 1) return -2;
+  if (ldz < n) return -3;
+  if (!work) return -4;
+  if (lwork < qdwhp_spd_inverse_workspace(n)) return QDWHP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    double* ws = (double*)work;
+    int* flag = (int*)(ws + spd_inverse_doubles(n));
+    QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    spd_inverse(Z, n, ldz, ws, flag, s);
+    int h = 0;
+    QDWHP_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipStreamSynchronize(s));
+    if (h) return QDWHP_ERR_CHOL;
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}
+
+extern "C" size_t qdwhp_geqrf_workspace(int64_t m, int64_t n) {
+  if (m < 1 || n < 1) return 0;
+  return (size_t)(qr_t_doubles(n) + qr_scratch_doubles(m, n) + 64) * 8 + 512;
+}
+
+extern "C" int qdwhp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, void* work,
+                           size_t lwork, void* stream) {
+  if (!A) return -1;
+  if (m < 1) return -2;
+  if (n < 1 || n > m) return -3;
+  if (lda < m) return -4;
+  if (!tau) return -5;
+  if (!work) return -6;
+  if (lwork < qdwhp_geqrf_workspace(m, n)) return QDWHP_ERR_WORKSPACE;
+  try {
+    double* Tall = (double*)work;
+    QrScratch sc = carve_qr_scratch(Tall + qr_t_doubles(n), m, n);
+    fill(Tall, QB, cdiv(n, QB) * QB, QB, 0.0, 0.0, (hipStream_t)stream);
+    geqrf(A, m, n, lda, tau, Tall, sc, (hipStream_t)stream);
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}
+
+extern "C" int qdwhp_orgqr(const double* A, int64_t m, int64_t n, int64_t lda, const double* tau,
+                           int64_t c0, int64_t q, double* Q, int64_t ldq, void* work, size_t lwork,
+                           void* stream) {
+  (void)tau;
+  if (!A) return -1;
+  if (m < 1) return -2;
+  if (n < 1 || n > m) return -3;
+  if (lda < m) return -4;
+  if (c0 < 0 || c0 > m) return -6;
+  if (q < 0 || c0 + q > m) return -7;
+  if (!Q) return -8;
+  if (ldq < m) return -9;
+  if (!work) return -10;
+  if (lwork < qdwhp_geqrf_workspace(m, n)) return QDWHP_ERR_WORKSPACE;
+  try {
+    double* Tall = (double*)work;
+    QrScratch sc = carve_qr_scratch(Tall + qr_t_doubles(n), m, n);
+    orgqr(A, m, lda, Tall, n, c0, q, Q, ldq, sc, (hipStream_t)stream);
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}
+
+extern "C" size_t qdwhp_syev_workspace(int64_t n) {
+  return n < 1 ? 0 : (size_t)(syev_scratch_doubles(n) + 64) * 8;
+}
+
+extern "C" int qdwhp_syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw,
+                          void* work, size_t lwork, void* stream, int* sweeps) {
+  if (!H) return -1;
+  if (n < 1) return -2;
+  if (ldh < n) return -3;
+  if (!w) return -4;
+  if (!W) return -5;
+  if (ldw < n) return -6;
+  if (!work) return -7;
+  if (lwork < qdwhp_syev_workspace(n)) return QDWHP_ERR_WORKSPACE;
+  try {
+    const int sw = syev(H, n, ldh, w, W, ldw, (double*)work, (hipStream_t)stream);
+    if (sweeps) *sweeps = sw;
+    if (sw < 0) return QDWHP_ERR_NOCONV;
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}
+
+extern "C" size_t qdwhp_gesvj_workspace(int64_t n) {
+  return n < 1 ? 0 : (size_t)(gesvj_scratch_doubles(n, n) + 64) * 8;
+}
+
+extern "C" int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double* V, int64_t ldv,
+                           void* work, size_t lwork, void* stream, int* sweeps) {
+  if (!R) return -1;
+  if (n < 1) return -2;
+  if (ldr < n) return -3;
+  if (!S) return -4;
+  if (!V) return -5;
+  if (ldv < n) return -6;
+  if (!work) return -7;
+  if (lwork < qdwhp_gesvj_workspace(n)) return QDWHP_ERR_WORKSPACE;
+  try {
+    const int sw = gesvj(R, n, n, ldr, S, V, ldv, (double*)work, (hipStream_t)stream);
+    QDWHP_HIP(hipStreamSynchronize((hipStream_t)stream));
+    if (sweeps) *sweeps = sw;
+    if (sw < 0) return QDWHP_ERR_NOCONV;
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}

@@ -1,0 +1,135 @@
+"""Kernel-level parity of the HIP building blocks against FP64 host references.
+
+Each case prints its shape before the GPU call so a failing case is named."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _cm(torch, X):
+    """Column-major device buffer of host matrix X (shape (cols, rows))."""
+    return torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+
+
+def _host(T):
+    return T.cpu().numpy().T
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb", [
+    (128, 128, 16, 0, 0), (300, 257, 129, 0, 0), (257, 300, 77, 1, 0),
+    (190, 64, 300, 0, 1), (1, 1, 1, 1, 1), (513, 511, 1000, 1, 1), (5, 700, 3, 0, 0)])
+def test_dgemm_parity(m, n, k, ta, tb):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(m * 7 + n + k)
+    A = g.standard_normal((k, m) if ta else (m, k))
+    B = g.standard_normal((n, k) if tb else (k, n))
+    C = g.standard_normal((m, n))
+    print(f"dgemm m={m} n={n} k={k} ta={ta} tb={tb}", flush=True)
+    Cd = _cm(torch, C)
+    q.dgemm(_cm(torch, A), _cm(torch, B), Cd, alpha=0.75, beta=-0.5, transa=ta, transb=tb)
+    torch.cuda.synchronize()
+    ref = 0.75 * ((A.T if ta else A) @ (B.T if tb else B)) - 0.5 * C
+    err = np.abs(_host(Cd) - ref).max() / (np.abs(ref).max() + 1e-300)
+    assert err < 1e-14 * max(1, np.sqrt(k)), err
+
+
+def test_dgemm_upper_tiles_only():
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(3)
+    n, k = 400, 150
+    X = g.standard_normal((k, n))
+    print("dgemm upper n=400", flush=True)
+    C = np.full((n, n), 7.0)
+    Cd = _cm(torch, C)
+    q.dgemm(_cm(torch, X), _cm(torch, X), Cd, transa=True, upper=True)
+    torch.cuda.synchronize()
+    got = _host(Cd)
+    ref = X.T @ X
+    iu = np.triu_indices(n)
+    assert np.abs(got[iu] - ref[iu]).max() < 1e-12
+    # a strictly-lower tile far from the diagonal is untouched
+    assert np.all(got[300:, :100] == 7.0)
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 200, 517])
+def test_spd_inverse(n):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(n)
+    X = g.standard_normal((n + 5, n))
+    Z = np.eye(n) + 3.0 * X.T @ X / n
+    print(f"spd_inverse n={n}", flush=True)
+    Zi = q.spd_inverse(torch.from_numpy(Z).cuda()).cpu().numpy()
+    ref = np.linalg.inv(Z)
+    assert np.abs(Zi - ref).max() / np.abs(ref).max() < 1e-13 * np.linalg.cond(Z)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (40, 40), (300, 129), (513, 256), (1024, 512), (700, 700)])
+def test_qr(m, n):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(m + n)
+    A = g.standard_normal((m, n))
+    print(f"qr m={m} n={n}", flush=True)
+    Q, R, tau = q.qr(torch.from_numpy(A).cuda())
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    assert np.abs(Q @ R - A).max() < 2e-15 * np.abs(A).max() * np.sqrt(m)
+    assert np.abs(Q.T @ Q - np.eye(n)).max() < 2e-15 * np.sqrt(m)
+    Rl = np.linalg.qr(A, mode="r")
+    assert np.abs(np.abs(np.diag(R)) - np.abs(np.diag(Rl))).max() < 1e-12 * np.abs(Rl).max()
+
+
+def test_qr_trailing_columns():
+    """Columns c0.. of Q of a square matrix (the Q2 of the projector)."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(11)
+    n, c0 = 300, 170
+    A = g.standard_normal((n, n))
+    print("qr trailing columns", flush=True)
+    Qc, R, _ = q.qr(torch.from_numpy(A).cuda(), c0=c0, q=n - c0)
+    Qf, _ = np.linalg.qr(A)
+    P1 = Qc.cpu().numpy() @ Qc.cpu().numpy().T
+    P2 = Qf[:, c0:] @ Qf[:, c0:].T
+    assert np.abs(P1 - P2).max() < 1e-12
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 100, 257])
+def test_syev(n):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(n + 3)
+    G = g.standard_normal((n, n))
+    H = 0.5 * (G + G.T)
+    print(f"syev n={n}", flush=True)
+    w, W, sw = q.syev(torch.from_numpy(H).cuda())
+    w, W = w.cpu().numpy(), W.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(H))[::-1]
+    sc = np.abs(ref).max()
+    assert np.abs(w - ref).max() < 5e-15 * sc * max(1, np.sqrt(n))
+    assert np.abs(H @ W - W * w[None, :]).max() < 5e-15 * sc * max(1, np.sqrt(n))
+    assert np.abs(W.T @ W - np.eye(n)).max() < 5e-15 * max(1, np.sqrt(n))
+
+
+@pytest.mark.parametrize("n", [1, 2, 32, 45, 200])
+def test_gesvj(n):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(n + 5)
+    R = np.triu(g.standard_normal((n, n)))
+    print(f"gesvj n={n}", flush=True)
+    U, S, V, sw = q.gesvj(torch.from_numpy(R).cuda())
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    ref = np.linalg.svd(R, compute_uv=False)
+    assert np.abs(S - ref).max() < 5e-15 * ref.max() * max(1, np.sqrt(n))
+    assert np.abs(R @ V - U * S[None, :]).max() < 5e-15 * ref.max() * max(1, np.sqrt(n))
+    assert np.abs(V.T @ V - np.eye(n)).max() < 5e-15 * max(1, np.sqrt(n))

@@ -1,0 +1,84 @@
+"""End-to-end parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Each case prints its name before the GPU call."""
+import numpy as np
+import pytest
+
+import oracle
+from synthetic import eig_uniform, eig_clustered, svd_geometric, svd_loguniform
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2104_14186_amd as q
+    return torch, q
+
+
+def _subspace_err(V1, V2):
+    return np.linalg.norm(V1 @ (V1.T @ V2) - V2, 2)
+
+
+@pytest.mark.parametrize("n,f,seed,which", [(512, 0.1, 1000, "largest"), (333, 0.2, 7, "largest"),
+                                            (300, 0.05, 8, "smallest"), (130, 0.3, 9, "largest")])
+def test_eig_vs_oracle(n, f, seed, which):
+    torch, q = _gpu()
+    A, lam = eig_uniform(n, seed)
+    print(f"eig n={n} f={f} which={which}", flush=True)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, which=which, return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    r = oracle.eig_partial(A, fraction=f, which=which)
+    k = r["k"]
+    assert info["k"] == k
+    # values: oracle and planted
+    exact = (np.sort(lam)[::-1] if which == "largest" else np.sort(lam))[:k]
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+    assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["residual"] < 1e-13, met
+    assert met["orth"] < 1e-12, met
+    # vectors: same sign convention, compare column by column (gaps are not tiny)
+    assert np.max(np.abs(V - r["V"])) < 1e-9
+    # estimator agreement (both sides draw the same Philox vectors)
+    assert abs(info["tau"] - r["tau"] * (1 if which == "largest" else -1)) < 1e-8
+    assert info["kinds"] == [s["kind"] for s in r["sched"]]
+    assert abs(info["ell"] - r["ell"]) <= 2
+
+
+def test_eig_replay_intermediates():
+    """Same tau / mu / rho / kinds on both sides: ell and Ritz values agree."""
+    torch, q = _gpu()
+    A, lam = eig_clustered(600, 44)
+    r = oracle.eig_partial(A, fraction=0.1)
+    o = q.default_opts(tau=r["tau"], mu=r["mu"], rho=r["rho"], kinds=[s["kind"] for s in r["sched"]])
+    print("eig replay n=600", flush=True)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=0.1, opts=o, return_info=True)
+    assert info["ell"] == r["ell"] and info["ind"] == r["ind"]
+    assert np.max(np.abs(w.cpu().numpy() - r["w"]) / np.abs(r["w"])) < 1e-12
+    # clustered top eigenvalues: compare the spanned subspace
+    assert _subspace_err(V.cpu().numpy(), r["V"]) < 1e-10
+
+
+@pytest.mark.parametrize("m,n,k,kind", [(512, 512, 26, "geo"), (400, 250, 25, "log"),
+                                        (250, 400, 25, "log"), (300, 300, 15, "geo")])
+def test_svd_vs_oracle(m, n, k, kind):
+    torch, q = _gpu()
+    if kind == "geo":
+        A, sig = svd_geometric(m, n, 1001)
+    else:
+        A, sig = svd_loguniform(max(m, n), min(m, n), 1003)
+        if m < n:
+            A = A.T.copy()
+    print(f"svd m={m} n={n} k={k}", flush=True)
+    U, S, V, info = q.svd(torch.from_numpy(A).cuda(), k, return_info=True)
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    r = oracle.svd_partial(A, k)
+    assert np.max(np.abs(S - r["S"]) / r["S"]) < 1e-12
+    assert np.max(np.abs(S - sig[:k]) / sig[:k]) < 1e-12
+    met = oracle.svd_metrics(A, U, S, V, sig[:k])
+    assert met["residual"] < 1e-13, met
+    assert max(met["orth_u"], met["orth_v"]) < 1e-12, met
+    assert np.max(np.abs(V - r["V"])) < 1e-8 and np.max(np.abs(U - r["U"])) < 1e-8
+    assert info["kinds"] == [s["kind"] for s in r["sched"]]
