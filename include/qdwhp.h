@@ -206,6 +206,19 @@ size_t qdwhp_gesvj_workspace(int64_t n);
 int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double* V, int64_t ldv,
                 void* work, size_t lwork, void* stream, int* sweeps);
 
+/*
+ * Kernel-level measurement: between qdwhp_profile_begin and
+ * qdwhp_profile_end every launch of the FP64 MFMA GEMM kernel (the dense
+ * products of Eqs. (2)-(3), Theorem 1's projector and the Rayleigh-Ritz step)
+ * is bracketed by hipEvents on its own stream.  end synchronises those events
+ * and returns the summed algorithmic flops (only the products the operation
+ * needs: symmetric outputs count one triangle, triangular factors their
+ * nonzero part), the summed kernel time in ms and the launch count.
+ * Process-wide; not for concurrent use from several threads.
+ */
+void qdwhp_profile_begin(void);
+int qdwhp_profile_end(double* flops, double* ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

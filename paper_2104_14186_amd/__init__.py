@@ -77,6 +77,8 @@ _SIGS = {
     "qdwhp_syev": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
     "qdwhp_gesvj_workspace": (_SZ, [_I64]),
     "qdwhp_gesvj": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
+    "qdwhp_profile_begin": (None, []),
+    "qdwhp_profile_end": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
 
 
@@ -271,3 +273,14 @@ def gesvj(R):
     _check(lib().qdwhp_gesvj(_ptr(Rc), n, n, _ptr(S), _ptr(Vb), n, _ptr(ws), nbytes, _stream(torch),
                              ctypes.byref(sw)), "qdwhp_gesvj")
     return Rc.t(), S, Vb.t(), sw.value
+
+
+def profile_begin():
+    lib().qdwhp_profile_begin()
+
+
+def profile_end():
+    """(algorithmic GEMM flops, summed GEMM kernel ms, launches) since profile_begin."""
+    f, t, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int64(0)
+    _check(lib().qdwhp_profile_end(ctypes.byref(f), ctypes.byref(t), ctypes.byref(n)), "qdwhp_profile_end")
+    return f.value, t.value, n.value

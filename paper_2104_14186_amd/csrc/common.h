@@ -58,6 +58,14 @@ struct Gemm {
   int splitk = 1;        // set by dgemm(); callers leave it at 1
 };
 void dgemm(const Gemm& g, hipStream_t s);
+// Algorithmic flops of one GEMM call: 2 x (number of products the operation
+// needs), honouring the upper-output and triangular K-range structure.
+double gemm_flops(const Gemm& g);
+
+// Live kernel timing (prof.cpp).
+bool prof_active();
+void prof_begin_launch(hipStream_t s, void** tok);
+void prof_end_launch(hipStream_t s, void* tok, double flops);
 
 // ------------------------------------------------------- small kernels ----
 void fill(double* X, int64_t m, int64_t n, int64_t ld, double v, double diag, hipStream_t s);
