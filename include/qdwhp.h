@@ -67,8 +67,14 @@ typedef struct {
   double   kappa_max;      /* 100 : a step is QR-based when its bound on cond(Z)
                                     exceeds this (Sec. 4.2 advises QR when ill-conditioned) */
   int      svd_qr_first;   /* 1   : SVD step 0 QR-based (Table 1 counts one QR step)  */
-  int      precision;      /* QDWHP_FP64 or QDWHP_MIXED_FP32                         */
-  int      polish_steps;   /* 1   : FP64 Newton-Schulz steps after mixed iterations   */
+  int      precision;      /* QDWHP_FP64, or QDWHP_MIXED_FP32: the Gram matrix and
+                              the two triangular products of every Cholesky-based
+                              step on FP32 matrix cores; QR-based steps, the
+                              Cholesky-inversion, projector QR and Rayleigh-Ritz
+                              stay FP64                                             */
+  int      polish_steps;   /* 1   : FP64 polish steps after mixed iterations
+                              (Newton-Schulz X(3I - X^T X)/2; EIG uses Halley's
+                              (3,1,3) step when the unwanted side exceeds sqrt(3)) */
   uint64_t seed;           /* Philox key of the Lanczos start vectors               */
   int      lanczos_vectors;/* 8   : independent Lanczos runs of the estimator         */
   int      lanczos_steps;  /* 64  : steps per run (capped at n-1)                     */
@@ -146,13 +152,18 @@ int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
  * C is m x n, op(A) m x k, op(B) k x n, all column-major FP64 on the device.
  * The dense product behind every step of the method (Gram matrix of Eq. (3),
  * Q1 Q2^T of Eq. (2), the Rayleigh-Ritz projections of Algorithms 1 and 2).
- * upper != 0 computes only the 128x128 tiles of C that meet the upper
- * triangle (C must be square; the strictly-lower part of diagonal tiles is
- * written, other lower tiles are left untouched).
+ * flags bit 0 (QDWHP_GEMM_UPPER): compute only the 128x128 tiles of C that
+ * meet the upper triangle (C square; the strictly-lower part of diagonal
+ * tiles is written, other lower tiles are left untouched).
+ * flags bit 1 (QDWHP_GEMM_F32): operands are rounded to FP32 and multiplied
+ * on the FP32 matrix cores with FP32 accumulation; alpha, beta and C stay
+ * FP64 (the mixed-precision Cholesky-based step).
  */
+#define QDWHP_GEMM_UPPER 1
+#define QDWHP_GEMM_F32   2
 int qdwhp_dgemm(int transa, int transb, int64_t m, int64_t n, int64_t k,
                 double alpha, const double* A, int64_t lda, const double* B,
-                int64_t ldb, double beta, double* C, int64_t ldc, int upper,
+                int64_t ldb, double beta, double* C, int64_t ldc, int flags,
                 void* stream);
 
 /*

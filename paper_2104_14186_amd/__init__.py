@@ -137,7 +137,7 @@ def _workspace(torch, nbytes, device):
     return torch.empty(max(1, (nbytes + 7) // 8), dtype=torch.float64, device=device)
 
 
-def dgemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, upper=False):
+def dgemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, upper=False, f32=False):
     """C = alpha op(A) op(B) + beta C on column-major views.
 
     A, B, C are 2-D float64 CUDA tensors given as column-major buffers, i.e.
@@ -153,7 +153,7 @@ def dgemm(A, B, C=None, alpha=1.0, beta=0.0, transa=False, transb=False, upper=F
     if C is None:
         C = torch.zeros((n, m), dtype=torch.float64, device=A.device)
     st = lib().qdwhp_dgemm(int(transa), int(transb), m, n, k, alpha, _ptr(A), ma, _ptr(B), mb,
-                           beta, _ptr(C), m, int(upper), _stream(torch))
+                           beta, _ptr(C), m, int(upper) | (2 if f32 else 0), _stream(torch))
     _check(st, "qdwhp_dgemm")
     return C
 

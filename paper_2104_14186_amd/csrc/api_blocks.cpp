@@ -53,7 +53,7 @@ extern "C" int qdwhp_dgemm(int transa, int transb, int64_t m, int64_t n, int64_t
   if (lda < (transa ? (k > 1 ? k : 1) : (m > 1 ? m : 1))) return -8;
   if (ldb < (transb ? (n > 1 ? n : 1) : (k > 1 ? k : 1))) return -10;
   if (ldc < (m > 1 ? m : 1)) return -13;
-  if (upper && m != n) return -14;
+  if ((upper & 1) && m != n) return -14;
   if (m == 0 || n == 0) return QDWHP_OK;
   if ((k > 0 && (!A || !B)) || !C) return -7;
   try {
@@ -62,7 +62,8 @@ extern "C" int qdwhp_dgemm(int transa, int transb, int64_t m, int64_t n, int64_t
     g.A = A; g.lda = lda; g.ta = transa;
     g.B = B; g.ldb = ldb; g.tb = transb;
     g.C = C; g.ldc = ldc;
-    g.tiles = upper ? TILES_UPPER : TILES_ALL;
+    g.tiles = (upper & 1) ? TILES_UPPER : TILES_ALL;
+    g.f32 = (upper & 2) != 0;
     dgemm(g, (hipStream_t)stream);
   } catch (const HipError&) {
     return QDWHP_ERR_HIP;

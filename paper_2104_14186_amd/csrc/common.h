@@ -56,6 +56,7 @@ struct Gemm {
   // Optional scratch for a deterministic split-K (partials summed in order).
   double* ws = nullptr; int64_t ws_doubles = 0;
   int splitk = 1;        // set by dgemm(); callers leave it at 1
+  bool f32 = false;      // FP32 matrix cores (operands rounded to FP32, FP64 epilogue)
 };
 void dgemm(const Gemm& g, hipStream_t s);
 // Algorithmic flops of one GEMM call: 2 x (number of products the operation

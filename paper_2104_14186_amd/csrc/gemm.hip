@@ -2,6 +2,13 @@
 //
 // Result layout of v_mfma_f64_16x16x4f64 (checked on gfx950): lane l, element r
 // holds D[l/16 + 4r][l%16]; operands A[l%16][l/16] and B[l/16][l%16].
+// v_mfma_f32_16x16x4f32 (the mixed-precision variant) takes the same operand
+// layout but holds D[4(l/16) + r][l%16].
+//
+// Mixed precision (Gemm::f32): operands stay FP64 in HBM and are rounded to
+// FP32 when staged into LDS; products accumulate in FP32 on the FP32 matrix
+// cores (twice the FP64 rate); alpha, beta, the C term and the diagonal shift
+// are applied in FP64.
 //
 // Column-major operands.  One 256-thread workgroup (4 wave64s in a 2x2
 // arrangement) owns a 128x128 tile of C; each wave accumulates a 64x64
@@ -22,18 +29,72 @@ namespace {
 
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int PAD = 4;
-constexpr int SA = BM + PAD;   // LDS row stride (doubles) of the k-major A slice
+constexpr int SA = BM + PAD;   // LDS row stride (elements) of the k-major A slice
 constexpr int SB = BN + PAD;
+constexpr int NLD = BM * BK / 256;   // elements of each operand slice loaded per thread (8)
+constexpr int GM = 8;                // tile rows per group of the launch order
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
-  __shared__ double As[2][BK * SA];
-  __shared__ double Bs[2][BK * SB];
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <bool F32> struct MfmaT;
+template <> struct MfmaT<false> {
+  typedef double elem; typedef v4d acc;
+  static __device__ inline acc op(double a, double b, acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int r) { return lk + 4 * r; }
+};
+template <> struct MfmaT<true> {
+  typedef float elem; typedef v4f acc;
+  static __device__ inline acc op(float a, float b, acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int lk, int r) { return 4 * lk + r; }
+};
+
+// Launch order.  The hardware deals consecutive workgroups round-robin to the
+// 8 XCDs (each with its own L2); the linear id is remapped so each XCD gets a
+// contiguous range of the tile list.  Full launches walk groups of GM tile
+// rows column by column (workgroups resident together share A and B slices);
+// upper-triangle launches enumerate exactly the tiles with tm <= tn, column by
+// column, so every XCD gets the same number of tiles.
+__device__ inline int64_t xcd_remap(int64_t w, int64_t W) {
+  const int64_t q = W / 8, r = W % 8, xcd = w % 8, loc = w / 8;
+  return (xcd < r) ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
+}
+__device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, int64_t* tm, int64_t* tn) {
+  if (upper) {
+    const int64_t W = gx * (gx + 1) / 2;
+    const int64_t L = xcd_remap(w, W);
+    int64_t c = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) / 2.0);
+    while (c * (c + 1) / 2 > L) --c;
+    while ((c + 1) * (c + 2) / 2 <= L) ++c;
+    *tn = c;
+    *tm = L - c * (c + 1) / 2;
+    return;
+  }
+  const int64_t L = xcd_remap(w, gx * gy);
+  const int64_t per = (int64_t)GM * gy;
+  const int64_t grp = L / per, first = grp * GM;
+  const int64_t gm = (gx - first < GM) ? gx - first : GM;
+  const int64_t in = L % per;
+  *tm = first + in % gm;
+  *tn = in / gm;
+}
+
+template <bool TA, bool TB, bool F32>
+__global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
+  typedef typename MfmaT<F32>::elem E;
+  typedef typename MfmaT<F32>::acc ACC;
+  __shared__ E As[2][BK * SA];
+  __shared__ E Bs[2][BK * SB];
 
   const int tid = threadIdx.x;
-  const int64_t row0 = (int64_t)blockIdx.x * BM;
-  const int64_t col0 = (int64_t)blockIdx.y * BN;
-  if (g.tiles == TILES_UPPER && row0 > col0 + BN - 1) return;
+  const bool upper = (g.tiles == TILES_UPPER);
+  int64_t tm, tn;
+  tile_of(blockIdx.x, gx, gy, upper, &tm, &tn);
+  const int64_t row0 = tm * BM;
+  const int64_t col0 = tn * BN;
   const bool split = g.splitk > 1;
   const int64_t bz = split ? 0 : blockIdx.z;
   const double* __restrict__ A = g.A + bz * g.sA;
@@ -43,6 +104,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
   const int64_t ldcin = g.Cin ? g.ldcin : g.ldc;
   const int64_t M = g.M, N = g.N;
   const bool aul = g.a_unit_lower, bul = g.b_unit_lower;
+  const int64_t lda = g.lda, ldb = g.ldb;
 
   int64_t klo = 0, khi = g.K;
   if (g.klo == KLO_ROW) klo = row0 - g.koff;
@@ -57,62 +119,100 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
     if (klo < z * kc) klo = z * kc;
     if (khi > (z + 1) * kc) khi = (z + 1) * kc;
   }
+  // tiles that need no bounds or structure masks use straight-line loads
+  const bool interior = row0 + BM <= M && col0 + BN <= N && !aul && !bul;
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int li = lane & 15, lk = lane >> 4;
 
-  v4d acc[4][4];
+  // Operand slices are read with buffer loads: the 128-bit resource (scalar
+  // registers) points at the slice's corner and each thread keeps one 32-bit
+  // byte offset per element it loads.  Offsets at or beyond OOB read as zero,
+  // which is how bounds, K ranges and structure masks are applied.
+  //   A (m, k):  !TA: stored A[m + k lda] (thread: m = am, k = ak + 2r)
+  //               TA: stored A[k + m lda] (thread: m = am + 16r, k = ak)
+  //   B (k, n):  !TB: stored B[k + n ldb] (thread: n = bn + 16r, k = bk)
+  //               TB: stored B[n + k ldb] (thread: n = bn, k = bk + 2r)
+  const int am = TA ? (tid >> 4) : (tid & 127);
+  const int ak = TA ? (tid & 15) : (tid >> 7);
+  const int bn = TB ? (tid & 127) : (tid >> 4);
+  const int bk = TB ? (tid >> 7) : (tid & 15);
+  constexpr uint32_t OOB = 0x80000000u, RECORDS = 0x7ffffff8u;
+  uint32_t aoff[NLD], boff[NLD];
+#pragma unroll
+  for (int r = 0; r < NLD; ++r) {
+    aoff[r] = TA ? (uint32_t)((ak + (int64_t)(am + 16 * r) * lda) * 8)
+                 : (uint32_t)((am + (int64_t)(ak + 2 * r) * lda) * 8);
+    boff[r] = TB ? (uint32_t)((bn + (int64_t)(bk + 2 * r) * ldb) * 8)
+                 : (uint32_t)((bk + (int64_t)(bn + 16 * r) * ldb) * 8);
+  }
+  auto slice_a = [&](int64_t k0) {
+    const double* p = TA ? A + row0 * lda + k0 : A + k0 * lda + row0;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)RECORDS, 0x00020000);
+  };
+  auto slice_b = [&](int64_t k0) {
+    const double* p = TB ? B + k0 * ldb + col0 : B + col0 * ldb + k0;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)RECORDS, 0x00020000);
+  };
+  auto ld = [](__amdgpu_buffer_rsrc_t rs, uint32_t off) -> double {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+  };
+
+  ACC acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[i][j] = ACC{0, 0, 0, 0};
+  double acc64[F32 ? 4 : 1][F32 ? 4 : 1][4];   // FP32 path: slice sums added here in FP64
+  if constexpr (F32) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
+  }
 
-  double ra[8], rb[8];
+  E ra[NLD], rb[NLD];
 
   auto load = [&](int64_t k0) {
+    const __amdgpu_buffer_rsrc_t rsa = slice_a(k0), rsb = slice_b(k0);
+    if (interior && k0 + BK <= khi) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      int64_t m, k;
-      if (!TA) { m = row0 + (tid & 127); k = k0 + (tid >> 7) + 2 * r; }
-      else     { k = k0 + (tid & 15);    m = row0 + (tid >> 4) + 16 * r; }
-      double v = 0.0;
-      if (m < M && k < khi && k >= klo) {
-        const int64_t sr = TA ? k : m, sc = TA ? m : k;   // stored (row, col)
-        if (!aul || sr > sc) v = A[sr + sc * g.lda];
-        else if (sr == sc) v = 1.0;
-      }
-      ra[r] = v;
+      for (int r = 0; r < NLD; ++r) ra[r] = (E)ld(rsa, aoff[r]);
+#pragma unroll
+      for (int r = 0; r < NLD; ++r) rb[r] = (E)ld(rsb, boff[r]);
+      return;
     }
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      int64_t n, k;
-      if (TB) { n = col0 + (tid & 127); k = k0 + (tid >> 7) + 2 * r; }
-      else    { k = k0 + (tid & 15);    n = col0 + (tid >> 4) + 16 * r; }
-      double v = 0.0;
-      if (n < N && k < khi && k >= klo) {
-        const int64_t sr = TB ? n : k, sc = TB ? k : n;
-        if (!bul || sr > sc) v = B[sr + sc * g.ldb];
-        else if (sr == sc) v = 1.0;
-      }
-      rb[r] = v;
+    for (int r = 0; r < NLD; ++r) {
+      const int64_t m = row0 + am + (TA ? 16 * r : 0), k = k0 + ak + (TA ? 0 : 2 * r);
+      const int64_t sr = TA ? k : m, sc = TA ? m : k;   // stored (row, col)
+      const bool in = m < M && k >= klo && k < khi;
+      const bool take = in && (!aul || sr > sc);
+      double v = ld(rsa, take ? aoff[r] : OOB);
+      if (aul && in && sr == sc) v = 1.0;
+      ra[r] = (E)v;
+    }
+#pragma unroll
+    for (int r = 0; r < NLD; ++r) {
+      const int64_t n = col0 + bn + (TB ? 0 : 16 * r), k = k0 + bk + (TB ? 2 * r : 0);
+      const int64_t sr = TB ? n : k, sc = TB ? k : n;
+      const bool in = n < N && k >= klo && k < khi;
+      const bool take = in && (!bul || sr > sc);
+      double v = ld(rsb, take ? boff[r] : OOB);
+      if (bul && in && sr == sc) v = 1.0;
+      rb[r] = (E)v;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      int m, k;
-      if (!TA) { m = tid & 127; k = (tid >> 7) + 2 * r; }
-      else     { k = tid & 15;  m = (tid >> 4) + 16 * r; }
-      As[buf][k * SA + m] = ra[r];
-    }
+    for (int r = 0; r < NLD; ++r)
+      As[buf][(ak + (TA ? 0 : 2 * r)) * SA + am + (TA ? 16 * r : 0)] = ra[r];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      int n, k;
-      if (TB) { n = tid & 127; k = (tid >> 7) + 2 * r; }
-      else    { k = tid & 15;  n = (tid >> 4) + 16 * r; }
-      Bs[buf][k * SB + n] = rb[r];
-    }
+    for (int r = 0; r < NLD; ++r)
+      Bs[buf][(bk + (TB ? 2 * r : 0)) * SB + bn + (TB ? 0 : 16 * r)] = rb[r];
   };
 
   if (khi > klo) {
@@ -125,11 +225,11 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
       const int cur = (int)(t & 1);
       const bool more = (t + 1 < nk);
       if (more) load(kbeg + (t + 1) * BK);
-      const double* as = As[cur];
-      const double* bs = Bs[cur];
+      const E* as = As[cur];
+      const E* bs = Bs[cur];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        double a[4], b[4];
+        E a[4], b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) a[i] = as[(kk + lk) * SA + wm * 64 + i * 16 + li];
 #pragma unroll
@@ -138,13 +238,27 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
         for (int i = 0; i < 4; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = MfmaT<F32>::op(a[i], b[j], acc[i][j]);
+      }
+      if constexpr (F32) {
+        if ((t & 1) || !more) {   // every 32 k: fold the FP32 sums into FP64
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+              for (int r = 0; r < 4; ++r) { acc64[i][j][r] += (double)acc[i][j][r]; acc[i][j][r] = 0.0f; }
+        }
       }
       if (more) store(cur ^ 1);
       __syncthreads();
     }
   }
 
+  auto result = [&](int i, int j, int r) -> double {
+    if constexpr (F32) return acc64[i][j][r];
+    else return acc[i][j][r];
+  };
   const double alpha = g.alpha, beta = g.beta, dg = g.diag;
   if (split) {   // raw partial product of this K share
     double* P = g.ws + (int64_t)blockIdx.z * M * N;
@@ -154,9 +268,9 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
       for (int j = 0; j < 4; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = row0 + wm * 64 + i * 16 + lk + 4 * r;
+          const int64_t row = row0 + wm * 64 + i * 16 + MfmaT<F32>::row(lk, r);
           const int64_t col = col0 + wn * 64 + j * 16 + li;
-          if (row < M && col < N) P[row + col * M] = acc[i][j][r];
+          if (row < M && col < N) P[row + col * M] = result(i, j, r);
         }
     return;
   }
@@ -166,11 +280,11 @@ __global__ __launch_bounds__(256) void dgemm_kernel(Gemm g) {
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * 64 + i * 16 + lk + 4 * r;
+        const int64_t row = row0 + wm * 64 + i * 16 + MfmaT<F32>::row(lk, r);
         const int64_t col = col0 + wn * 64 + j * 16 + li;
         if (row < M && col < N) {
           double* p = C + row + col * g.ldc;
-          double v = alpha * acc[i][j][r];
+          double v = alpha * result(i, j, r);
           if (beta != 0.0) v += beta * Cin[row + col * ldcin];
           if (dg != 0.0 && row == col) v += dg;
           *p = v;
@@ -264,19 +378,32 @@ void dgemm(const Gemm& g0, hipStream_t s) {
     if (S > 64) S = 64;
     if (S >= 2) g.splitk = (int)S;
   }
-  dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)(g.splitk > 1 ? g.splitk : g.batch));
+  if (g.tiles == TILES_UPPER && tm != tn)
+    throw HipError{hipErrorInvalidValue};   // upper-tile output must be square
+  // every per-thread byte offset inside an operand slice must fit in 31 bits
+  if ((g.lda > 0 && g.lda >= (int64_t(1) << 21)) || (g.ldb > 0 && g.ldb >= (int64_t(1) << 21)))
+    throw HipError{hipErrorInvalidValue};   // leading dimension too large
+  const int64_t ntile = (g.tiles == TILES_UPPER) ? tm * (tm + 1) / 2 : tm * tn;
+  dim3 grid((unsigned)ntile, 1, (unsigned)(g.splitk > 1 ? g.splitk : g.batch));
   dim3 block(256);
-  if (!g.ta && !g.tb) dgemm_kernel<false, false><<<grid, block, 0, s>>>(g);
-  else if (!g.ta && g.tb) dgemm_kernel<false, true><<<grid, block, 0, s>>>(g);
-  else if (g.ta && !g.tb) dgemm_kernel<true, false><<<grid, block, 0, s>>>(g);
-  else dgemm_kernel<true, true><<<grid, block, 0, s>>>(g);
+  if (!g.f32) {
+    if (!g.ta && !g.tb) dgemm_kernel<false, false, false><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (!g.ta && g.tb) dgemm_kernel<false, true, false><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (g.ta && !g.tb) dgemm_kernel<true, false, false><<<grid, block, 0, s>>>(g, tm, tn);
+    else dgemm_kernel<true, true, false><<<grid, block, 0, s>>>(g, tm, tn);
+  } else {
+    if (!g.ta && !g.tb) dgemm_kernel<false, false, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (!g.ta && g.tb) dgemm_kernel<false, true, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (g.ta && !g.tb) dgemm_kernel<true, false, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else dgemm_kernel<true, true, true><<<grid, block, 0, s>>>(g, tm, tn);
+  }
   QDWHP_LAUNCH_CHECK();
   if (g.splitk > 1) {
     dim3 rg((unsigned)cdiv(g.M, 256), (unsigned)(g.N < 65535 ? g.N : 65535));
     splitk_reduce<<<rg, 256, 0, s>>>(g);
     QDWHP_LAUNCH_CHECK();
   }
-  if (prof) prof_end_launch(s, tok, gemm_flops(g0));
+  if (prof) prof_end_launch(s, tok, g0.f32 ? 0.0 : gemm_flops(g0));
 }
 
 }  // namespace qdwhp

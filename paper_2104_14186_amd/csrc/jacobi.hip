@@ -6,12 +6,16 @@
 // blocks once in round-robin (circle) order; in each step the Nb/2 disjoint
 // pairs are independent:
 //   * two-sided (symmetric H): the 32x32 diagonal sub-problem of each pair is
-//     diagonalised in LDS by cyclic Jacobi (one wave64 per pair, 16 disjoint
-//     rotations per round), giving an orthogonal J; then H <- J^T H J tile by
-//     tile (tile (P,Q) becomes J_P^T H_PQ J_Q) and V <- V J;
+//     diagonalised in LDS by cyclic Jacobi (16 disjoint rotations per
+//     round), giving an orthogonal J; then H <- J^T H J tile by tile (tile
+//     (P,Q) becomes J_P^T H_PQ J_Q) and V <- V J;
 //   * one-sided (R): each pair forms the Gram matrix of its 32 columns,
 //     diagonalises it the same way and rotates the columns of R and V by J,
 //     making them mutually orthogonal.
+// Each block rotation J is re-orthonormalised by one Newton-Schulz step: the
+// thousands of plane rotations inside one sub-problem leave J off orthogonal
+// by a random walk of roundings, which would otherwise accumulate over the
+// steps into the eigenvalues and residuals.
 // Off-diagonal magnitudes seen at the start of each pair solve are max-reduced
 // per sweep (an order-independent atomic max) and decide convergence.
 #include "common.h"
@@ -20,10 +24,12 @@
 namespace qdwhp {
 namespace {
 
-constexpr int P2 = 2 * JB;     // 32: size of a pair sub-problem
+constexpr int P2 = 2 * JB;     // size of a pair sub-problem
 constexpr int LDM = P2 + 1;
+constexpr int NT = (P2 / 4) * (P2 / 4);   // threads of the pair / tile kernels: 4x4 outputs each
+constexpr int ROT = P2 / 2;    // rotations per round
 
-// Pair (p, q) of step `step` in the circle method over nb (even) blocks.
+// Pair (p, q) of step `step` in the circle method over nb (even) players.
 __device__ __host__ inline void round_robin(int nb, int step, int i, int* p, int* q) {
   const int m = nb - 1;
   int a, b;
@@ -38,21 +44,23 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
 }
 
 // Cyclic Jacobi on the P2 x P2 symmetric M (LDS), accumulating J (LDS, starts
-// as identity).  Called by every thread of the block (blockDim.x >= 16).  A
-// rotation is skipped when |m_pq| <= tol (abs) or <= tol * sqrt(m_pp m_qq)
-// (relative).  Returns sweeps used.
+// as identity), with NT threads.  A rotation is skipped when |m_pq| <= tol
+// (abs) or <= tol * sqrt(m_pp m_qq) (relative).  Row and column updates stage
+// every value a thread touches in registers before storing (an LDS store
+// between two loads would serialise them).
 __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool relative,
                             int max_sweeps) {
-  __shared__ double cs[P2 / 2][2];
-  __shared__ int pidx[P2 / 2][2];
+  __shared__ double cs[ROT][2];
+  __shared__ int pidx[ROT][2];
   __shared__ int any;
-  const int t = threadIdx.x, nt = blockDim.x;
+  constexpr int PER = ROT * P2 / NT;   // (rotation, index) pairs per thread: 8
+  const int t = threadIdx.x;
   int sw = 0;
   for (; sw < max_sweeps; ++sw) {
     if (t == 0) any = 0;
     __syncthreads();
     for (int r = 0; r < P2 - 1; ++r) {
-      if (t < P2 / 2) {
+      if (t < ROT) {
         int p, q;
         round_robin(P2, r, t, &p, &q);
         const double app = M[p][p], aqq = M[q][q], apq = M[p][q];
@@ -73,34 +81,49 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
         cs[t][0] = c; cs[t][1] = s; pidx[t][0] = p; pidx[t][1] = q;
       }
       __syncthreads();
-      // rows: M <- J^T M   (thread handles column j of rows p, q of rotation k)
-      for (int e = t; e < (P2 / 2) * P2; e += nt) {
-        const int k = e / P2, j = e % P2;
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const int p = pidx[k][0], q = pidx[k][1];
-          const double mp = M[p][j], mq = M[q][j];
-          M[p][j] = c * mp - s * mq;
-          M[q][j] = s * mp + c * mq;
+      {  // rows: M <- J_r^T M
+        double mp[PER], mq[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = t + NT * u, k = e / P2, j = e % P2;
+          mp[u] = M[pidx[k][0]][j];
+          mq[u] = M[pidx[k][1]][j];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = t + NT * u, k = e / P2, j = e % P2;
+          const double c = cs[k][0], s = cs[k][1];
+          if (s != 0.0) {
+            M[pidx[k][0]][j] = c * mp[u] - s * mq[u];
+            M[pidx[k][1]][j] = s * mp[u] + c * mq[u];
+          }
         }
       }
       __syncthreads();
-      // columns: M <- M J and J <- J J_r
-      for (int e = t; e < (P2 / 2) * P2; e += nt) {
-        const int k = e / P2, i = e % P2;
-        const double c = cs[k][0], s = cs[k][1];
-        if (s != 0.0) {
-          const int p = pidx[k][0], q = pidx[k][1];
-          const double mp = M[i][p], mq = M[i][q];
-          M[i][p] = c * mp - s * mq;
-          M[i][q] = s * mp + c * mq;
-          const double jp = J[i][p], jq = J[i][q];
-          J[i][p] = c * jp - s * jq;
-          J[i][q] = s * jp + c * jq;
+      {  // columns: M <- M J_r, J <- J J_r
+        double mp[PER], mq[PER], jp[PER], jq[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = t + NT * u, k = e / P2, i = e % P2;
+          mp[u] = M[i][pidx[k][0]]; mq[u] = M[i][pidx[k][1]];
+          jp[u] = J[i][pidx[k][0]]; jq[u] = J[i][pidx[k][1]];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+          const int e = t + NT * u, k = e / P2, i = e % P2;
+          const double c = cs[k][0], s = cs[k][1];
+          if (s != 0.0) {
+            M[i][pidx[k][0]] = c * mp[u] - s * mq[u];
+            M[i][pidx[k][1]] = s * mp[u] + c * mq[u];
+            J[i][pidx[k][0]] = c * jp[u] - s * jq[u];
+            J[i][pidx[k][1]] = s * jp[u] + c * jq[u];
+          }
         }
       }
       __syncthreads();
-      if (t < P2 / 2 && cs[t][1] != 0.0) {
+      if (t < ROT && cs[t][1] != 0.0) {
         const int p = pidx[t][0], q = pidx[t][1];
         M[p][q] = 0.0; M[q][p] = 0.0;
       }
@@ -113,30 +136,49 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
   return sw;
 }
 
+// C = op(A) B for P2 x P2 LDS matrices (op = transpose when ta), 4x4 outputs
+// per thread.  C must not alias A or B.
+__device__ inline void lds_mm(const double (*A)[LDM], bool ta, const double (*B)[LDM],
+                              double (*C)[LDM], double alpha, const double (*D)[LDM], double beta) {
+  const int t = threadIdx.x;
+  const int i0 = (t % (P2 / 4)) * 4, j0 = (t / (P2 / 4)) * 4;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int k = 0; k < P2; ++k) {
+    double av[4], bv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = ta ? A[k][i0 + a] : A[i0 + a][k];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) bv[b] = B[k][j0 + b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double v = alpha * acc[a][b];
+      if (D) v += beta * D[i0 + a][j0 + b];
+      C[i0 + a][j0 + b] = v;
+    }
+}
+
 // J <- J (3I - J^T J) / 2: one Newton-Schulz step towards the nearest
-// orthogonal matrix.  The thousands of rotations of a sub-problem leave J
-// off orthogonal by a random walk of roundings; without this step that drift
-// accumulates over the block steps into the eigenvalues and residuals.
-__device__ void orthonormalize(double (*J)[LDM], double (*T)[LDM]) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int e = t; e < P2 * P2; e += nt) {      // T = (3I - J^T J) / 2
-    const int i = e % P2, j = e / P2;
-    double acc = 0.0;
-    for (int k = 0; k < P2; ++k) acc += J[k][i] * J[k][j];
-    T[i][j] = ((i == j) ? 1.5 : 0.0) - 0.5 * acc;
-  }
+// orthogonal matrix.  T and U are LDS scratch.
+__device__ void orthonormalize(double (*J)[LDM], double (*T)[LDM], double (*U)[LDM]) {
+  const int t = threadIdx.x;
+  lds_mm(J, true, J, T, -0.5, nullptr, 0.0);           // T = -J^T J / 2
   __syncthreads();
-  double out[P2 * P2 / 64];
-  int cnt = 0;
-  for (int e = t; e < P2 * P2; e += nt) {      // J T
-    const int i = e % P2, j = e / P2;
-    double acc = 0.0;
-    for (int k = 0; k < P2; ++k) acc += J[i][k] * T[k][j];
-    out[cnt++] = acc;
-  }
+  if (t < P2) T[t][t] += 1.5;                          // T = (3I - J^T J)/2
   __syncthreads();
-  cnt = 0;
-  for (int e = t; e < P2 * P2; e += nt) J[e % P2][e / P2] = out[cnt++];
+  lds_mm(J, false, T, U, 1.0, nullptr, 0.0);           // U = J T
+  __syncthreads();
+  for (int e = t; e < P2 * P2; e += NT) J[e % P2][e / P2] = U[e % P2][e / P2];
   __syncthreads();
 }
 
@@ -154,19 +196,20 @@ __device__ inline int64_t blk_index(int p, int q, int i) {  // pair (p,q) local 
   return (i < JB) ? (int64_t)p * JB + i : (int64_t)q * JB + (i - JB);
 }
 
-// One wave per pair: gather the pair's 32x32 diagonal sub-problem, diagonalise,
-// store J and write the rotated (diagonal) sub-problem back.
-__global__ __launch_bounds__(64) void sym_pair_kernel(SymArgs a) {
+// One workgroup per pair: gather the pair's diagonal sub-problem,
+// diagonalise, re-orthonormalise J, store J and write back the rotated
+// sub-problem with its diagonal recomputed as diag(J^T M0 J).
+__global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
   __shared__ double M[P2][LDM];
   __shared__ double J[P2][LDM];
   __shared__ double M0[P2][LDM];
   __shared__ double T[P2][LDM];
-  __shared__ double dg[P2];
+  __shared__ double red[NT / 64];
   const int t = threadIdx.x;
   int p, q;
   round_robin(a.nb, a.step, blockIdx.x, &p, &q);
   double off = 0.0;
-  for (int e = t; e < P2 * P2; e += 64) {
+  for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
     const double v = a.H[blk_index(p, q, i) + blk_index(p, q, j) * a.ldh];
     M[i][j] = v;
@@ -175,40 +218,40 @@ __global__ __launch_bounds__(64) void sym_pair_kernel(SymArgs a) {
     if (i != j) off = fmax(off, fabs(v));
   }
   for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
-  if (t == 0) atomic_max_nonneg(a.offmax + a.sweep, off);
+  if ((t & 63) == 0) red[t >> 6] = off;
   __syncthreads();
+  if (t == 0) {
+    double m = red[0];
+    for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
+    atomic_max_nonneg(a.offmax + a.sweep, m);
+  }
   inner_jacobi(M, J, a.tol, false, 30);
-  orthonormalize(J, T);
-  // diagonal of J^T M0 J with the orthonormalised J (T = M0 J)
-  for (int e = t; e < P2 * P2; e += 64) {
+  // off-diagonal part of the rotated sub-problem goes back now, freeing M
+  for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
-    double acc = 0.0;
-    for (int k = 0; k < P2; ++k) acc += M0[i][k] * J[k][j];
-    T[i][j] = acc;
+    if (i != j) a.H[blk_index(p, q, i) + blk_index(p, q, j) * a.ldh] = M[i][j];
   }
   __syncthreads();
+  orthonormalize(J, T, M);
+  // diagonal of J^T M0 J with the orthonormalised J: T = M0 J, d_i = sum_k J[k][i] T[k][i]
+  lds_mm(M0, false, J, T, 1.0, nullptr, 0.0);
+  __syncthreads();
+  double* Jout = a.Jb + (int64_t)blockIdx.x * P2 * P2;
+  for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[e % P2][e / P2];
   if (t < P2) {
     double acc = 0.0;
     for (int k = 0; k < P2; ++k) acc += J[k][t] * T[k][t];
-    dg[t] = acc;
-  }
-  __syncthreads();
-  double* Jout = a.Jb + (int64_t)blockIdx.x * P2 * P2;
-  for (int e = t; e < P2 * P2; e += 64) {
-    const int i = e % P2, j = e / P2;
-    Jout[i + j * P2] = J[i][j];
-    a.H[blk_index(p, q, i) + blk_index(p, q, j) * a.ldh] = (i == j) ? dg[i] : M[i][j];
+    a.H[blk_index(p, q, t) + blk_index(p, q, t) * a.ldh] = acc;
   }
 }
 
 // Tile (P, Q), P < Q over pair indices: H_PQ <- J_P^T H_PQ J_Q, mirrored to H_QP.
-__global__ __launch_bounds__(256) void sym_update_kernel(SymArgs a) {
+__global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   __shared__ double X[P2][LDM];
   __shared__ double Y[P2][LDM];
   __shared__ double JP[P2][LDM];
   __shared__ double JQ[P2][LDM];
   const int np = a.nb / 2;
-  // linear index over pairs P < Q
   const int64_t lin = blockIdx.x;
   int P = 0;
   int64_t rem = lin;
@@ -220,143 +263,148 @@ __global__ __launch_bounds__(256) void sym_update_kernel(SymArgs a) {
   const int t = threadIdx.x;
   const double* JbP = a.Jb + (int64_t)P * P2 * P2;
   const double* JbQ = a.Jb + (int64_t)Q * P2 * P2;
-  for (int e = t; e < P2 * P2; e += 256) {
+  for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
     X[i][j] = a.H[blk_index(pP, qP, i) + blk_index(pQ, qQ, j) * a.ldh];
     JP[i][j] = JbP[e];
     JQ[i][j] = JbQ[e];
   }
   __syncthreads();
-  for (int e = t; e < P2 * P2; e += 256) {   // Y = J_P^T X
-    const int i = e % P2, j = e / P2;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < P2; ++k) acc += JP[k][i] * X[k][j];
-    Y[i][j] = acc;
-  }
+  lds_mm(JP, true, X, Y, 1.0, nullptr, 0.0);     // Y = J_P^T X
   __syncthreads();
-  for (int e = t; e < P2 * P2; e += 256) {   // Z = Y J_Q
+  lds_mm(Y, false, JQ, X, 1.0, nullptr, 0.0);    // X = Y J_Q
+  __syncthreads();
+  for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < P2; ++k) acc += Y[i][k] * JQ[k][j];
     const int64_t gi = blk_index(pP, qP, i), gj = blk_index(pQ, qQ, j);
-    a.H[gi + gj * a.ldh] = acc;
-    a.H[gj + gi * a.ldh] = acc;
+    const double v = X[i][j];
+    a.H[gi + gj * a.ldh] = v;
+    a.H[gj + gi * a.ldh] = v;
   }
 }
 
-// V[:, pair Q] <- V[:, pair Q] J_Q for a chunk of 64 rows.
-__global__ __launch_bounds__(256) void cols_update_kernel(double* V, int64_t ldv, int64_t rows, int nb,
+// V[:, pair Q] <- V[:, pair Q] J_Q for a chunk of P2 rows.
+__global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv, int64_t rows, int nb,
                                                          int step, const double* Jb) {
   __shared__ double JQ[P2][LDM];
-  __shared__ double X[64][LDM];
+  __shared__ double X[P2][LDM];
+  __shared__ double Y[P2][LDM];
   const int Q = blockIdx.y;
   int p, q;
   round_robin(nb, step, Q, &p, &q);
   const int t = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int64_t r0 = (int64_t)blockIdx.x * P2;
   const double* J = Jb + (int64_t)Q * P2 * P2;
-  for (int e = t; e < P2 * P2; e += 256) JQ[e % P2][e / P2] = J[e];
-  for (int e = t; e < 64 * P2; e += 256) {
-    const int i = e % 64, j = e / 64;
+  for (int e = t; e < P2 * P2; e += NT) {
+    const int i = e % P2, j = e / P2;
+    JQ[i][j] = J[e];
     const int64_t r = r0 + i;
     X[i][j] = (r < rows) ? V[r + blk_index(p, q, j) * ldv] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < 64 * P2; e += 256) {
-    const int i = e % 64, j = e / 64;
+  lds_mm(X, false, JQ, Y, 1.0, nullptr, 0.0);
+  __syncthreads();
+  for (int e = t; e < P2 * P2; e += NT) {
+    const int i = e % P2, j = e / P2;
     const int64_t r = r0 + i;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int k = 0; k < P2; ++k) acc += X[i][k] * JQ[k][j];
-    if (r < rows) V[r + blk_index(p, q, j) * ldv] = acc;
+    if (r < rows) V[r + blk_index(p, q, j) * ldv] = Y[i][j];
   }
 }
 
-// One-sided step: Gram of the pair's 32 columns of R (rows x npad), Jacobi,
-// rotation of those columns of R and V.  256 threads; the eigen-solve runs
-// on the first wave.
+// One-sided step: Gram of the pair's columns of R (rows x npad), Jacobi,
+// rotation of those columns of R and V.
 struct SvjArgs {
   double* R; int64_t ldr; int64_t rows; int nb;
   double* V; int64_t ldv; int64_t vrows;
   double* Jb; double tol; double* offmax; int sweep; int step;
 };
 
-__global__ __launch_bounds__(256) void svj_pair_kernel(SvjArgs a) {
+__global__ __launch_bounds__(NT) void svj_pair_kernel(SvjArgs a) {
   __shared__ double M[P2][LDM];
   __shared__ double J[P2][LDM];
-  __shared__ double X[64][LDM];
+  __shared__ double X[P2][LDM];
+  __shared__ double red[NT / 64];
   const int t = threadIdx.x;
   int p, q;
   round_robin(a.nb, a.step, blockIdx.x, &p, &q);
-  // Gram: each thread owns 4 entries of M (e = t + 256*u)
-  double g[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t r0 = 0; r0 < a.rows; r0 += 64) {
-    for (int e = t; e < 64 * P2; e += 256) {
-      const int i = e % 64, j = e / 64;
+  // Gram M = sum over row chunks of X^T X (4x4 register blocks per thread)
+  const int i0 = (t % (P2 / 4)) * 4, j0 = (t / (P2 / 4)) * 4;
+  double g[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[u][v] = 0.0;
+  for (int64_t r0 = 0; r0 < a.rows; r0 += P2) {
+    for (int e = t; e < P2 * P2; e += NT) {
+      const int i = e % P2, j = e / P2;
       const int64_t r = r0 + i;
       X[i][j] = (r < a.rows) ? a.R[r + blk_index(p, q, j) * a.ldr] : 0.0;
     }
     __syncthreads();
+    for (int k = 0; k < P2; ++k) {
+      double av[4], bv[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int e = t + 256 * u, i = e % P2, j = e / P2;
-      double acc = g[u];
-      for (int k = 0; k < 64; ++k) acc += X[k][i] * X[k][j];
-      g[u] = acc;
+      for (int u = 0; u < 4; ++u) av[u] = X[k][i0 + u];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = X[k][j0 + v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) g[u][v] += av[u] * bv[v];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int e = t + 256 * u;
-    M[e % P2][e / P2] = g[u];
-    J[e % P2][e / P2] = ((e % P2) == (e / P2)) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  if (t < 64) {
-    double off = 0.0;
-    for (int e = t; e < P2 * P2; e += 64) {
-      const int i = e % P2, j = e / P2;
-      if (i != j) {
-        const double den = sqrt(fabs(M[i][i] * M[j][j]));
-        if (den > 0.0) off = fmax(off, fabs(M[i][j]) / den);
-      }
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      M[i0 + u][j0 + v] = g[u][v];
+      J[i0 + u][j0 + v] = (i0 + u == j0 + v) ? 1.0 : 0.0;
     }
-    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
-    if (t == 0) atomic_max_nonneg(a.offmax + a.sweep, off);
-  }
   __syncthreads();
+  double off = 0.0;
+  for (int e = t; e < P2 * P2; e += NT) {
+    const int i = e % P2, j = e / P2;
+    if (i != j) {
+      const double den = sqrt(fabs(M[i][i] * M[j][j]));
+      if (den > 0.0) off = fmax(off, fabs(M[i][j]) / den);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o));
+  if ((t & 63) == 0) red[t >> 6] = off;
+  __syncthreads();
+  if (t == 0) {
+    double m = red[0];
+    for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
+    atomic_max_nonneg(a.offmax + a.sweep, m);
+  }
   inner_jacobi(M, J, a.tol, true, 30);
-  orthonormalize(J, M);
-  // rotate columns of R and V
+  orthonormalize(J, M, X);
+  // rotate columns of R and V (chunks of P2 rows; M is scratch for the product)
   for (int pass = 0; pass < 2; ++pass) {
     double* Mat = pass == 0 ? a.R : a.V;
     const int64_t ld = pass == 0 ? a.ldr : a.ldv;
     const int64_t rows = pass == 0 ? a.rows : a.vrows;
-    for (int64_t r0 = 0; r0 < rows; r0 += 64) {
-      for (int e = t; e < 64 * P2; e += 256) {
-        const int i = e % 64, j = e / 64;
+    for (int64_t r0 = 0; r0 < rows; r0 += P2) {
+      for (int e = t; e < P2 * P2; e += NT) {
+        const int i = e % P2, j = e / P2;
         const int64_t r = r0 + i;
         X[i][j] = (r < rows) ? Mat[r + blk_index(p, q, j) * ld] : 0.0;
       }
       __syncthreads();
-      for (int e = t; e < 64 * P2; e += 256) {
-        const int i = e % 64, j = e / 64;
+      lds_mm(X, false, J, M, 1.0, nullptr, 0.0);
+      __syncthreads();
+      for (int e = t; e < P2 * P2; e += NT) {
+        const int i = e % P2, j = e / P2;
         const int64_t r = r0 + i;
-        double acc = 0.0;
-#pragma unroll 8
-        for (int k = 0; k < P2; ++k) acc += X[i][k] * J[k][j];
-        if (r < rows) Mat[r + blk_index(p, q, j) * ld] = acc;
+        if (r < rows) Mat[r + blk_index(p, q, j) * ld] = M[i][j];
       }
       __syncthreads();
     }
   }
 }
 
-// Rank of each of the first n values by descending key (ties by index), then
-// gather: out[rank] = key, and column rank of Wout = column i of Win.
+// Rank of each of the first n values by descending key (ties by index).
 __global__ void rank_kernel(const double* key, int64_t kstride, int64_t n, int64_t* rank) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -370,12 +418,11 @@ __global__ void rank_kernel(const double* key, int64_t kstride, int64_t n, int64
 }
 
 __global__ void gather_cols_kernel(const double* Win, int64_t ldi, double* Wout, int64_t ldo,
-                                   int64_t rows, const int64_t* rank, int64_t n, double scale_by_norm) {
+                                   int64_t rows, const int64_t* rank, int64_t n) {
   const int64_t col = blockIdx.y;
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (col >= n || r >= rows) return;
   Wout[r + rank[col] * ldo] = Win[r + col * ldi];
-  (void)scale_by_norm;
 }
 
 __global__ void diag_gather_kernel(const double* H, int64_t ldh, int64_t n, const int64_t* rank, double* w) {
@@ -459,7 +506,9 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   QDWHP_HIP(hipStreamSynchronize(s));
   SymArgs a;
   a.H = Hp; a.ldh = np; a.nb = nb; a.n = n; a.Jb = Jb; a.V = Vp; a.ldv = np;
-  a.tol = 4.4e-16 * (hf > 0.0 ? hf : 1.0);
+  // skip / stop threshold: 2u times the rms eigenvalue ||H||_F / sqrt(n); an
+  // eigenvector's residual is then at most ~2u ||H||_F
+  a.tol = 2.0 * 1.1102230246251565e-16 * (hf > 0.0 ? hf / std::sqrt((double)n) : 1.0);
   a.offmax = offmax;
   const int np2 = nb / 2;
   const int64_t ntiles = (int64_t)np2 * (np2 - 1) / 2;
@@ -468,13 +517,13 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
     a.sweep = sw;
     for (int st = 0; st < nb - 1; ++st) {
       a.step = st;
-      sym_pair_kernel<<<np2, 64, 0, s>>>(a);
+      sym_pair_kernel<<<np2, NT, 0, s>>>(a);
       QDWHP_LAUNCH_CHECK();
       if (ntiles > 0) {
-        sym_update_kernel<<<(unsigned)ntiles, 256, 0, s>>>(a);
+        sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
         QDWHP_LAUNCH_CHECK();
       }
-      cols_update_kernel<<<dim3((unsigned)cdiv(np, 64), np2), 256, 0, s>>>(Vp, np, np, nb, st, Jb);
+      cols_update_kernel<<<dim3((unsigned)cdiv(n, P2), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb);
       QDWHP_LAUNCH_CHECK();
     }
     double off = 0.0;
@@ -487,7 +536,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   QDWHP_LAUNCH_CHECK();
   diag_gather_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(Hp, np, n, rank, w);
   QDWHP_LAUNCH_CHECK();
-  gather_cols_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)n), 256, 0, s>>>(Vp, np, W, ldw, n, rank, n, 0.0);
+  gather_cols_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)n), 256, 0, s>>>(Vp, np, W, ldw, n, rank, n);
   QDWHP_LAUNCH_CHECK();
   return sweeps;
 }
@@ -513,14 +562,14 @@ int gesvj(double* R, int64_t rows, int64_t n, int64_t ldr, double* S, double* V,
   fill(Vp, np, np, np, 0.0, 1.0, s);
   QDWHP_HIP(hipMemsetAsync(offmax, 0, 64 * sizeof(double), s));
   SvjArgs a;
-  a.R = Rp; a.ldr = rows; a.rows = rows; a.nb = nb; a.V = Vp; a.ldv = np; a.vrows = np;
-  a.Jb = Jb; a.tol = 4e-16 * sqrt((double)rows); a.offmax = offmax;
+  a.R = Rp; a.ldr = rows; a.rows = rows; a.nb = nb; a.V = Vp; a.ldv = np; a.vrows = n;
+  a.Jb = Jb; a.tol = 4e-16 * std::sqrt((double)rows); a.offmax = offmax;
   int sweeps = -1;
   for (int sw = 0; sw < 40; ++sw) {
     a.sweep = sw;
     for (int st = 0; st < nb - 1; ++st) {
       a.step = st;
-      svj_pair_kernel<<<nb / 2, 256, 0, s>>>(a);
+      svj_pair_kernel<<<nb / 2, NT, 0, s>>>(a);
       QDWHP_LAUNCH_CHECK();
     }
     double off = 0.0;
@@ -534,9 +583,9 @@ int gesvj(double* R, int64_t rows, int64_t n, int64_t ldr, double* S, double* V,
   QDWHP_LAUNCH_CHECK();
   scale_cols_kernel<<<dim3((unsigned)cdiv(rows, 256), (unsigned)n), 256, 0, s>>>(Rp, rows, rows, nrm);
   QDWHP_LAUNCH_CHECK();
-  gather_cols_kernel<<<dim3((unsigned)cdiv(rows, 256), (unsigned)n), 256, 0, s>>>(Rp, rows, R, ldr, rows, rank, n, 0.0);
+  gather_cols_kernel<<<dim3((unsigned)cdiv(rows, 256), (unsigned)n), 256, 0, s>>>(Rp, rows, R, ldr, rows, rank, n);
   QDWHP_LAUNCH_CHECK();
-  gather_cols_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)n), 256, 0, s>>>(Vp, np, V, ldv, n, rank, n, 0.0);
+  gather_cols_kernel<<<dim3((unsigned)cdiv(n, 256), (unsigned)n), 256, 0, s>>>(Vp, np, V, ldv, n, rank, n);
   QDWHP_LAUNCH_CHECK();
   scatter_rank_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(nrm, n, rank, S);
   QDWHP_LAUNCH_CHECK();

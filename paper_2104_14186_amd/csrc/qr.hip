@@ -23,43 +23,60 @@ namespace qdwhp {
 namespace {
 
 constexpr int CH = 32;          // columns per register chunk
-constexpr int RPT_MAX = 4;      // rows per thread
+constexpr int RPT_MAX = 8;      // rows per thread
+constexpr int QT = 256;         // threads per workgroup
+constexpr int NWG_MAX = 64;     // workgroups per column launch
 
 struct Panel {
   double* P; int64_t ld; int64_t h; int w;
   double* tau;
-  double* part;     // [2][256][QB] partial statistics (double-buffered by launch parity)
+  double* part;     // [2][NWG_MAX][QB] partial statistics (double-buffered by launch parity)
   double* piv;      // [2][QB] pivot-row values
   int nwg; int rpt;
 };
 
-__device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
-
-__global__ __launch_bounds__(256) void qr_col_kernel(Panel a, int j) {
+// Launch j (j = -1 gathers the statistics of column 0 only):
+//  1. sums the previous launch's partials (fixed order) into the statistics of
+//     column j: t_c = sum_{r > j} P[r][j] P[r][c], c >= j, and reads the pivot
+//     row P[j][c] saved by the previous launch;
+//  2. forms reflector j (LAPACK convention: beta = -sign(x0) ||x||,
+//     tau = (beta - x0)/beta, v = x/(x0 - beta) below the pivot, v_j = 1);
+//  3. applies H_j to this workgroup's rows of columns j+1.. and stores v;
+//  4. accumulates the statistics of column j+1 from the updated values and
+//     saves the new pivot row.
+// All loads of a reduction are issued before they are consumed (independent
+// chains), since every column pays these latencies on the critical path.
+__global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
   __shared__ double sh_s[QB];
   __shared__ double sh_w[QB];
-  __shared__ double sh_red[4][CH];
-  const int t = threadIdx.x, g = blockIdx.x, lane = t & 63, wv = t >> 6;
+  __shared__ double sh_half[2][QB];
+  __shared__ double sh_acc[QT][CH + 1];
+  __shared__ double sh_seg[QT / CH][CH];
+  const int t = threadIdx.x, g = blockIdx.x;
   const int w = a.w;
   const int64_t ld = a.ld;
   double* P = a.P;
-  const double* part_in = a.part + (int64_t)((j + 2) & 1) * 256 * QB;
-  double* part_out = a.part + (int64_t)((j + 1) & 1) * 256 * QB;
+  const double* part_in = a.part + (int64_t)((j + 2) & 1) * NWG_MAX * QB;
+  double* part_out = a.part + (int64_t)((j + 1) & 1) * NWG_MAX * QB;
   const double* piv_in = a.piv + ((j + 2) & 1) * QB;
   double* piv_out = a.piv + ((j + 1) & 1) * QB;
 
   double tau = 0.0, scale = 0.0, beta = 0.0;
   if (j >= 0) {
-    for (int c = t; c < w; c += 256) {
-      double s = 0.0;
-      if (c >= j)
-        for (int q = 0; q < a.nwg; ++q) s += part_in[(int64_t)q * QB + c];
-      sh_s[c] = s;
+    {  // column c summed by two threads over alternate partials, 8 chains each
+      const int c = t & (QB - 1), half = t >> 7;
+      double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      if (c >= j && c < w) {
+#pragma unroll
+        for (int u = 0; u < NWG_MAX / 2; ++u) {
+          const int q = 2 * u + half;
+          if (q < a.nwg) s8[u & 7] += part_in[(int64_t)q * QB + c];
+        }
+      }
+      sh_half[half][c] = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     }
+    __syncthreads();
+    if (t < QB) sh_s[t] = sh_half[0][t] + sh_half[1][t];
     __syncthreads();
     const double x0 = piv_in[j];
     const double tail2 = sh_s[j];
@@ -71,18 +88,17 @@ __global__ __launch_bounds__(256) void qr_col_kernel(Panel a, int j) {
       tau = (beta - x0) / beta;
       scale = 1.0 / (x0 - beta);
     }
-    for (int c = t; c < w; c += 256)
-      if (c > j) sh_w[c] = piv_in[c] + scale * sh_s[c];
+    if (t < w && t > j) sh_w[t] = piv_in[t] + scale * sh_s[t];
     if (g == 0 && t == 0) a.tau[j] = tau;
     __syncthreads();
   }
 
-  const int64_t rbase = (int64_t)g * 256 * a.rpt;
+  const int64_t rbase = (int64_t)g * QT * a.rpt;
   double vr[RPT_MAX], xn[RPT_MAX];
   int64_t rr[RPT_MAX];
 #pragma unroll
   for (int q = 0; q < RPT_MAX; ++q) {
-    rr[q] = rbase + (int64_t)q * 256 + t;
+    rr[q] = rbase + (int64_t)q * QT + t;
     vr[q] = 0.0; xn[q] = 0.0;
     if (q >= a.rpt || rr[q] >= a.h) { rr[q] = -1; continue; }
     const int64_t r = rr[q];
@@ -97,7 +113,6 @@ __global__ __launch_bounds__(256) void qr_col_kernel(Panel a, int j) {
   }
 
   const int jn = j + 1;      // column whose statistics this launch gathers
-  // value of column jn after reflector j, per owned row (multiplier of the statistics)
   if (jn < w) {
 #pragma unroll
     for (int q = 0; q < RPT_MAX; ++q) {
@@ -120,51 +135,80 @@ __global__ __launch_bounds__(256) void qr_col_kernel(Panel a, int j) {
       const bool below = (j >= 0 && r > j), pivrow = (j >= 0 && r == j);
       if (r < jn && !pivrow) continue;          // rows above the next pivot: untouched
       const double x = xn[q];
+      // all loads of the chunk first: a store to P between two loads would
+      // order them (the compiler cannot rule out aliasing), serialising the
+      // chunk into dependent round trips
+      double pv[CH];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) pv[cc] = (cb + cc < w) ? P[r + (int64_t)(cb + cc) * ld] : 0.0;
+      const double f = below ? tau * vr[q] : (pivrow ? tau : 0.0);
 #pragma unroll
       for (int cc = 0; cc < CH; ++cc) {
-        const int c = cb + cc;
-        if (c < w) {
-          double p = P[r + (int64_t)c * ld];
-          if (below) p -= tau * vr[q] * sh_w[c];
-          else if (pivrow) p -= tau * sh_w[c];
-          if (below || pivrow) P[r + (int64_t)c * ld] = p;
-          if (r > jn) acc[cc] += x * p;
-          if (r == jn) piv_out[c] = p;
+        if (cb + cc < w) {
+          pv[cc] -= f * sh_w[cb + cc];
+          if (r > jn) acc[cc] += x * pv[cc];
         }
       }
-    }
+      if (below || pivrow) {
 #pragma unroll
-    for (int cc = 0; cc < CH; ++cc) {
-      const double v = wave_sum(acc[cc]);
-      if (lane == 0) sh_red[wv][cc] = v;
+        for (int cc = 0; cc < CH; ++cc)
+          if (cb + cc < w) P[r + (int64_t)(cb + cc) * ld] = pv[cc];
+      }
+      if (r == jn) {
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc)
+          if (cb + cc < w) piv_out[cb + cc] = pv[cc];
+      }
+    }
+    // workgroup sums of the CH column statistics: transpose through LDS,
+    // 8 segments of 32 threads, then the 8 segment sums.
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) sh_acc[t][cc] = acc[cc];
+    __syncthreads();
+    {
+      const int cc = t & (CH - 1), seg = t / CH;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < CH; ++i) s4[i & 3] += sh_acc[seg * CH + i][cc];
+      sh_seg[seg][cc] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     __syncthreads();
-    if (t < CH && cb + t < w)
-      part_out[(int64_t)g * QB + cb + t] = sh_red[0][t] + sh_red[1][t] + sh_red[2][t] + sh_red[3][t];
+    if (t < CH && cb + t < w) {
+      double s = 0.0;
+#pragma unroll
+      for (int seg = 0; seg < QT / CH; ++seg) s += sh_seg[seg][t];
+      part_out[(int64_t)g * QB + cb + t] = s;
+    }
     __syncthreads();
   }
 }
 
-// T (w x w, upper) of the compact WY form from G = V^T V and tau.
-__global__ __launch_bounds__(256) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
-                                                      double* T, int64_t ldt, int w) {
-  __shared__ double S[QB][QB + 1];
+// T (w x w, upper) of the compact WY form from G = V^T V and tau:
+// T(j,j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One LDS array
+// holds G above the diagonal and T^T on and below it.  Thread i owns row i of
+// T and runs over j (rows are independent).
+__global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
+                                                     double* T, int64_t ldt, int w) {
+  __shared__ double L[QB][QB + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < QB * QB; e += 256) S[e % QB][e / QB] = 0.0;
-  __syncthreads();
-  for (int j = 0; j < w; ++j) {
-    const double tj = tau[j];
-    if (t < j) {
-      double acc = 0.0;
-      for (int k = t; k < j; ++k) acc += S[t][k] * G[k + (int64_t)j * ldg];
-      S[t][j] = -tj * acc;
-    }
-    if (t == 0) S[j][j] = tj;
-    __syncthreads();
-  }
-  for (int e = t; e < QB * QB; e += 256) {
+  for (int e = t; e < QB * QB; e += QB) {
     const int r = e % QB, c = e / QB;
-    if (r < w && c < w) T[r + (int64_t)c * ldt] = S[r][c];
+    L[r][c] = (r < c && r < w && c < w) ? G[r + (int64_t)c * ldg] : 0.0;
+  }
+  __syncthreads();
+  if (t < w) {
+    const int i = t;
+    L[i][i] = tau[i];                       // T(i,i), stored at L[i][i]
+    for (int j = i + 1; j < w; ++j) {
+      double acc = 0.0;
+      for (int k = i; k < j; ++k) acc += L[k][i] * L[k][j];   // T(i,k) = L[k][i]; G(k,j) = L[k][j]
+      L[j][i] = -tau[j] * acc;
+    }
+  }
+  __syncthreads();
+  for (int e = t; e < QB * QB; e += QB) {
+    const int r = e % QB, c = e / QB;
+    if (r < w && c < w) T[r + (int64_t)c * ldt] = (r <= c) ? L[c][r] : 0.0;
   }
 }
 
@@ -179,14 +223,14 @@ __global__ void eye_cols_kernel(double* Q, int64_t m, int64_t q, int64_t ldq, in
 int64_t qr_scratch_doubles(int64_t m, int64_t n) {
   (void)m;
   const int64_t nn = n > 1 ? n : 1;
-  return 2 * 256 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256;
+  return 2 * 64 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256;
 }
 
 QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
   (void)m;
   const int64_t nn = n > 1 ? n : 1;
   QrScratch s;
-  s.part = w; w += 2 * 256 * QB;
+  s.part = w; w += 2 * 64 * QB;
   s.piv = w; w += 2 * QB;
   s.G = w; w += QB * QB;
   s.W1 = w; w += QB * nn;
@@ -203,12 +247,11 @@ void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Ta
     Panel p;
     p.P = A + c0 + c0 * lda; p.ld = lda; p.h = h; p.w = w;
     p.tau = tau + c0; p.part = sc.part; p.piv = sc.piv;
-    p.rpt = (int)cdiv(h, 256 * 256);
-    if (p.rpt > RPT_MAX) p.rpt = RPT_MAX;
-    p.nwg = (int)cdiv(h, 256 * p.rpt);
-    if (p.nwg > 256) throw HipError{hipErrorInvalidValue};
+    p.rpt = (int)cdiv(h, (int64_t)QT * NWG_MAX);
+    if (p.rpt > RPT_MAX) throw HipError{hipErrorInvalidValue};   // h > 131072 rows
+    p.nwg = (int)cdiv(h, (int64_t)QT * p.rpt);
     for (int j = -1; j < w; ++j) {
-      qr_col_kernel<<<p.nwg, 256, 0, s>>>(p, j);
+      qr_col_kernel<<<p.nwg, QT, 0, s>>>(p, j);
       QDWHP_LAUNCH_CHECK();
     }
     // G = V^T V, then T
@@ -218,7 +261,7 @@ void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Ta
     g.ws = sc.ws; g.ws_doubles = sc.ws_doubles;
     dgemm(g, s);
     double* T = Tall + (c0 / QB) * QB * QB;
-    build_t_kernel<<<1, 256, 0, s>>>(sc.G, QB, tau + c0, T, QB, w);
+    build_t_kernel<<<1, QB, 0, s>>>(sc.G, QB, tau + c0, T, QB, w);
     QDWHP_LAUNCH_CHECK();
     const int64_t nc = n - c0 - w;
     if (nc > 0) {

@@ -97,9 +97,14 @@ struct StepBufs {
 // triangular products (W^{-1} upper: X W^{-1} only needs k <= column,
 // (.) W^{-T} only k >= column).  For symmetric X (EIG) only the upper tiles
 // of the result are formed and then mirrored.
+//
+// f32: the Gram matrix and both triangular products run on the FP32 matrix
+// cores (operands rounded to FP32, FP64 epilogue); the Cholesky-inversion
+// stays FP64.
 void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b, double c, bool sym,
-               const StepBufs& B, hipStream_t s) {
+               const StepBufs& B, hipStream_t s, bool f32 = false) {
   Gemm g;
+  g.f32 = f32;
   g.M = n; g.N = n; g.K = m; g.alpha = c; g.beta = 0.0; g.diag = 1.0;
   g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.Z; g.ldc = n;
   g.tiles = TILES_UPPER;
@@ -108,13 +113,33 @@ void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b
   const double* Wi = B.spd;
   double* T = B.spd + spd_inverse_doubles(n);
   Gemm t;
+  t.f32 = f32;
   t.M = m; t.N = n; t.K = n; t.A = X; t.lda = m; t.B = Wi; t.ldb = n; t.C = T; t.ldc = m;
   t.khi = KHI_COL;
   dgemm(t, s);
   Gemm u;
+  u.f32 = f32;
   u.M = m; u.N = n; u.K = n; u.alpha = a - b / c; u.beta = b / c;
   u.A = T; u.lda = m; u.B = Wi; u.ldb = n; u.tb = true; u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
   u.klo = KLO_COL;
+  if (sym) u.tiles = TILES_UPPER;
+  dgemm(u, s);
+  if (sym) mirror_upper(Xn, n, m, s);
+  std::swap(X, Xn);
+}
+
+// FP64 Newton-Schulz step X <- X (3I - X^T X)/2 (polish after mixed-precision
+// Cholesky steps: drives the singular values that the iteration mapped near 1
+// back to 1 to FP64 accuracy).  Needs ||X||_2 < sqrt(3).
+void ns_step(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, const StepBufs& B, hipStream_t s) {
+  Gemm g;
+  g.M = n; g.N = n; g.K = m; g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.Z; g.ldc = n;
+  g.tiles = TILES_UPPER;
+  dgemm(g, s);
+  mirror_upper(B.Z, n, n, s);
+  Gemm u;
+  u.M = m; u.N = n; u.K = n; u.alpha = -0.5; u.beta = 1.5; u.A = X; u.lda = m; u.B = B.Z; u.ldb = n;
+  u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
   if (sym) u.tiles = TILES_UPPER;
   dgemm(u, s);
   if (sym) mirror_upper(Xn, n, m, s);
@@ -305,9 +330,21 @@ extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fractio
       double* Xn = P.Xn;
       eig_x0(A, lda, X, n, n, (1.0 - sfix) / mu, tau, sgn, sfix, s);
       const StepBufs sb = step_bufs(P, n, n);
+      const bool mixed = (o.precision == QDWHP_MIXED_FP32);
+      double xbound = 1.0;
       for (const auto& st : sched) {
         if (st.kind == 1) qr_step(X, n, n, st.a, st.b, st.c, true, sb, s);
-        else chol_step(X, Xn, n, n, st.a, st.b, st.c, true, sb, s);
+        else chol_step(X, Xn, n, n, st.a, st.b, st.c, true, sb, s, mixed);
+        xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
+      }
+      if (mixed) {
+        // FP64 polish: Newton-Schulz while the unwanted side stays below
+        // sqrt(3) (where it converges), else Halley's (3,1,3) step in
+        // Cholesky form (monotone for any x)
+        for (int p = 0; p < o.polish_steps; ++p) {
+          if (xbound < 1.7) { ns_step(X, Xn, n, n, true, sb, s); xbound = std::max(1.0, 0.5 * xbound * (3.0 - xbound * xbound)); }
+          else { chol_step(X, Xn, n, n, 3.0, 1.0, 3.0, true, sb, s, false); xbound = std::max(1.0, dwh_map(xbound, 3.0, 1.0, 3.0)); }
+        }
       }
       ev.mark(2, s);
       // ---- projector (X + I)/2, QR, ind (Algorithm 1)
@@ -485,10 +522,13 @@ extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int
       double* Xn = P.Xn;
       scale_copy(A, lda, X, mm, mm, nn, 1.0 / alpha, tr, s);
       const StepBufs sb = step_bufs(P, mm, nn);
+      const bool mixed = (o.precision == QDWHP_MIXED_FP32);
       for (const auto& st : sched) {
         if (st.kind == 1) qr_step(X, mm, nn, st.a, st.b, st.c, false, sb, s);
-        else chol_step(X, Xn, mm, nn, st.a, st.b, st.c, false, sb, s);
+        else chol_step(X, Xn, mm, nn, st.a, st.b, st.c, false, sb, s, mixed);
       }
+      if (mixed)   // FP64 Newton-Schulz polish (singular values of X lie in [0, 1 + O(u_32)])
+        for (int p = 0; p < o.polish_steps; ++p) ns_step(X, Xn, mm, nn, false, sb, s);
       ev.mark(2, s);
       // ---- projector I - X^T X, QR, ind (Algorithm 2)
       Gemm gb;
