@@ -5,9 +5,9 @@
 // The index set is cut into blocks of JB = 16.  A sweep visits every pair of
 // blocks once in round-robin (circle) order; in each step the Nb/2 disjoint
 // pairs are independent:
-//   * two-sided (symmetric H): the 32x32 diagonal sub-problem of each pair is
-//     diagonalised in LDS by cyclic Jacobi (16 disjoint rotations per
-//     round), giving an orthogonal J; then H <- J^T H J tile by tile (tile
+//   * two-sided (symmetric H): the 32x32 diagonal sub-problem of each pair
+//     gets one cyclic Jacobi sweep in LDS (16 disjoint rotations per round),
+//     giving an orthogonal J; then H <- J^T H J tile by tile (tile
 //     (P,Q) becomes J_P^T H_PQ J_Q) and V <- V J;
 //   * one-sided (R): each pair forms the Gram matrix of its 32 columns,
 //     diagonalises it the same way and rotates the columns of R and V by J,
@@ -23,6 +23,13 @@
 
 namespace qdwhp {
 namespace {
+
+// Inner sweeps per pair sub-problem.  One sweep per visit is enough: the
+// outer sweeps converge in the same number of steps as when every 2JB x 2JB
+// sub-problem is diagonalised to convergence, at a fraction of the cost.
+#ifndef QDWHP_JACOBI_INNER
+#define QDWHP_JACOBI_INNER 1
+#endif
 
 constexpr int P2 = 2 * JB;     // size of a pair sub-problem
 constexpr int LDM = P2 + 1;
@@ -225,7 +232,7 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
     atomic_max_nonneg(a.offmax + a.sweep, m);
   }
-  inner_jacobi(M, J, a.tol, false, 30);
+  inner_jacobi(M, J, a.tol, false, QDWHP_JACOBI_INNER);
   // off-diagonal part of the rotated sub-problem goes back now, freeing M
   for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
@@ -378,7 +385,7 @@ __global__ __launch_bounds__(NT) void svj_pair_kernel(SvjArgs a) {
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
     atomic_max_nonneg(a.offmax + a.sweep, m);
   }
-  inner_jacobi(M, J, a.tol, true, 30);
+  inner_jacobi(M, J, a.tol, true, QDWHP_JACOBI_INNER);
   orthonormalize(J, M, X);
   // rotate columns of R and V (chunks of P2 rows; M is scratch for the product)
   for (int pass = 0; pass < 2; ++pass) {

@@ -13,7 +13,6 @@
 #include <vector>
 
 #include "common.h"
-#include "jacobi.h"
 
 namespace qdwhp {
 
@@ -26,7 +25,8 @@ struct LanczosOp {
 
 struct LanczosResult {
   std::vector<double> nodes, weights, resid, alpha, beta;
-  int nv = 0, m = 0; int64_t n = 0; int sweeps = 0;
+  int nv = 0, m = 0; int64_t n = 0;
+  int sweeps = 0;   // -1 if a tridiagonal eigenproblem did not converge
 };
 
 int64_t lanczos_doubles(int64_t n, int64_t rows_op, int nv, int m);

@@ -124,41 +124,111 @@ __global__ __launch_bounds__(LZ_T) void normalize_kernel(const double* W, int64_
   if (r < n) Qn[r + run * qstride] = (nrm > 0.0) ? W[r + run * wstride] / nrm : 0.0;
 }
 
-// Block-diagonal matrix of the runs' tridiagonals: T (nv*m square).
-__global__ void tridiag_kernel(const double* alpha, const double* beta, int nv, int m, double* T) {
-  const int N = nv * m;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)N * N) return;
-  const int i = (int)(e % N), j = (int)(e / N);
-  double v = 0.0;
-  if (i / m == j / m) {
-    const int run = i / m, a = i % m, b = j % m;
-    if (a == b) v = alpha[run * m + a];
-    else if (a == b + 1) v = beta[run * m + b];
-    else if (b == a + 1) v = beta[run * m + a];
-  }
-  T[i + (int64_t)j * N] = v;
+// Step bookkeeping on the device (no host round trip per step): alpha_j =
+// q_j^T w (from the first CGS pass), beta_j = ||w||.  A run whose beta_j falls
+// below 1e-10 times its running |T| bound has found an invariant subspace:
+// beta_j is set to 0 (the tridiagonal decouples) and the run is flagged for a
+// restart with a fresh random vector.  The last step never restarts.
+__global__ void step_kernel(const double* dvec, const double* nrm, int nv, int m, int j,
+                            double* alpha, double* beta, double* amax, int* active) {
+  const int i = threadIdx.x;
+  if (i >= nv) return;
+  const double a = dvec[i * 128 + j];
+  alpha[i * m + j] = a;
+  const double am = fmax(amax[i], fabs(a) + (j > 0 ? beta[i * m + j - 1] : 0.0));
+  amax[i] = am;
+  const double b = nrm[i];
+  int act = 0;
+  if (j == m - 1) beta[i * m + j] = b;
+  else if (b <= 1e-10 * am) { beta[i * m + j] = 0.0; act = 1; }
+  else beta[i * m + j] = b;
+  active[i] = act;
 }
 
-// For each eigenpair (column c of W) of the block-diagonal T: the run holding
-// it, its quadrature weight (first component in that run)^2 and residual
-// bound |beta_m y_m|.
-__global__ void nodes_kernel(const double* W, int nv, int m, const double* beta, double* weight,
-                             double* resid) {
-  const int N = nv * m;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
-  int best = 0;
-  double bm = -1.0;
-  for (int run = 0; run < nv; ++run) {
-    double s = 0.0;
-    for (int a = 0; a < m; ++a) { const double v = W[run * m + a + (int64_t)c * N]; s += v * v; }
-    if (s > bm) { bm = s; best = run; }
+// Gaussian stream for each flagged run (grid.y = run): W_run <- stream nv + run*m + j.
+__global__ void restart_gaussian_kernel(double* W, int64_t n, uint64_t seed, int nv, int m, int j,
+                                        const int* active) {
+  const int run = blockIdx.y;
+  if (!active[run]) return;
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (2 * p >= n) return;
+  const uint64_t stream = (uint64_t)nv + (uint64_t)run * m + j;
+  uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), (uint32_t)stream, 0u};
+  philox10(c, seed);
+  const double sc = 1.1102230246251565e-16;
+  const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * sc;
+  const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * sc;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(6.283185307179586 * u2, &sn, &cs);
+  double* w = W + run * n;
+  w[2 * p] = rad * cs;
+  if (2 * p + 1 < n) w[2 * p + 1] = rad * sn;
+}
+
+// Eigenvalues of each run's m x m tridiagonal (diagonal alpha, off-diagonal
+// beta) by the implicit symmetric QR iteration with Wilkinson shift (Golub &
+// Van Loan, Matrix Computations, Sec. 8.3), one thread per run.  Only the
+// first and last rows of the eigenvector matrix are carried along: the
+// Gauss-quadrature weight of node i is (first component)^2 (Golub & Welsch)
+// and its Ritz residual is |beta_m| |last component|.
+__global__ void tridiag_eig_kernel(const double* alpha, const double* beta, int nv, int m,
+                                   double* scratch, double* theta, double* weight, double* resid,
+                                   int* fail) {
+  if (threadIdx.x == 0) *fail = 0;
+  __syncthreads();
+  const int run = blockIdx.x * blockDim.x + threadIdx.x;
+  if (run >= nv) return;
+  double* d = scratch + (int64_t)run * 4 * m;
+  double* e = d + m;
+  double* z0 = e + m;
+  double* zl = z0 + m;
+  for (int i = 0; i < m; ++i) {
+    d[i] = alpha[run * m + i];
+    e[i] = (i + 1 < m) ? beta[run * m + i] : 0.0;
+    z0[i] = (i == 0) ? 1.0 : 0.0;
+    zl[i] = (i == m - 1) ? 1.0 : 0.0;
   }
-  const double y0 = W[best * m + (int64_t)c * N];
-  const double ym = W[best * m + m - 1 + (int64_t)c * N];
-  weight[c] = y0 * y0;
-  resid[c] = fabs(beta[best * m + m - 1] * ym);
+  const double u = 1.1102230246251565e-16;
+  int hi = m - 1, steps = 0;
+  while (hi > 0) {
+    for (int i = 0; i < hi; ++i)
+      if (fabs(e[i]) <= u * (fabs(d[i]) + fabs(d[i + 1]))) e[i] = 0.0;
+    if (e[hi - 1] == 0.0) { --hi; continue; }
+    int lo = hi - 1;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    if (++steps > 40 * m) { *fail = 1; break; }
+    // Wilkinson shift from the trailing 2x2 of the unreduced block [lo, hi]
+    const double tb = e[hi - 1];
+    const double del = 0.5 * (d[hi - 1] - d[hi]);
+    const double den = del + (del >= 0.0 ? 1.0 : -1.0) * hypot(del, tb);
+    const double mu = d[hi] - tb * tb / den;
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      // rotation in the (k, k+1) plane that zeroes z against x
+      const double r = hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r > 0.0) { c = x / r; s = z / r; }
+      if (k > lo) e[k - 1] = r;
+      const double dk = d[k], dk1 = d[k + 1], ek = e[k];
+      d[k] = c * c * dk + 2.0 * c * s * ek + s * s * dk1;
+      d[k + 1] = s * s * dk - 2.0 * c * s * ek + c * c * dk1;
+      e[k] = (c * c - s * s) * ek + c * s * (dk1 - dk);
+      double bulge = 0.0;
+      if (k + 1 < hi) { bulge = s * e[k + 1]; e[k + 1] = c * e[k + 1]; }
+      const double a0 = z0[k], a1 = z0[k + 1];
+      z0[k] = c * a0 + s * a1; z0[k + 1] = -s * a0 + c * a1;
+      const double b0 = zl[k], b1 = zl[k + 1];
+      zl[k] = c * b0 + s * b1; zl[k + 1] = -s * b0 + c * b1;
+      x = e[k]; z = bulge;
+    }
+  }
+  const double bm = fabs(beta[run * m + m - 1]);
+  for (int i = 0; i < m; ++i) {
+    theta[run * m + i] = d[i];
+    weight[run * m + i] = z0[i] * z0[i];
+    resid[run * m + i] = bm * fabs(zl[i]);
+  }
 }
 
 }  // namespace
@@ -169,8 +239,8 @@ int64_t lanczos_doubles(int64_t n, int64_t rows_op, int nv, int m) {
   return n * (int64_t)(m + 1) * nv       // bases
          + 2 * n * nv + rows_op * nv      // w, spare, operator temp
          + 2 * nv * 128 * nchunk          // partials
-         + nv * 128 * 2 + 4 * (int64_t)nv * m  // d, alpha/beta
-         + N * N * 2 + syev_scratch_doubles(N) + 4 * N + 256;
+         + nv * 128 * 2 + 4 * (int64_t)nv * m  // d, alpha/beta, norms
+         + 4 * N + 3 * N + 2 * nv + 256;       // tridiagonal scratch, nodes, amax/flags
 }
 
 // Runs the Lanczos processes; `op` applies the operator to nv columns.
@@ -187,30 +257,29 @@ LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t se
   double* alpha = ws;             ws += (int64_t)nv * m;
   double* beta = ws;              ws += (int64_t)nv * m;
   double* nrm = ws;               ws += 2 * (int64_t)nv * m;
-  double* T = ws;                 ws += N * N;
-  double* Wt = ws;                ws += N * N;
-  double* js = ws;                ws += syev_scratch_doubles(N);
+  double* tscr = ws;              ws += 4 * N;
   double* theta = ws;             ws += N;
   double* weight = ws;            ws += N;
   double* resid = ws;             ws += N;
+  double* amax = ws;              ws += nv;
+  int* d_active = (int*)ws;       ws += nv;   // nv ints, then the failure flag
   const int64_t qs = n * (m + 1);
   const dim3 gdots((unsigned)nchunk, (unsigned)nv);
   const dim3 grow((unsigned)cdiv(n, LZ_T), (unsigned)nv);
+  const dim3 ggauss((unsigned)cdiv(cdiv(n, 2), 256), (unsigned)nv);
 
   // start vectors
   for (int i = 0; i < nv; ++i) {
     gaussian_kernel<<<(unsigned)cdiv(cdiv(n, 2), 256), 256, 0, s>>>(G + i * n, n, seed, (uint64_t)i);
     QDWHP_LAUNCH_CHECK();
   }
+  fill(amax, nv, 1, nv, 0.0, 0.0, s);
+  fill(beta, nv, m, nv, 0.0, 0.0, s);
   dots_kernel<<<gdots, LZ_T, 0, s>>>(G, n, n, G, n, 1, part, nchunk, nullptr);
   QDWHP_LAUNCH_CHECK();
   normalize_kernel<<<grow, LZ_T, 0, s>>>(G, n, Q, qs, n, part, nchunk, nullptr, nullptr);
   QDWHP_LAUNCH_CHECK();
 
-  std::vector<double> h_a((size_t)nv * m), h_b((size_t)nv * m, 0.0), h_nrm(nv);
-  std::vector<double> amax(nv, 0.0);
-  std::vector<int> h_active(nv);
-  int* d_active = (int*)(nrm + nv * (int64_t)m);   // spare room after nrm (nv ints)
   for (int j = 0; j < m; ++j) {
     // w = Op q_j for all runs (columns at stride qs)
     op.apply(Q + (int64_t)j * n, qs, Wv, n, tmp, s);
@@ -226,55 +295,46 @@ LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t se
     QDWHP_LAUNCH_CHECK();
     normalize_kernel<<<grow, LZ_T, 0, s>>>(Wv, n, Q + (int64_t)(j + 1) * n, qs, n, part, nchunk, nrm, nullptr);
     QDWHP_LAUNCH_CHECK();
-    std::vector<double> h_d((size_t)nv * 128);
-    QDWHP_HIP(hipMemcpyAsync(h_d.data(), dvec, sizeof(double) * nv * 128, hipMemcpyDeviceToHost, s));
-    QDWHP_HIP(hipMemcpyAsync(h_nrm.data(), nrm, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
-    QDWHP_HIP(hipStreamSynchronize(s));
-    bool restart = false;
-    for (int i = 0; i < nv; ++i) {
-      const double a = h_d[(size_t)i * 128 + j];
-      h_a[(size_t)i * m + j] = a;
-      amax[i] = std::max(amax[i], std::fabs(a) + (j > 0 ? h_b[(size_t)i * m + j - 1] : 0.0));
-      const double b = h_nrm[i];
-      h_active[i] = 0;
-      if (j == m - 1) { h_b[(size_t)i * m + j] = b; continue; }
-      if (b <= 1e-10 * amax[i]) { h_active[i] = 1; restart = true; h_b[(size_t)i * m + j] = 0.0; }
-      else h_b[(size_t)i * m + j] = b;
-    }
-    if (restart && j < m - 1) {
-      QDWHP_HIP(hipMemcpyAsync(d_active, h_active.data(), sizeof(int) * nv, hipMemcpyHostToDevice, s));
-      for (int i = 0; i < nv; ++i)
-        if (h_active[i]) {
-          gaussian_kernel<<<(unsigned)cdiv(cdiv(n, 2), 256), 256, 0, s>>>(
-              Wv + i * n, n, seed, (uint64_t)(nv + (int64_t)i * m + j));
-          QDWHP_LAUNCH_CHECK();
-        }
-      for (int pass = 0; pass < 2; ++pass) {
-        dots_kernel<<<gdots, LZ_T, 0, s>>>(Q, n, qs, Wv, n, j + 1, part, nchunk, d_active);
-        QDWHP_LAUNCH_CHECK();
-        sub_kernel<<<grow, LZ_T, 0, s>>>(Q, n, qs, Wv, n, j + 1, part, nchunk, nullptr, d_active);
-        QDWHP_LAUNCH_CHECK();
-      }
-      dots_kernel<<<gdots, LZ_T, 0, s>>>(Wv, n, n, Wv, n, 1, part, nchunk, d_active);
+    step_kernel<<<1, 64, 0, s>>>(dvec, nrm, nv, m, j, alpha, beta, amax, d_active);
+    QDWHP_LAUNCH_CHECK();
+    if (j == m - 1) break;
+    // restart of the flagged runs (the kernels return at once for the others)
+    restart_gaussian_kernel<<<ggauss, 256, 0, s>>>(Wv, n, seed, nv, m, j, d_active);
+    QDWHP_LAUNCH_CHECK();
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_kernel<<<gdots, LZ_T, 0, s>>>(Q, n, qs, Wv, n, j + 1, part, nchunk, d_active);
       QDWHP_LAUNCH_CHECK();
-      normalize_kernel<<<grow, LZ_T, 0, s>>>(Wv, n, Q + (int64_t)(j + 1) * n, qs, n, part, nchunk,
-                                             nullptr, d_active);
+      sub_kernel<<<grow, LZ_T, 0, s>>>(Q, n, qs, Wv, n, j + 1, part, nchunk, nullptr, d_active);
       QDWHP_LAUNCH_CHECK();
     }
+    dots_kernel<<<gdots, LZ_T, 0, s>>>(Wv, n, n, Wv, n, 1, part, nchunk, d_active);
+    QDWHP_LAUNCH_CHECK();
+    normalize_kernel<<<grow, LZ_T, 0, s>>>(Wv, n, Q + (int64_t)(j + 1) * n, qs, n, part, nchunk,
+                                           nullptr, d_active);
+    QDWHP_LAUNCH_CHECK();
   }
-  QDWHP_HIP(hipMemcpyAsync(alpha, h_a.data(), sizeof(double) * nv * m, hipMemcpyHostToDevice, s));
-  QDWHP_HIP(hipMemcpyAsync(beta, h_b.data(), sizeof(double) * nv * m, hipMemcpyHostToDevice, s));
-  tridiag_kernel<<<(unsigned)cdiv(N * N, 256), 256, 0, s>>>(alpha, beta, nv, m, T);
+  int* d_fail = d_active + nv;
+  tridiag_eig_kernel<<<1, 64, 0, s>>>(alpha, beta, nv, m, tscr, theta, weight, resid, d_fail);
   QDWHP_LAUNCH_CHECK();
-  LanczosResult res;
-  res.sweeps = syev(T, N, N, theta, Wt, N, js, s);
-  nodes_kernel<<<(unsigned)cdiv(N, 256), 256, 0, s>>>(Wt, nv, m, beta, weight, resid);
-  QDWHP_LAUNCH_CHECK();
-  res.nodes.resize(N); res.weights.resize(N); res.resid.resize(N);
-  QDWHP_HIP(hipMemcpyAsync(res.nodes.data(), theta, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-  QDWHP_HIP(hipMemcpyAsync(res.weights.data(), weight, sizeof(double) * N, hipMemcpyDeviceToHost, s));
-  QDWHP_HIP(hipMemcpyAsync(res.resid.data(), resid, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  std::vector<double> h_a((size_t)N), h_b((size_t)N), th(N), wt(N), rs(N);
+  int h_fail = 0;
+  QDWHP_HIP(hipMemcpyAsync(h_a.data(), alpha, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(h_b.data(), beta, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(th.data(), theta, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(wt.data(), weight, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(rs.data(), resid, sizeof(double) * N, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(&h_fail, d_fail, sizeof(int), hipMemcpyDeviceToHost, s));
   QDWHP_HIP(hipStreamSynchronize(s));
+  // nodes in descending order (ties by run-major index)
+  std::vector<int64_t> idx(N);
+  for (int64_t i = 0; i < N; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int64_t x, int64_t y) { return th[x] > th[y]; });
+  LanczosResult res;
+  res.sweeps = h_fail ? -1 : 0;
+  res.nodes.resize(N); res.weights.resize(N); res.resid.resize(N);
+  for (int64_t i = 0; i < N; ++i) {
+    res.nodes[i] = th[idx[i]]; res.weights[i] = wt[idx[i]]; res.resid[i] = rs[idx[i]];
+  }
   res.alpha = h_a; res.beta = h_b; res.nv = nv; res.m = m; res.n = n;
   return res;
 }

@@ -289,6 +289,7 @@ extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fractio
         dgemm(g, st);
       };
       lz = lanczos(op, n, nv, (int)msteps, o.seed, P.lz, s);
+      if (lz.sweeps < 0) return ret(QDWHP_ERR_NOCONV);
       lmax = -std::numeric_limits<double>::infinity();
       lmin = std::numeric_limits<double>::infinity();
       for (size_t i = 0; i < lz.nodes.size(); ++i) {
@@ -483,6 +484,7 @@ extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int
         dgemm(h, st);
       };
       lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
+      if (lz.sweeps < 0) return ret(QDWHP_ERR_NOCONV);
       lmax = -std::numeric_limits<double>::infinity();
       lmin = std::numeric_limits<double>::infinity();
       for (size_t i = 0; i < lz.nodes.size(); ++i) {
