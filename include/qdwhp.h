@@ -44,6 +44,7 @@ extern "C" {
 #define QDWHP_ERR_WORKSPACE      4  /* lwork smaller than the workspace query     */
 #define QDWHP_ERR_HIP            5  /* a HIP runtime call failed                  */
 #define QDWHP_ERR_NOCONV         6  /* small Jacobi solver did not converge       */
+#define QDWHP_PENDING          100  /* qdwhp_serve_poll: request not finished yet  */
 
 /* ---- selectors -------------------------------------------------------- */
 #define QDWHP_LARGEST   0   /* wanted = k largest eigenvalues               */
@@ -216,6 +217,100 @@ int qdwhp_syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t 
 size_t qdwhp_gesvj_workspace(int64_t n);
 int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double* V, int64_t ldv,
                 void* work, size_t lwork, void* stream, int* sweeps);
+
+/* ---- ragged batches ---------------------------------------------------- */
+#define QDWHP_PROBLEM_EIG  0
+#define QDWHP_PROBLEM_SVD  1
+
+/*
+ * One independent problem: the arguments of qdwhp_eig (type EIG: A n x n,
+ * fraction, which, w, V) or of qdwhp_svd (type SVD: A m x n, k, w = S, U, V).
+ * Fields a type does not use are ignored.  Device pointers, column-major.
+ */
+typedef struct {
+  int type;                  /* QDWHP_PROBLEM_EIG or QDWHP_PROBLEM_SVD                 */
+  int which;                 /* EIG: QDWHP_LARGEST / QDWHP_SMALLEST                    */
+  int64_t m, n;              /* SVD: m x n; EIG: n x n (m ignored)                     */
+  const double* A; int64_t lda;
+  double fraction;           /* EIG: k = floor(fraction n + 1/2), clamped to [1, n]     */
+  int64_t k;                 /* SVD: number of wanted triplets                          */
+  double* w;                 /* EIG eigenvalues / SVD singular values, length k         */
+  double* U; int64_t ldu;    /* SVD left singular vectors (m x k); unused for EIG       */
+  double* V; int64_t ldv;    /* EIG eigenvectors / SVD right singular vectors (n x k)   */
+} qdwhp_problem;
+
+/* Workspace bytes of one problem (qdwhp_eig_workspace / qdwhp_svd_workspace
+ * of its type); 0 for an invalid type. */
+size_t qdwhp_problem_workspace(const qdwhp_problem* p, const qdwhp_opts* opts);
+
+/*
+ * Solves `count` independent problems of uneven sizes (Algorithms 1 and 2
+ * applied to each).  Instances run concurrently on `lanes` streams driven by
+ * host threads (0: the tuned default, "batch.lanes"); each uses its own slice
+ * of `work`.  The final products V = Q2 W of all instances run as one
+ * persistent ragged GEMM launch on `stream`.  Every instance's results are
+ * bitwise identical to a standalone qdwhp_eig / qdwhp_svd call with the same
+ * options.  infos[i] / status[i] (optional, host arrays of `count`) receive
+ * each instance's report and status; the return value is 0 if all succeeded,
+ * else the first failing instance's status (or a negative argument index).
+ * Synchronises `stream` like the single-problem calls; lanes start after the
+ * work already queued on `stream`.
+ */
+size_t qdwhp_batched_workspace(int count, const qdwhp_problem* probs, const qdwhp_opts* opts);
+int qdwhp_batched(int count, const qdwhp_problem* probs, void* work, size_t lwork,
+                  const qdwhp_opts* opts, int lanes, void* stream, qdwhp_info* infos,
+                  int* status);
+
+/*
+ * Persistent ragged GEMM: C_i = alpha_i op(A_i) op(B_i) + beta_i C_i for
+ * i < count in one launch (shared transposes; m, n, k, alpha, A, lda, B, ldb,
+ * beta, C, ldc are host arrays of `count` entries holding sizes, scalars and
+ * device pointers).  Tiles of all problems form one list that a fixed grid
+ * walks; each tile is computed exactly as by qdwhp_dgemm.  work: device
+ * memory of qdwhp_dgemm_grouped_workspace(count) bytes for the descriptor
+ * table.  Leading dimensions must be below 2^21.
+ */
+size_t qdwhp_dgemm_grouped_workspace(int count);
+int qdwhp_dgemm_grouped(int count, int transa, int transb, const int64_t* m, const int64_t* n,
+                        const int64_t* k, const double* alpha, const double* const* A,
+                        const int64_t* lda, const double* const* B, const int64_t* ldb,
+                        const double* beta, double* const* C, const int64_t* ldc,
+                        void* work, size_t lwork, void* stream);
+
+/* ---- continuous-batching server --------------------------------------- */
+/*
+ * A server owns one device arena of `arena_bytes` (its only allocation, made
+ * here) and `lanes` worker threads with their own streams (0: the tuned
+ * default, "serve.lanes").  submit() queues a problem (the descriptor is
+ * copied; its buffers must stay valid until the request finishes) and
+ * returns a ticket.  Requests are admitted in FIFO order when a lane is idle
+ * and the request's workspace fits in a free range of the arena; admitted
+ * requests run concurrently.  A request larger than the arena finishes at
+ * once with QDWHP_ERR_WORKSPACE.  poll() returns QDWHP_PENDING while the
+ * request runs (wait = 0) or blocks until it finishes (wait != 0); a
+ * finished request returns its status, fills info, the latency from submit
+ * to results ready and the time it queued (ms, host clock), and its ticket
+ * is released.  destroy() finishes every queued request, then frees the
+ * arena.  Results equal those of a standalone call bitwise.
+ */
+typedef struct qdwhp_server qdwhp_server;
+int qdwhp_serve_create(size_t arena_bytes, int lanes, const qdwhp_opts* opts, qdwhp_server** srv);
+int qdwhp_serve_submit(qdwhp_server* srv, const qdwhp_problem* p, int64_t* ticket);
+int qdwhp_serve_poll(qdwhp_server* srv, int64_t ticket, int wait, qdwhp_info* info,
+                     double* latency_ms, double* queue_ms);
+int qdwhp_serve_destroy(qdwhp_server* srv);
+
+/* ---- tuning table ------------------------------------------------------ */
+/*
+ * Named integer parameters read by launch-shape decisions, written by the
+ * autotuner (or by hand).  Keys: "gemm.small_tiles" (a GEMM whose 128x128
+ * tile count is below this value runs with 64x64 tiles; default 96),
+ * "batch.lanes" (default 8), "serve.lanes" (default 8).  Unset keys keep
+ * their defaults.  Values apply to calls made after they are set.
+ */
+int qdwhp_tune_set(const char* key, int64_t value);
+int64_t qdwhp_tune_get(const char* key, int64_t fallback);
+void qdwhp_tune_clear(void);
 
 /*
  * Kernel-level measurement: between qdwhp_profile_begin and

@@ -57,7 +57,23 @@ class Info(ctypes.Structure):
         return d
 
 
+class Problem(ctypes.Structure):
+    _fields_ = [("type", ctypes.c_int), ("which", ctypes.c_int),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("fraction", ctypes.c_double), ("k", ctypes.c_int64),
+                ("w", ctypes.c_void_p), ("U", ctypes.c_void_p), ("ldu", ctypes.c_int64),
+                ("V", ctypes.c_void_p), ("ldv", ctypes.c_int64)]
+
+
+PROBLEM_EIG, PROBLEM_SVD = 0, 1
+PENDING = 100
+TUNING_PATH = os.path.join(_PKG, "tuning_gfx950.json")
+
 _P, _I64, _D, _I, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int, ctypes.c_size_t
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_PI64 = ctypes.POINTER(ctypes.c_int64)
+_PD = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
     "qdwhp_opts_default": (None, [ctypes.POINTER(Opts)]),
     "qdwhp_strerror": (ctypes.c_char_p, [_I]),
@@ -77,6 +93,20 @@ _SIGS = {
     "qdwhp_syev": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
     "qdwhp_gesvj_workspace": (_SZ, [_I64]),
     "qdwhp_gesvj": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
+    "qdwhp_problem_workspace": (_SZ, [ctypes.POINTER(Problem), ctypes.POINTER(Opts)]),
+    "qdwhp_batched_workspace": (_SZ, [_I, ctypes.POINTER(Problem), ctypes.POINTER(Opts)]),
+    "qdwhp_batched": (_I, [_I, ctypes.POINTER(Problem), _P, _SZ, ctypes.POINTER(Opts), _I, _P,
+                           ctypes.POINTER(Info), ctypes.POINTER(_I)]),
+    "qdwhp_dgemm_grouped_workspace": (_SZ, [_I]),
+    "qdwhp_dgemm_grouped": (_I, [_I, _I, _I, _PI64, _PI64, _PI64, _PD, _PP, _PI64, _PP, _PI64, _PD,
+                                 _PP, _PI64, _P, _SZ, _P]),
+    "qdwhp_serve_create": (_I, [_SZ, _I, ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_void_p)]),
+    "qdwhp_serve_submit": (_I, [_P, ctypes.POINTER(Problem), _PI64]),
+    "qdwhp_serve_poll": (_I, [_P, _I64, _I, ctypes.POINTER(Info), _PD, _PD]),
+    "qdwhp_serve_destroy": (_I, [_P]),
+    "qdwhp_tune_set": (_I, [ctypes.c_char_p, _I64]),
+    "qdwhp_tune_get": (_I64, [ctypes.c_char_p, _I64]),
+    "qdwhp_tune_clear": (None, []),
     "qdwhp_profile_begin": (None, []),
     "qdwhp_profile_end": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }
@@ -95,7 +125,28 @@ def lib():
             fn.restype = res
             fn.argtypes = args
         _lib = L
+        load_tuning()
     return _lib
+
+
+def load_tuning(path=TUNING_PATH):
+    """Apply the autotuner's table (JSON {"params": {key: int}}) if present."""
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        params = json.load(f).get("params", {})
+    for key, v in params.items():
+        tune_set(key, int(v))
+    return params
+
+
+def tune_set(key, value):
+    _check(lib().qdwhp_tune_set(key.encode(), int(value)), "qdwhp_tune_set")
+
+
+def tune_get(key, fallback=-1):
+    return lib().qdwhp_tune_get(key.encode(), int(fallback))
 
 
 def exported_symbols():
@@ -284,3 +335,144 @@ def profile_end():
     f, t, n = ctypes.c_double(0), ctypes.c_double(0), ctypes.c_int64(0)
     _check(lib().qdwhp_profile_end(ctypes.byref(f), ctypes.byref(t), ctypes.byref(n)), "qdwhp_profile_end")
     return f.value, t.value, n.value
+
+
+# ---------------------------------------------------------------- batches
+def _problem(torch, spec):
+    """(Problem, keep-alive list, outputs) for one spec dict:
+    {"type": "eig", "A": (n,n) symmetric, "fraction": f, "which": "largest"}
+    or {"type": "svd", "A": (m,n), "k": k}."""
+    A = spec["A"]
+    assert A.dtype == torch.float64 and A.is_cuda
+    p = Problem()
+    if spec["type"] == "eig":
+        n = A.shape[0]
+        f = float(spec["fraction"])
+        k = min(n, max(1, int(math.floor(f * n + 0.5))))
+        Ac = A.contiguous()
+        w = torch.empty(k, dtype=torch.float64, device=A.device)
+        Vb = torch.empty((k, n), dtype=torch.float64, device=A.device)
+        p.type, p.which, p.m, p.n = PROBLEM_EIG, LARGEST if spec.get("which", "largest") == "largest" else SMALLEST, n, n
+        p.A, p.lda, p.fraction = Ac.data_ptr(), n, f
+        p.w, p.V, p.ldv = w.data_ptr(), Vb.data_ptr(), n
+        return p, [Ac, w, Vb], ("eig", w, Vb)
+    m, n = A.shape
+    k = int(spec["k"])
+    Ac = A.t().contiguous()
+    S = torch.empty(k, dtype=torch.float64, device=A.device)
+    Ub = torch.empty((k, m), dtype=torch.float64, device=A.device)
+    Vb = torch.empty((k, n), dtype=torch.float64, device=A.device)
+    p.type, p.m, p.n, p.A, p.lda, p.k = PROBLEM_SVD, m, n, Ac.data_ptr(), m, k
+    p.w, p.U, p.ldu, p.V, p.ldv = S.data_ptr(), Ub.data_ptr(), m, Vb.data_ptr(), n
+    return p, [Ac, S, Ub, Vb], ("svd", S, Ub, Vb)
+
+
+def _result(out):
+    if out[0] == "eig":
+        return out[1], out[2].t()
+    return out[2].t(), out[1], out[3].t()
+
+
+def batched(specs, lanes=0, opts=None, return_info=False):
+    """Solve a ragged list of problems (see _problem for the spec dicts) with
+    qdwhp_batched.  Returns a list of per-problem results ((w, V) for EIG,
+    (U, S, V) for SVD) [+ list of info dicts]; raises if any failed."""
+    import torch
+    o = opts if opts is not None else default_opts()
+    count = len(specs)
+    probs = (Problem * count)()
+    keep, outs = [], []
+    for i, sp in enumerate(specs):
+        p, kp, out = _problem(torch, sp)
+        probs[i] = p
+        keep += kp
+        outs.append(out)
+    dev = specs[0]["A"].device
+    nbytes = lib().qdwhp_batched_workspace(count, probs, ctypes.byref(o))
+    ws = _workspace(torch, nbytes, dev)
+    infos = (Info * count)()
+    stat = (ctypes.c_int * count)()
+    st = lib().qdwhp_batched(count, probs, _ptr(ws), nbytes, ctypes.byref(o), int(lanes), _stream(torch),
+                             infos, stat)
+    _check(st, "qdwhp_batched")
+    res = [_result(out) for out in outs]
+    return (res, [infos[i].as_dict() for i in range(count)]) if return_info else res
+
+
+def dgemm_grouped(As, Bs, Cs, alphas=None, betas=None, transa=False, transb=False):
+    """C_i = alpha_i op(A_i) op(B_i) + beta_i C_i for all i in one launch, on
+    column-major buffers (contiguous (cols, rows) tensors, as for dgemm)."""
+    import torch
+    cnt = len(As)
+    alphas = alphas or [1.0] * cnt
+    betas = betas or [0.0] * cnt
+    M, N, K, LA, LB, LC = [], [], [], [], [], []
+    for A, B, C in zip(As, Bs, Cs):
+        ka, ma = A.shape
+        kb, mb = B.shape
+        m, k = (ka, ma) if transa else (ma, ka)
+        n = kb if not transb else mb
+        M.append(m); N.append(n); K.append(k)
+        LA.append(max(1, ma)); LB.append(max(1, mb)); LC.append(max(1, C.shape[1]))
+    arr = lambda t, v: (t * cnt)(*v)
+    ptrs = lambda ts: (ctypes.c_void_p * cnt)(*[t.data_ptr() for t in ts])
+    nbytes = lib().qdwhp_dgemm_grouped_workspace(cnt)
+    ws = _workspace(torch, nbytes, As[0].device)
+    st = lib().qdwhp_dgemm_grouped(cnt, int(transa), int(transb), arr(ctypes.c_int64, M), arr(ctypes.c_int64, N),
+                                   arr(ctypes.c_int64, K), arr(ctypes.c_double, alphas), ptrs(As),
+                                   arr(ctypes.c_int64, LA), ptrs(Bs), arr(ctypes.c_int64, LB),
+                                   arr(ctypes.c_double, betas), ptrs(Cs), arr(ctypes.c_int64, LC),
+                                   _ptr(ws), nbytes, _stream(torch))
+    _check(st, "qdwhp_dgemm_grouped")
+    return Cs
+
+
+class Server:
+    """Continuous-batching server (qdwhp_serve_*): requests are admitted by
+    HBM footprint into a device arena and run concurrently on `lanes`
+    streams.  Inputs must not be modified until their request finishes."""
+
+    def __init__(self, arena_bytes, lanes=0, opts=None):
+        import torch
+        self._torch = torch
+        self.opts = opts if opts is not None else default_opts()
+        h = ctypes.c_void_p()
+        _check(lib().qdwhp_serve_create(int(arena_bytes), int(lanes), ctypes.byref(self.opts), ctypes.byref(h)),
+               "qdwhp_serve_create")
+        self._h = h
+        self._live = {}
+
+    def submit(self, spec):
+        """Queue one problem (spec dict as for batched); returns a ticket."""
+        torch = self._torch
+        p, keep, out = _problem(torch, spec)
+        torch.cuda.current_stream().synchronize()   # inputs (and their copies) made on torch's stream are ready
+        t = ctypes.c_int64(0)
+        _check(lib().qdwhp_serve_submit(self._h, ctypes.byref(p), ctypes.byref(t)), "qdwhp_serve_submit")
+        self._live[t.value] = (keep, out)
+        return t.value
+
+    def poll(self, ticket, wait=True):
+        """None while pending (wait=False); else (result, info dict, latency_ms,
+        queue_ms).  Raises if the request failed."""
+        info = Info()
+        lat, q = ctypes.c_double(0), ctypes.c_double(0)
+        st = lib().qdwhp_serve_poll(self._h, int(ticket), int(bool(wait)), ctypes.byref(info),
+                                    ctypes.byref(lat), ctypes.byref(q))
+        if st == PENDING:
+            return None
+        keep, out = self._live.pop(ticket)
+        _check(st, "qdwhp_serve request")
+        return _result(out), info.as_dict(), lat.value, q.value
+
+    def close(self):
+        if self._h:
+            _check(lib().qdwhp_serve_destroy(self._h), "qdwhp_serve_destroy")
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -23,6 +23,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "drivers.h"
 
 namespace qdwhp {
 namespace {
@@ -82,21 +83,20 @@ __device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, in
   *tn = in / gm;
 }
 
+// One 128x128 output tile (tm, tn) of problem g; zi is the batch index, or
+// the K share when g.splitk > 1.  As / Bs are the workgroup's LDS buffers.
 template <bool TA, bool TB, bool F32>
-__global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
+__device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn, int64_t zi,
+                                          typename MfmaT<F32>::elem (*As)[BK * SA],
+                                          typename MfmaT<F32>::elem (*Bs)[BK * SB]) {
   typedef typename MfmaT<F32>::elem E;
   typedef typename MfmaT<F32>::acc ACC;
-  __shared__ E As[2][BK * SA];
-  __shared__ E Bs[2][BK * SB];
 
   const int tid = threadIdx.x;
-  const bool upper = (g.tiles == TILES_UPPER);
-  int64_t tm, tn;
-  tile_of(blockIdx.x, gx, gy, upper, &tm, &tn);
   const int64_t row0 = tm * BM;
   const int64_t col0 = tn * BN;
   const bool split = g.splitk > 1;
-  const int64_t bz = split ? 0 : blockIdx.z;
+  const int64_t bz = split ? 0 : zi;
   const double* __restrict__ A = g.A + bz * g.sA;
   const double* __restrict__ B = g.B + bz * g.sB;
   double* C = g.C + bz * g.sC;
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t
   if (khi > g.K) khi = g.K;
   if (split) {   // this workgroup's share of K, in whole BK slices
     const int64_t kc = ((g.K + g.splitk - 1) / g.splitk + BK - 1) / BK * BK;
-    const int64_t z = blockIdx.z;
+    const int64_t z = zi;
     if (klo < z * kc) klo = z * kc;
     if (khi > (z + 1) * kc) khi = (z + 1) * kc;
   }
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t
   };
   const double alpha = g.alpha, beta = g.beta, dg = g.diag;
   if (split) {   // raw partial product of this K share
-    double* P = g.ws + (int64_t)blockIdx.z * M * N;
+    double* P = g.ws + zi * M * N;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -290,6 +290,60 @@ __global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t
           *p = v;
         }
       }
+}
+
+template <bool TA, bool TB, bool F32>
+__global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
+  __shared__ typename MfmaT<F32>::elem As[2][BK * SA];
+  __shared__ typename MfmaT<F32>::elem Bs[2][BK * SB];
+  int64_t tm, tn;
+  tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, &tm, &tn);
+  gemm_tile<TA, TB, F32>(g, tm, tn, blockIdx.z, As, Bs);
+}
+
+// Persistent launch over a ragged list of FP64 problems (same transposes):
+// tile t of the concatenated tile list belongs to the problem p with
+// first[p] <= t < first[p + 1]; its tiles are numbered column by column.
+// Each tile is computed exactly as by dgemm_kernel.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256, 2) void dgemm_grouped_kernel(const GroupedDesc* descs, const int64_t* first,
+                                                               int count) {
+  __shared__ double As[2][BK * SA];
+  __shared__ double Bs[2][BK * SB];
+  const int64_t total = first[count];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) / 2;
+      if (first[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    const GroupedDesc d = descs[lo];
+    Gemm g;
+    g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
+    g.A = d.A; g.lda = d.lda; g.ta = TA; g.B = d.B; g.ldb = d.ldb; g.tb = TB; g.C = d.C; g.ldc = d.ldc;
+    const int64_t local = t - first[lo];
+    const int64_t gx = (g.M + BM - 1) / BM;
+    gemm_tile<TA, TB, false>(g, local % gx, local / gx, 0, As, Bs);
+    __syncthreads();
+  }
+}
+
+// The descriptor table travels in kernel arguments (no host staging buffer
+// whose lifetime would outlast the call): DESC_CHUNK entries per launch.
+constexpr int DESC_CHUNK = 24;
+struct DescChunk {
+  GroupedDesc d[DESC_CHUNK];
+  int64_t first[DESC_CHUNK + 1];
+  int count, base;
+};
+
+__global__ void desc_write_kernel(GroupedDesc* table, int64_t* first, DescChunk c, int total_count) {
+  const int i = threadIdx.x;
+  if (i < c.count) {
+    table[c.base + i] = c.d[i];
+    first[c.base + i] = c.first[i];
+  }
+  if (i == 0 && c.base + c.count == total_count) first[total_count] = c.first[c.count];
 }
 
 // C = alpha * sum_z P_z + beta * Cin (+ diag), summed in a fixed order.
@@ -404,6 +458,48 @@ void dgemm(const Gemm& g0, hipStream_t s) {
     QDWHP_LAUNCH_CHECK();
   }
   if (prof) prof_end_launch(s, tok, g0.f32 ? 0.0 : gemm_flops(g0));
+}
+
+size_t grouped_table_bytes(int count) {
+  const size_t d = ((size_t)(count > 0 ? count : 1) * sizeof(GroupedDesc) + 255) / 256 * 256;
+  return d + ((size_t)(count + 1) * sizeof(int64_t) + 255) / 256 * 256;
+}
+
+void dgemm_grouped(const GroupedDesc* descs, int count, bool ta, bool tb, void* table, hipStream_t s) {
+  if (count <= 0) return;
+  GroupedDesc* dt = (GroupedDesc*)table;
+  int64_t* first = (int64_t*)((char*)table + ((size_t)count * sizeof(GroupedDesc) + 255) / 256 * 256);
+  int64_t run = 0;
+  for (int base = 0; base < count; base += DESC_CHUNK) {
+    DescChunk c;
+    c.base = base;
+    c.count = std::min(DESC_CHUNK, count - base);
+    for (int i = 0; i < c.count; ++i) {
+      const GroupedDesc& d = descs[base + i];
+      if (d.lda >= (int64_t(1) << 21) || d.ldb >= (int64_t(1) << 21)) throw HipError{hipErrorInvalidValue};
+      c.d[i] = d;
+      c.first[i] = run;
+      if (d.M > 0 && d.N > 0) run += cdiv(d.M, BM) * cdiv(d.N, BN);
+    }
+    c.first[c.count] = run;
+    desc_write_kernel<<<1, 64, 0, s>>>(dt, first, c, count);
+    QDWHP_LAUNCH_CHECK();
+  }
+  if (run == 0) return;
+  void* tok = nullptr;
+  const bool prof = prof_active();
+  if (prof) prof_begin_launch(s, &tok);
+  const unsigned grid = (unsigned)std::min<int64_t>(run, 512);
+  if (!ta && !tb) dgemm_grouped_kernel<false, false><<<grid, 256, 0, s>>>(dt, first, count);
+  else if (!ta && tb) dgemm_grouped_kernel<false, true><<<grid, 256, 0, s>>>(dt, first, count);
+  else if (ta && !tb) dgemm_grouped_kernel<true, false><<<grid, 256, 0, s>>>(dt, first, count);
+  else dgemm_grouped_kernel<true, true><<<grid, 256, 0, s>>>(dt, first, count);
+  QDWHP_LAUNCH_CHECK();
+  if (prof) {
+    double fl = 0.0;
+    for (int i = 0; i < count; ++i) fl += 2.0 * (double)descs[i].M * (double)descs[i].N * (double)descs[i].K;
+    prof_end_launch(s, tok, fl);
+  }
 }
 
 }  // namespace qdwhp

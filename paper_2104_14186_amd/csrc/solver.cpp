@@ -14,6 +14,7 @@
 
 #include "qdwhp.h"
 #include "common.h"
+#include "drivers.h"
 #include "dwh_sched.h"
 #include "elem.h"
 #include "jacobi.h"
@@ -241,9 +242,9 @@ extern "C" size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_op
   return ar.off;
 }
 
-extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fraction, int which,
-                         double* w, double* V, int64_t ldv, void* work, size_t lwork,
-                         const qdwhp_opts* opts, void* stream, qdwhp_info* info) {
+int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, int which,
+                   double* w, double* V, int64_t ldv, void* work, size_t lwork,
+                   const qdwhp_opts* opts, void* stream, qdwhp_info* info, Deferred* df) {
   qdwhp_info dummy;
   if (!info) info = &dummy;
   std::memset(info, 0, sizeof(*info));
@@ -289,7 +290,12 @@ extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fractio
         dgemm(g, st);
       };
       lz = lanczos(op, n, nv, (int)msteps, o.seed, P.lz, s);
-      if (lz.sweeps < 0) return ret(QDWHP_ERR_NOCONV);
+      if (lz.sweeps < 0) {   // a non-finite input shows up here first
+        int hf[8];
+        QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        QDWHP_HIP(hipStreamSynchronize(s));
+        return ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
+      }
       lmax = -std::numeric_limits<double>::infinity();
       lmin = std::numeric_limits<double>::infinity();
       for (size_t i = 0; i < lz.nodes.size(); ++i) {
@@ -403,9 +409,13 @@ extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fractio
     // ---- V = Q2 W(:, 1:k), w = sgn theta(1:k)
     Gemm g3;
     g3.M = n; g3.N = k; g3.K = ell; g3.A = Q2; g3.lda = n; g3.B = Wv; g3.ldb = ell; g3.C = V; g3.ldc = ldv;
-    dgemm(g3, s);
     scale_vec(P.vals, w, k, sgn, s);
-    sign_normalize(V, ldv, n, k, nullptr, 0, 0, s);
+    if (df) {   // the caller launches the product and the sign step
+      df->g = g3; df->V = V; df->ldv = ldv; df->n = n; df->k = k; df->U = nullptr; df->ldu = 0; df->m = 0;
+    } else {
+      dgemm(g3, s);
+      sign_normalize(V, ldv, n, k, nullptr, 0, 0, s);
+    }
     ev.mark(7, s);
     ev.fill(info->ms);
     const double dn = (double)n, dl = (double)ell, dk = (double)k;
@@ -431,10 +441,10 @@ extern "C" size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdw
   return ar.off;
 }
 
-extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
-                         double* U, int64_t ldu, double* S, double* V, int64_t ldv,
-                         void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
-                         qdwhp_info* info) {
+int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                   double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                   void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
+                   qdwhp_info* info, Deferred* df) {
   qdwhp_info dummy;
   if (!info) info = &dummy;
   std::memset(info, 0, sizeof(*info));
@@ -484,7 +494,12 @@ extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int
         dgemm(h, st);
       };
       lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
-      if (lz.sweeps < 0) return ret(QDWHP_ERR_NOCONV);
+      if (lz.sweeps < 0) {   // a non-finite input shows up here first
+        int hf[8];
+        QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+        QDWHP_HIP(hipStreamSynchronize(s));
+        return ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
+      }
       lmax = -std::numeric_limits<double>::infinity();
       lmin = std::numeric_limits<double>::infinity();
       for (size_t i = 0; i < lz.nodes.size(); ++i) {
@@ -594,9 +609,13 @@ extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int
     apply_q(Y, mm, mm, P.Tall, ell, Um, k, ldum, P.qrs, s);
     Gemm gv;
     gv.M = nn; gv.N = k; gv.K = ell; gv.A = Q2; gv.lda = nn; gv.B = Vt; gv.ldb = ell; gv.C = Vm; gv.ldc = ldvm;
-    dgemm(gv, s);
     scale_vec(P.vals, S, k, 1.0, s);
-    sign_normalize(V, ldv, n, k, U, ldu, m, s);
+    if (df) {
+      df->g = gv; df->V = V; df->ldv = ldv; df->n = n; df->k = k; df->U = U; df->ldu = ldu; df->m = m;
+    } else {
+      dgemm(gv, s);
+      sign_normalize(V, ldv, n, k, U, ldu, m, s);
+    }
     ev.mark(7, s);
     ev.fill(info->ms);
     const double dm = (double)mm, dn = (double)nn, dl = (double)ell, dk = (double)k;
@@ -609,6 +628,19 @@ extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int
     return ret(QDWHP_ERR_HIP);
   }
   return ret(QDWHP_OK);
+}
+
+extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fraction, int which,
+                         double* w, double* V, int64_t ldv, void* work, size_t lwork,
+                         const qdwhp_opts* opts, void* stream, qdwhp_info* info) {
+  return eig_impl(A, n, lda, fraction, which, w, V, ldv, work, lwork, opts, stream, info, nullptr);
+}
+
+extern "C" int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
+                         double* U, int64_t ldu, double* S, double* V, int64_t ldv,
+                         void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
+                         qdwhp_info* info) {
+  return svd_impl(A, m, n, lda, k, U, ldu, S, V, ldv, work, lwork, opts, stream, info, nullptr);
 }
 
 // ===========================================================================

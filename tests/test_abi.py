@@ -1,0 +1,61 @@
+"""The C-ABI library loads without a GPU and exports every entry point that
+include/qdwhp.h declares (no compute calls are made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "qdwhp.h")
+LIB = os.path.join(ROOT, "paper_2104_14186_amd", "libqdwhp.so")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # drop comments
+    return sorted(set(re.findall(r"\b(qdwhp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_solver_entry_points():
+    names = declared()
+    for must in ["qdwhp_eig", "qdwhp_svd", "qdwhp_eig_workspace", "qdwhp_svd_workspace",
+                 "qdwhp_batched", "qdwhp_serve_create", "qdwhp_serve_submit", "qdwhp_serve_poll",
+                 "qdwhp_serve_destroy", "qdwhp_dgemm_grouped", "qdwhp_tune_set"]:
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built (run __graft_entry__.build())")
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(L, n)]
+    assert not missing, f"declared but not exported: {missing}"
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_signatures_cover_the_header():
+    import paper_2104_14186_amd as q
+    assert sorted(q.exported_symbols()) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_only_calls():
+    """Calls that touch no device: options, strings, tuning table, size queries."""
+    import paper_2104_14186_amd as q
+    L = q.lib()
+    o = q.default_opts()
+    assert o.tol == 0.05 and o.eig_iters == 3 and o.kappa_max == 100.0
+    assert L.qdwhp_strerror(2)
+    q.tune_set("test.key", 7)
+    assert q.tune_get("test.key", -1) == 7
+    assert q.tune_get("test.absent", 3) == 3
+    assert L.qdwhp_eig_workspace(512, 0.1, ctypes.byref(o)) > 512 * 512 * 8
+    p = q.Problem()
+    p.type, p.m, p.n, p.k = q.PROBLEM_SVD, 300, 200, 10
+    assert L.qdwhp_problem_workspace(ctypes.byref(p), ctypes.byref(o)) == L.qdwhp_svd_workspace(300, 200, 10, ctypes.byref(o))
+    probs = (q.Problem * 2)(p, p)
+    assert L.qdwhp_batched_workspace(2, probs, ctypes.byref(o)) >= 2 * L.qdwhp_svd_workspace(300, 200, 10, ctypes.byref(o))
+    # argument checks return before any device work
+    assert L.qdwhp_eig(None, 4, 4, 0.5, 0, None, None, 4, None, 0, None, None, None) == -1
+    assert L.qdwhp_batched(-1, None, None, 0, None, 0, None, None, None) == -1
+    assert L.qdwhp_serve_submit(None, None, None) == -1
