@@ -22,6 +22,7 @@
 // known-zero blocks.
 #include <algorithm>
 
+#include "qdwhp.h"
 #include "common.h"
 #include "drivers.h"
 
@@ -83,18 +84,23 @@ __device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, in
   *tn = in / gm;
 }
 
-// One 128x128 output tile (tm, tn) of problem g; zi is the batch index, or
+// One BT x BT output tile (tm, tn) of problem g (BT = 128 or 64); zi is the batch index, or
 // the K share when g.splitk > 1.  As / Bs are the workgroup's LDS buffers.
-template <bool TA, bool TB, bool F32>
+template <bool TA, bool TB, bool F32, int BT>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn, int64_t zi,
-                                          typename MfmaT<F32>::elem (*As)[BK * SA],
-                                          typename MfmaT<F32>::elem (*Bs)[BK * SB]) {
+                                          typename MfmaT<F32>::elem (*As)[BK * (BT + PAD)],
+                                          typename MfmaT<F32>::elem (*Bs)[BK * (BT + PAD)]) {
+  // tile geometry: 2x2 waves, each owning a (BT/2)^2 block of WT x WT MFMA tiles
+  constexpr int TM = BT, TN = BT, TSA = BT + PAD, TSB = BT + PAD;
+  constexpr int TNLD = BT * BK / 256;   // operand elements loaded per thread per slice
+  constexpr int WT = BT / 32, HALF = BT / 2;
+  constexpr int KS = 256 / BT;          // k rows covered by one pass of a k-major load
   typedef typename MfmaT<F32>::elem E;
   typedef typename MfmaT<F32>::acc ACC;
 
   const int tid = threadIdx.x;
-  const int64_t row0 = tm * BM;
-  const int64_t col0 = tn * BN;
+  const int64_t row0 = tm * TM;
+  const int64_t col0 = tn * TN;
   const bool split = g.splitk > 1;
   const int64_t bz = split ? 0 : zi;
   const double* __restrict__ A = g.A + bz * g.sA;
@@ -109,8 +115,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   int64_t klo = 0, khi = g.K;
   if (g.klo == KLO_ROW) klo = row0 - g.koff;
   else if (g.klo == KLO_COL) klo = col0 - g.koff;
-  if (g.khi == KHI_ROW) khi = row0 + BM - g.koff;
-  else if (g.khi == KHI_COL) khi = col0 + BN - g.koff;
+  if (g.khi == KHI_ROW) khi = row0 + TM - g.koff;
+  else if (g.khi == KHI_COL) khi = col0 + TN - g.koff;
   if (klo < 0) klo = 0;
   if (khi > g.K) khi = g.K;
   if (split) {   // this workgroup's share of K, in whole BK slices
@@ -120,7 +126,7 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
     if (khi > (z + 1) * kc) khi = (z + 1) * kc;
   }
   // tiles that need no bounds or structure masks use straight-line loads
-  const bool interior = row0 + BM <= M && col0 + BN <= N && !aul && !bul;
+  const bool interior = row0 + TM <= M && col0 + TN <= N && !aul && !bul;
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -130,21 +136,21 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   // registers) points at the slice's corner and each thread keeps one 32-bit
   // byte offset per element it loads.  Offsets at or beyond OOB read as zero,
   // which is how bounds, K ranges and structure masks are applied.
-  //   A (m, k):  !TA: stored A[m + k lda] (thread: m = am, k = ak + 2r)
+  //   A (m, k):  !TA: stored A[m + k lda] (thread: m = am, k = ak + KS r)
   //               TA: stored A[k + m lda] (thread: m = am + 16r, k = ak)
   //   B (k, n):  !TB: stored B[k + n ldb] (thread: n = bn + 16r, k = bk)
-  //               TB: stored B[n + k ldb] (thread: n = bn, k = bk + 2r)
-  const int am = TA ? (tid >> 4) : (tid & 127);
-  const int ak = TA ? (tid & 15) : (tid >> 7);
-  const int bn = TB ? (tid & 127) : (tid >> 4);
-  const int bk = TB ? (tid >> 7) : (tid & 15);
+  //               TB: stored B[n + k ldb] (thread: n = bn, k = bk + KS r)
+  const int am = TA ? (tid >> 4) : (tid & (BT - 1));
+  const int ak = TA ? (tid & 15) : (tid / BT);
+  const int bn = TB ? (tid & (BT - 1)) : (tid >> 4);
+  const int bk = TB ? (tid / BT) : (tid & 15);
   constexpr uint32_t OOB = 0x80000000u, RECORDS = 0x7ffffff8u;
-  uint32_t aoff[NLD], boff[NLD];
+  uint32_t aoff[TNLD], boff[TNLD];
 #pragma unroll
-  for (int r = 0; r < NLD; ++r) {
+  for (int r = 0; r < TNLD; ++r) {
     aoff[r] = TA ? (uint32_t)((ak + (int64_t)(am + 16 * r) * lda) * 8)
-                 : (uint32_t)((am + (int64_t)(ak + 2 * r) * lda) * 8);
-    boff[r] = TB ? (uint32_t)((bn + (int64_t)(bk + 2 * r) * ldb) * 8)
+                 : (uint32_t)((am + (int64_t)(ak + KS * r) * lda) * 8);
+    boff[r] = TB ? (uint32_t)((bn + (int64_t)(bk + KS * r) * ldb) * 8)
                  : (uint32_t)((bk + (int64_t)(bn + 16 * r) * ldb) * 8);
   }
   auto slice_a = [&](int64_t k0) {
@@ -159,35 +165,35 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
   };
 
-  ACC acc[4][4];
+  ACC acc[WT][WT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = ACC{0, 0, 0, 0};
-  double acc64[F32 ? 4 : 1][F32 ? 4 : 1][4];   // FP32 path: slice sums added here in FP64
+    for (int j = 0; j < WT; ++j) acc[i][j] = ACC{0, 0, 0, 0};
+  double acc64[F32 ? WT : 1][F32 ? WT : 1][4];   // FP32 path: slice sums added here in FP64
   if constexpr (F32) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < WT; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc64[i][j][r] = 0.0;
   }
 
-  E ra[NLD], rb[NLD];
+  E ra[TNLD], rb[TNLD];
 
   auto load = [&](int64_t k0) {
     const __amdgpu_buffer_rsrc_t rsa = slice_a(k0), rsb = slice_b(k0);
     if (interior && k0 + BK <= khi) {
 #pragma unroll
-      for (int r = 0; r < NLD; ++r) ra[r] = (E)ld(rsa, aoff[r]);
+      for (int r = 0; r < TNLD; ++r) ra[r] = (E)ld(rsa, aoff[r]);
 #pragma unroll
-      for (int r = 0; r < NLD; ++r) rb[r] = (E)ld(rsb, boff[r]);
+      for (int r = 0; r < TNLD; ++r) rb[r] = (E)ld(rsb, boff[r]);
       return;
     }
 #pragma unroll
-    for (int r = 0; r < NLD; ++r) {
-      const int64_t m = row0 + am + (TA ? 16 * r : 0), k = k0 + ak + (TA ? 0 : 2 * r);
+    for (int r = 0; r < TNLD; ++r) {
+      const int64_t m = row0 + am + (TA ? 16 * r : 0), k = k0 + ak + (TA ? 0 : KS * r);
       const int64_t sr = TA ? k : m, sc = TA ? m : k;   // stored (row, col)
       const bool in = m < M && k >= klo && k < khi;
       const bool take = in && (!aul || sr > sc);
@@ -196,8 +202,8 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       ra[r] = (E)v;
     }
 #pragma unroll
-    for (int r = 0; r < NLD; ++r) {
-      const int64_t n = col0 + bn + (TB ? 0 : 16 * r), k = k0 + bk + (TB ? 2 * r : 0);
+    for (int r = 0; r < TNLD; ++r) {
+      const int64_t n = col0 + bn + (TB ? 0 : 16 * r), k = k0 + bk + (TB ? KS * r : 0);
       const int64_t sr = TB ? n : k, sc = TB ? k : n;
       const bool in = n < N && k >= klo && k < khi;
       const bool take = in && (!bul || sr > sc);
@@ -208,11 +214,11 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < NLD; ++r)
-      As[buf][(ak + (TA ? 0 : 2 * r)) * SA + am + (TA ? 16 * r : 0)] = ra[r];
+    for (int r = 0; r < TNLD; ++r)
+      As[buf][(ak + (TA ? 0 : KS * r)) * TSA + am + (TA ? 16 * r : 0)] = ra[r];
 #pragma unroll
-    for (int r = 0; r < NLD; ++r)
-      Bs[buf][(bk + (TB ? 2 * r : 0)) * SB + bn + (TB ? 0 : 16 * r)] = rb[r];
+    for (int r = 0; r < TNLD; ++r)
+      Bs[buf][(bk + (TB ? KS * r : 0)) * TSB + bn + (TB ? 0 : 16 * r)] = rb[r];
   };
 
   if (khi > klo) {
@@ -229,23 +235,23 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       const E* bs = Bs[cur];
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
-        E a[4], b[4];
+        E a[WT], b[WT];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) a[i] = as[(kk + lk) * SA + wm * 64 + i * 16 + li];
+        for (int i = 0; i < WT; ++i) a[i] = as[(kk + lk) * TSA + wm * HALF + i * 16 + li];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = bs[(kk + lk) * SB + wn * 64 + j * 16 + li];
+        for (int j = 0; j < WT; ++j) b[j] = bs[(kk + lk) * TSB + wn * HALF + j * 16 + li];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < WT; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j)
+          for (int j = 0; j < WT; ++j)
             acc[i][j] = MfmaT<F32>::op(a[i], b[j], acc[i][j]);
       }
       if constexpr (F32) {
         if ((t & 1) || !more) {   // every 32 k: fold the FP32 sums into FP64
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < WT; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < WT; ++j)
 #pragma unroll
               for (int r = 0; r < 4; ++r) { acc64[i][j][r] += (double)acc[i][j][r]; acc[i][j][r] = 0.0f; }
         }
@@ -263,25 +269,25 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   if (split) {   // raw partial product of this K share
     double* P = g.ws + zi * M * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < WT; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < WT; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = row0 + wm * 64 + i * 16 + MfmaT<F32>::row(lk, r);
-          const int64_t col = col0 + wn * 64 + j * 16 + li;
+          const int64_t row = row0 + wm * HALF + i * 16 + MfmaT<F32>::row(lk, r);
+          const int64_t col = col0 + wn * HALF + j * 16 + li;
           if (row < M && col < N) P[row + col * M] = result(i, j, r);
         }
     return;
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < WT; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = row0 + wm * 64 + i * 16 + MfmaT<F32>::row(lk, r);
-        const int64_t col = col0 + wn * 64 + j * 16 + li;
+        const int64_t row = row0 + wm * HALF + i * 16 + MfmaT<F32>::row(lk, r);
+        const int64_t col = col0 + wn * HALF + j * 16 + li;
         if (row < M && col < N) {
           double* p = C + row + col * g.ldc;
           double v = alpha * result(i, j, r);
@@ -292,13 +298,13 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       }
 }
 
-template <bool TA, bool TB, bool F32>
-__global__ __launch_bounds__(256, F32 ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
-  __shared__ typename MfmaT<F32>::elem As[2][BK * SA];
-  __shared__ typename MfmaT<F32>::elem Bs[2][BK * SB];
+template <bool TA, bool TB, bool F32, int BT>
+__global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
+  __shared__ typename MfmaT<F32>::elem As[2][BK * (BT + PAD)];
+  __shared__ typename MfmaT<F32>::elem Bs[2][BK * (BT + PAD)];
   int64_t tm, tn;
   tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, &tm, &tn);
-  gemm_tile<TA, TB, F32>(g, tm, tn, blockIdx.z, As, Bs);
+  gemm_tile<TA, TB, F32, BT>(g, tm, tn, blockIdx.z, As, Bs);
 }
 
 // Persistent launch over a ragged list of FP64 problems (same transposes):
@@ -323,7 +329,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_grouped_kernel(const GroupedDesc
     g.A = d.A; g.lda = d.lda; g.ta = TA; g.B = d.B; g.ldb = d.ldb; g.tb = TB; g.C = d.C; g.ldc = d.ldc;
     const int64_t local = t - first[lo];
     const int64_t gx = (g.M + BM - 1) / BM;
-    gemm_tile<TA, TB, false>(g, local % gx, local / gx, 0, As, Bs);
+    gemm_tile<TA, TB, false, 128>(g, local % gx, local / gx, 0, As, Bs);
     __syncthreads();
   }
 }
@@ -414,6 +420,24 @@ double gemm_flops(const Gemm& g) {
   return 2.0 * total * g.batch;
 }
 
+template <int BT>
+static void launch_tiles(const Gemm& g, int64_t tm, int64_t tn, hipStream_t s) {
+  const int64_t ntile = (g.tiles == TILES_UPPER) ? tm * (tm + 1) / 2 : tm * tn;
+  dim3 grid((unsigned)ntile, 1, (unsigned)(g.splitk > 1 ? g.splitk : g.batch));
+  dim3 block(256);
+  if (!g.f32) {
+    if (!g.ta && !g.tb) dgemm_kernel<false, false, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (!g.ta && g.tb) dgemm_kernel<false, true, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (g.ta && !g.tb) dgemm_kernel<true, false, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else dgemm_kernel<true, true, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
+  } else {
+    if (!g.ta && !g.tb) dgemm_kernel<false, false, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (!g.ta && g.tb) dgemm_kernel<false, true, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (g.ta && !g.tb) dgemm_kernel<true, false, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
+    else dgemm_kernel<true, true, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
+  }
+}
+
 void dgemm(const Gemm& g0, hipStream_t s) {
   if (g0.M <= 0 || g0.N <= 0 || g0.batch <= 0) return;
   void* tok = nullptr;
@@ -421,8 +445,13 @@ void dgemm(const Gemm& g0, hipStream_t s) {
   if (prof) prof_begin_launch(s, &tok);
   Gemm g = g0;
   g.splitk = 1;
-  const int64_t tm = cdiv(g.M, BM), tn = cdiv(g.N, BN);
-  const int64_t tiles = tm * tn * g.batch;
+  int64_t tm = cdiv(g.M, BM), tn = cdiv(g.N, BN);
+  if (g.tiles == TILES_UPPER && tm != tn)
+    throw HipError{hipErrorInvalidValue};   // upper-tile output must be square
+  // every per-thread byte offset inside an operand slice must fit in 31 bits
+  if ((g.lda > 0 && g.lda >= (int64_t(1) << 21)) || (g.ldb > 0 && g.ldb >= (int64_t(1) << 21)))
+    throw HipError{hipErrorInvalidValue};   // leading dimension too large
+  const int64_t tiles = ((g.tiles == TILES_UPPER) ? tm * (tm + 1) / 2 : tm * tn) * g.batch;
   if (g.batch == 1 && g.ws && g.tiles == TILES_ALL && tiles < 160 && g.K >= 4 * BK * 8) {
     int64_t S = cdiv(320, tiles);
     const int64_t kmax = g.K / (BK * 8);
@@ -432,24 +461,13 @@ void dgemm(const Gemm& g0, hipStream_t s) {
     if (S > 64) S = 64;
     if (S >= 2) g.splitk = (int)S;
   }
-  if (g.tiles == TILES_UPPER && tm != tn)
-    throw HipError{hipErrorInvalidValue};   // upper-tile output must be square
-  // every per-thread byte offset inside an operand slice must fit in 31 bits
-  if ((g.lda > 0 && g.lda >= (int64_t(1) << 21)) || (g.ldb > 0 && g.ldb >= (int64_t(1) << 21)))
-    throw HipError{hipErrorInvalidValue};   // leading dimension too large
-  const int64_t ntile = (g.tiles == TILES_UPPER) ? tm * (tm + 1) / 2 : tm * tn;
-  dim3 grid((unsigned)ntile, 1, (unsigned)(g.splitk > 1 ? g.splitk : g.batch));
-  dim3 block(256);
-  if (!g.f32) {
-    if (!g.ta && !g.tb) dgemm_kernel<false, false, false><<<grid, block, 0, s>>>(g, tm, tn);
-    else if (!g.ta && g.tb) dgemm_kernel<false, true, false><<<grid, block, 0, s>>>(g, tm, tn);
-    else if (g.ta && !g.tb) dgemm_kernel<true, false, false><<<grid, block, 0, s>>>(g, tm, tn);
-    else dgemm_kernel<true, true, false><<<grid, block, 0, s>>>(g, tm, tn);
+  // Launches with few 128x128 tiles run 64x64 tiles (4x the workgroups).  The
+  // per-element k order is the same for both, so the results are identical.
+  if (g.splitk == 1 && tiles < qdwhp_tune_get("gemm.small_tiles", 96)) {
+    tm = cdiv(g.M, 64); tn = cdiv(g.N, 64);
+    launch_tiles<64>(g, tm, tn, s);
   } else {
-    if (!g.ta && !g.tb) dgemm_kernel<false, false, true><<<grid, block, 0, s>>>(g, tm, tn);
-    else if (!g.ta && g.tb) dgemm_kernel<false, true, true><<<grid, block, 0, s>>>(g, tm, tn);
-    else if (g.ta && !g.tb) dgemm_kernel<true, false, true><<<grid, block, 0, s>>>(g, tm, tn);
-    else dgemm_kernel<true, true, true><<<grid, block, 0, s>>>(g, tm, tn);
+    launch_tiles<128>(g, tm, tn, s);
   }
   QDWHP_LAUNCH_CHECK();
   if (g.splitk > 1) {

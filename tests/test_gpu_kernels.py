@@ -133,3 +133,31 @@ def test_gesvj(n):
     assert np.abs(S - ref).max() < 5e-15 * ref.max() * max(1, np.sqrt(n))
     assert np.abs(R @ V - U * S[None, :]).max() < 5e-15 * ref.max() * max(1, np.sqrt(n))
     assert np.abs(V.T @ V - np.eye(n)).max() < 5e-15 * max(1, np.sqrt(n))
+
+
+@pytest.mark.parametrize("m,n,k,ta,tb,upper", [
+    (300, 257, 129, 0, 0, 0), (257, 300, 77, 1, 0, 0), (190, 64, 300, 0, 1, 0),
+    (513, 511, 100, 1, 1, 0), (333, 333, 200, 1, 0, 1)])
+def test_dgemm_tile_size_does_not_change_results(m, n, k, ta, tb, upper):
+    """64x64 and 128x128 tiles sum every element in the same k order."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    print("tiles", m, n, k, ta, tb, upper, flush=True)
+    g = np.random.default_rng(9)
+    A = g.standard_normal((k, m) if ta else (m, k))
+    B = g.standard_normal((n, k) if tb else (k, n))
+    dA, dB = _cm(torch, A), _cm(torch, B)
+    out = []
+    old = q.tune_get("gemm.small_tiles", 96)
+    try:
+        for thr in (0, 1 << 40):
+            q.tune_set("gemm.small_tiles", thr)
+            C = torch.zeros((n, m), dtype=torch.float64, device="cuda")
+            q.dgemm(dA, dB, C, 1.0, 0.0, transa=bool(ta), transb=bool(tb), upper=bool(upper))
+            torch.cuda.synchronize()
+            out.append(C.clone())
+    finally:
+        q.tune_set("gemm.small_tiles", old)
+    if upper:   # only the upper triangle is defined for an upper-tile output
+        out = [torch.triu(c.t()) for c in out]
+    assert bool((out[0] == out[1]).all())
