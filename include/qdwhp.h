@@ -85,6 +85,11 @@ typedef struct {
   double   tau, mu, rho;
   double   alpha, s_svd;
   int      kinds[16];      /* per-step QDWHP_KIND_*; QDWHP_KIND_AUTO = rule         */
+  int      graphs;         /* 0   : 1 = run the DWH iterations as a captured hipGraph:
+                              the first solve with given buffers, sizes and step kinds
+                              records the launch sequence, later ones replay it with
+                              new weights (pays off for repeated solves on one
+                              workspace; results are identical either way)        */
 } qdwhp_opts;
 
 /* ---- per-call report (host struct) ------------------------------------ */

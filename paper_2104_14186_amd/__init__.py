@@ -34,7 +34,7 @@ class Opts(ctypes.Structure):
                 ("lanczos_vectors", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("s_svd", ctypes.c_double),
-                ("kinds", ctypes.c_int * 16)]
+                ("kinds", ctypes.c_int * 16), ("graphs", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):

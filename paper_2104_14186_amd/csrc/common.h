@@ -57,6 +57,9 @@ struct Gemm {
   double* ws = nullptr; int64_t ws_doubles = 0;
   int splitk = 1;        // set by dgemm(); callers leave it at 1
   bool f32 = false;      // FP32 matrix cores (operands rounded to FP32, FP64 epilogue)
+  // alpha = dscal[ia] and beta = dscal[ib] (device memory) when set, so a
+  // captured launch sequence can be replayed with new scalars
+  const double* dscal = nullptr; int ia = -1, ib = -1;
 };
 void dgemm(const Gemm& g, hipStream_t s);
 // Algorithmic flops of one GEMM call: 2 x (number of products the operation
@@ -72,6 +75,9 @@ void prof_end_launch(hipStream_t s, void* tok, double flops);
 void fill(double* X, int64_t m, int64_t n, int64_t ld, double v, double diag, hipStream_t s);
 void copy(const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t s);
 void mirror_upper(double* X, int64_t n, int64_t ld, hipStream_t s);
+// dst[0..count) = vals (count <= 128) through kernel arguments: no host
+// buffer outlives the call and the copy can sit in a captured graph.
+void write_params(double* dst, const double* vals, int count, hipStream_t s);
 
 // ------------------------------------------------- Cholesky / inverse ----
 // Z (n x n SPD, upper triangle read) -> Z^{-1} (both triangles).  work holds

@@ -8,8 +8,9 @@ void eig_x0(const double* A, int64_t lda, double* X, int64_t ldx, int64_t n, dou
             double sgn, double s, hipStream_t st);
 void scale_copy(const double* A, int64_t lda, double* X, int64_t ldx, int64_t rows, int64_t cols,
                 double inv, bool trans, hipStream_t st);
+// W = [sc X; I] ((m + n) x n); sc is read from *dsc when dsc is set.
 void stacked(const double* X, int64_t ldx, double* W, int64_t ldw, int64_t m, int64_t n, double sc,
-             hipStream_t st);
+             hipStream_t st, const double* dsc = nullptr);
 void symmetrize(double* X, int64_t n, int64_t ld, hipStream_t st);
 void half_plus_identity(const double* X, int64_t ldx, double* B, int64_t ldb, int64_t n, hipStream_t st);
 void diagonal(const double* A, int64_t lda, int64_t n, double* d, hipStream_t st);

@@ -46,7 +46,8 @@ __global__ __launch_bounds__(256) void scale_t_kernel(const double* A, int64_t l
 
 // W = [sqrt(c) X; I]   ((m + n) x n)
 __global__ void stacked_kernel(const double* X, int64_t ldx, double* W, int64_t ldw, int64_t m, int64_t n,
-                               double sc) {
+                               double sc, const double* dsc) {
+  if (dsc) sc = *dsc;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
     if (i < m) W[i + j * ldw] = sc * X[i + j * ldx];
@@ -161,8 +162,8 @@ void scale_copy(const double* A, int64_t lda, double* X, int64_t ldx, int64_t ro
   QDWHP_LAUNCH_CHECK();
 }
 void stacked(const double* X, int64_t ldx, double* W, int64_t ldw, int64_t m, int64_t n, double sc,
-             hipStream_t st) {
-  stacked_kernel<<<grid2(m + n, n), 256, 0, st>>>(X, ldx, W, ldw, m, n, sc);
+             hipStream_t st, const double* dsc) {
+  stacked_kernel<<<grid2(m + n, n), 256, 0, st>>>(X, ldx, W, ldw, m, n, sc, dsc);
   QDWHP_LAUNCH_CHECK();
 }
 void symmetrize(double* X, int64_t n, int64_t ld, hipStream_t st) {

@@ -265,7 +265,9 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
     if constexpr (F32) return acc64[i][j][r];
     else return acc[i][j][r];
   };
-  const double alpha = g.alpha, beta = g.beta, dg = g.diag;
+  const double alpha = (g.dscal && g.ia >= 0) ? g.dscal[g.ia] : g.alpha;
+  const double beta = (g.dscal && g.ib >= 0) ? g.dscal[g.ib] : g.beta;
+  const double dg = g.diag;
   if (split) {   // raw partial product of this K share
     double* P = g.ws + zi * M * N;
 #pragma unroll
@@ -362,8 +364,10 @@ __global__ void splitk_reduce(Gemm g) {
     if (i >= M) continue;
     double acc = 0.0;
     for (int z = 0; z < g.splitk; ++z) acc += g.ws[(int64_t)z * M * N + i + j * M];
-    double v = g.alpha * acc;
-    if (g.beta != 0.0) v += g.beta * Cin[i + j * ldcin];
+    const double alpha = (g.dscal && g.ia >= 0) ? g.dscal[g.ia] : g.alpha;
+    const double beta = (g.dscal && g.ib >= 0) ? g.dscal[g.ib] : g.beta;
+    double v = alpha * acc;
+    if (beta != 0.0) v += beta * Cin[i + j * ldcin];
     if (g.diag != 0.0 && i == j) v += g.diag;
     g.C[i + j * g.ldc] = v;
   }

@@ -60,4 +60,22 @@ void mirror_upper(double* X, int64_t n, int64_t ld, hipStream_t s) {
   QDWHP_LAUNCH_CHECK();
 }
 
+namespace {
+struct Params { double v[128]; int count; };
+__global__ void write_params_kernel(double* dst, Params p) {
+  const int i = threadIdx.x;
+  if (i < p.count) dst[i] = p.v[i];
+}
+}  // namespace
+
+void write_params(double* dst, const double* vals, int count, hipStream_t s) {
+  if (count <= 0) return;
+  if (count > 128) throw HipError{hipErrorInvalidValue};
+  Params p;
+  for (int i = 0; i < count; ++i) p.v[i] = vals[i];
+  p.count = count;
+  write_params_kernel<<<1, 128, 0, s>>>(dst, p);
+  QDWHP_LAUNCH_CHECK();
+}
+
 }  // namespace qdwhp

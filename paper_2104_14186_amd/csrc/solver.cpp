@@ -16,6 +16,7 @@
 #include "common.h"
 #include "drivers.h"
 #include "dwh_sched.h"
+#include "graphs.h"
 #include "elem.h"
 #include "jacobi.h"
 #include "lanczos.h"
@@ -102,11 +103,22 @@ struct StepBufs {
 // f32: the Gram matrix and both triangular products run on the FP32 matrix
 // cores (operands rounded to FP32, FP64 epilogue); the Cholesky-inversion
 // stays FP64.
+// Device weight block of one step (dw, optional): [c, a - b/c, b/c, sqrt(c),
+// (a - b/c)/sqrt(c)]; when given, the products read their scalars from it so
+// the same captured launches serve any weights.
+constexpr int kStepParams = 8;
+void step_params(double a, double b, double c, double* out) {
+  out[0] = c; out[1] = a - b / c; out[2] = b / c; out[3] = std::sqrt(c);
+  out[4] = (a - b / c) / std::sqrt(c);
+  out[5] = out[6] = out[7] = 0.0;
+}
+
 void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b, double c, bool sym,
-               const StepBufs& B, hipStream_t s, bool f32 = false) {
+               const StepBufs& B, hipStream_t s, bool f32 = false, const double* dw = nullptr) {
   Gemm g;
   g.f32 = f32;
   g.M = n; g.N = n; g.K = m; g.alpha = c; g.beta = 0.0; g.diag = 1.0;
+  if (dw) { g.dscal = dw; g.ia = 0; }
   g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.Z; g.ldc = n;
   g.tiles = TILES_UPPER;
   dgemm(g, s);
@@ -123,6 +135,7 @@ void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b
   u.M = m; u.N = n; u.K = n; u.alpha = a - b / c; u.beta = b / c;
   u.A = T; u.lda = m; u.B = Wi; u.ldb = n; u.tb = true; u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
   u.klo = KLO_COL;
+  if (dw) { u.dscal = dw; u.ia = 1; u.ib = 2; }
   if (sym) u.tiles = TILES_UPPER;
   dgemm(u, s);
   if (sym) mirror_upper(Xn, n, m, s);
@@ -149,14 +162,15 @@ void ns_step(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, const Step
 
 // Eq. (2): [sqrt(c) X; I] = [Q1; Q2] R, X+ = (b/c) X + (a - b/c)/sqrt(c) Q1 Q2^T.
 void qr_step(double* X, int64_t m, int64_t n, double a, double b, double c, bool sym,
-             const StepBufs& B, hipStream_t s) {
+             const StepBufs& B, hipStream_t s, const double* dw = nullptr) {
   const int64_t mn = m + n;
-  stacked(X, m, B.W, mn, m, n, std::sqrt(c), s);
+  stacked(X, m, B.W, mn, m, n, std::sqrt(c), s, dw ? dw + 3 : nullptr);
   geqrf(B.W, mn, n, mn, B.tau, B.Tall, B.qrs, s);
   orgqr(B.W, mn, mn, B.Tall, n, 0, n, B.Q, mn, B.qrs, s);
   Gemm g;
   g.M = m; g.N = n; g.K = n; g.alpha = (a - b / c) / std::sqrt(c); g.beta = b / c;
   g.A = B.Q; g.lda = mn; g.B = B.Q + m; g.ldb = mn; g.tb = true; g.C = X; g.ldc = m;
+  if (dw) { g.dscal = dw; g.ia = 4; g.ib = 2; }
   dgemm(g, s);
   if (sym) symmetrize(X, n, m, s);
 }
@@ -165,7 +179,7 @@ void qr_step(double* X, int64_t m, int64_t n, double a, double b, double c, bool
 struct Plan {
   double *X, *Xn, *Z, *big;
   int64_t big_doubles;
-  double *tau, *Tall, *diag, *vals, *lz;
+  double *tau, *Tall, *diag, *vals, *lz, *wts;
   QrScratch qrs;
   int* flags;       // [0] Cholesky breakdown, [1] non-finite input
 };
@@ -190,6 +204,7 @@ Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd) 
   p.qrs = ar.base ? carve_qr_scratch(q, mm + nn, nn) : QrScratch{};
   p.lz = ar.take(lanczos_doubles(nn, mm, nv, (int)msteps));
   p.flags = (int*)ar.take(8);
+  p.wts = ar.take(16 * 8);
   return p;
 }
 
@@ -227,6 +242,48 @@ double table1_iter_flops(const std::vector<DwhStep>& sched, double m, double n) 
   for (const auto& st : sched)
     f += (st.kind == 1) ? 6.0 * m * n * n + 8.0 / 3.0 * n * n * n : 4.0 * m * n * n + n * n * n / 3.0;
   return f;
+}
+
+// The DWH steps of a solve, then the FP64 polish plan (0 = Newton-Schulz,
+// 1 = Halley (3,1,3) in Cholesky form) of the mixed-precision variant.
+// With opts.graphs the sequence is captured once per (buffers, sizes, step
+// kinds, plan) and replayed with this solve's weights.
+void run_iterations(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, const std::vector<DwhStep>& sched,
+                    bool mixed, const std::vector<int>& polish, const Plan& P, const StepBufs& sb, bool graphs,
+                    hipStream_t s) {
+  std::vector<double> w(kStepParams * sched.size());
+  for (size_t i = 0; i < sched.size(); ++i) step_params(sched[i].a, sched[i].b, sched[i].c, &w[kStepParams * i]);
+  auto body = [&](double*& x, double*& xn, const double* dw) {
+    for (size_t i = 0; i < sched.size(); ++i) {
+      const DwhStep& st = sched[i];
+      const double* d = dw ? dw + kStepParams * i : nullptr;
+      if (st.kind == 1) qr_step(x, m, n, st.a, st.b, st.c, sym, sb, s, d);
+      else chol_step(x, xn, m, n, st.a, st.b, st.c, sym, sb, s, mixed, d);
+    }
+    for (int p : polish) {
+      if (p == 0) ns_step(x, xn, m, n, sym, sb, s);
+      else chol_step(x, xn, m, n, 3.0, 1.0, 3.0, sym, sb, s, false);
+    }
+  };
+  if (graphs && sched.size() <= 16 && !prof_active()) {
+    std::vector<int64_t> key = {(int64_t)(intptr_t)X, (int64_t)(intptr_t)Xn, (int64_t)(intptr_t)P.big,
+                                (int64_t)(intptr_t)P.wts, m, n, sym, mixed};
+    for (const auto& st : sched) key.push_back(st.kind);
+    key.push_back(-1);
+    for (int p : polish) key.push_back(p);
+    write_params(P.wts, w.data(), (int)w.size(), s);
+    double* x = X;
+    double* xn = Xn;
+    if (graph_replay(key, s, [&] { double* a = X; double* b = Xn; body(a, b, P.wts); })) {
+      // the steps exchange X and Xn once per Cholesky-form or polish step
+      int swaps = (int)polish.size();
+      for (const auto& st : sched) swaps += (st.kind != 1);
+      if (swaps & 1) std::swap(x, xn);
+      X = x; Xn = xn;
+      return;
+    }
+  }
+  body(X, Xn, nullptr);
 }
 
 }  // namespace
@@ -339,20 +396,18 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       const StepBufs sb = step_bufs(P, n, n);
       const bool mixed = (o.precision == QDWHP_MIXED_FP32);
       double xbound = 1.0;
-      for (const auto& st : sched) {
-        if (st.kind == 1) qr_step(X, n, n, st.a, st.b, st.c, true, sb, s);
-        else chol_step(X, Xn, n, n, st.a, st.b, st.c, true, sb, s, mixed);
-        xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
-      }
+      for (const auto& st : sched) xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
+      std::vector<int> polish;
       if (mixed) {
         // FP64 polish: Newton-Schulz while the unwanted side stays below
         // sqrt(3) (where it converges), else Halley's (3,1,3) step in
         // Cholesky form (monotone for any x)
         for (int p = 0; p < o.polish_steps; ++p) {
-          if (xbound < 1.7) { ns_step(X, Xn, n, n, true, sb, s); xbound = std::max(1.0, 0.5 * xbound * (3.0 - xbound * xbound)); }
-          else { chol_step(X, Xn, n, n, 3.0, 1.0, 3.0, true, sb, s, false); xbound = std::max(1.0, dwh_map(xbound, 3.0, 1.0, 3.0)); }
+          if (xbound < 1.7) { polish.push_back(0); xbound = std::max(1.0, 0.5 * xbound * (3.0 - xbound * xbound)); }
+          else { polish.push_back(1); xbound = std::max(1.0, dwh_map(xbound, 3.0, 1.0, 3.0)); }
         }
       }
+      run_iterations(X, Xn, n, n, true, sched, mixed, polish, P, sb, o.graphs != 0, s);
       ev.mark(2, s);
       // ---- projector (X + I)/2, QR, ind (Algorithm 1)
       half_plus_identity(X, n, P.Z, n, n, s);
@@ -540,12 +595,9 @@ int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t 
       scale_copy(A, lda, X, mm, mm, nn, 1.0 / alpha, tr, s);
       const StepBufs sb = step_bufs(P, mm, nn);
       const bool mixed = (o.precision == QDWHP_MIXED_FP32);
-      for (const auto& st : sched) {
-        if (st.kind == 1) qr_step(X, mm, nn, st.a, st.b, st.c, false, sb, s);
-        else chol_step(X, Xn, mm, nn, st.a, st.b, st.c, false, sb, s, mixed);
-      }
-      if (mixed)   // FP64 Newton-Schulz polish (singular values of X lie in [0, 1 + O(u_32)])
-        for (int p = 0; p < o.polish_steps; ++p) ns_step(X, Xn, mm, nn, false, sb, s);
+      // FP64 Newton-Schulz polish after mixed steps (singular values of X lie in [0, 1 + O(u_32)])
+      const std::vector<int> polish(mixed ? std::max(0, o.polish_steps) : 0, 0);
+      run_iterations(X, Xn, mm, nn, false, sched, mixed, polish, P, sb, o.graphs != 0, s);
       ev.mark(2, s);
       // ---- projector I - X^T X, QR, ind (Algorithm 2)
       Gemm gb;

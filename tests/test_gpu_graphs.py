@@ -1,0 +1,107 @@
+"""Captured DWH iteration schedules (opts.graphs = 1).
+
+The first solve on a workspace records the launch sequence; later solves
+with the same sizes and step kinds replay it with their own weights.  Every
+replay, with eager work and synchronisations in between, must equal the
+uncaptured solve bitwise."""
+import ctypes
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _eig_fixed_ws(q, torch, A, f, opts, ws):
+    n = A.shape[0]
+    k = min(n, max(1, int(np.floor(f * n + 0.5))))
+    w = torch.empty(k, dtype=torch.float64, device="cuda")
+    Vb = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    info = q.Info()
+    st = q.lib().qdwhp_eig(ctypes.c_void_p(A.data_ptr()), n, n, f, 0, ctypes.c_void_p(w.data_ptr()),
+                           ctypes.c_void_p(Vb.data_ptr()), n, ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8,
+                           ctypes.byref(opts), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                           ctypes.byref(info))
+    assert st == 0
+    torch.cuda.synchronize()
+    return w, Vb, info.as_dict()
+
+
+def _svd_fixed_ws(q, torch, A, k, opts, ws):
+    m, n = A.shape
+    Ac = A.t().contiguous()
+    S = torch.empty(k, dtype=torch.float64, device="cuda")
+    Ub = torch.empty((k, m), dtype=torch.float64, device="cuda")
+    Vb = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    st = q.lib().qdwhp_svd(ctypes.c_void_p(Ac.data_ptr()), m, n, m, k, ctypes.c_void_p(Ub.data_ptr()), m,
+                           ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(Vb.data_ptr()), n,
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8, ctypes.byref(opts),
+                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+    assert st == 0
+    torch.cuda.synchronize()
+    return S, Ub, Vb
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_eig_graph_replays_equal_eager(precision):
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import eig_uniform
+    n, f = 320, 0.1
+    print("eig graphs", n, f, precision, flush=True)
+    eager = q.default_opts(precision=precision)
+    graph = q.default_opts(precision=precision, graphs=1)
+    nbytes = q.lib().qdwhp_eig_workspace(n, f, ctypes.byref(eager))
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    kinds = set()
+    for rep, seed in enumerate([31, 31, 32, 33]):     # same matrix twice, then new weights
+        A, lam = eig_uniform(n, seed, device=torch.device("cuda"))
+        g = _eig_fixed_ws(q, torch, A, f, graph, ws)
+        _ = torch.randn(1000, device="cuda").sum().item()   # eager work between replays
+        e = _eig_fixed_ws(q, torch, A, f, eager, ws)
+        assert bool((g[0] == e[0]).all()) and bool((g[1] == e[1]).all()), (rep, seed)
+        kinds.add(tuple(g[2]["kinds"]))
+        ex = np.sort(lam)[::-1][:len(g[0])]
+        tol = 1e-12
+        assert np.max(np.abs(g[0].cpu().numpy() - ex) / np.abs(ex)) <= tol
+    assert len(kinds) >= 1
+
+
+def test_svd_graph_replays_equal_eager():
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import svd_geometric
+    m, n, k = 300, 220, 15
+    print("svd graphs", m, n, k, flush=True)
+    eager = q.default_opts()
+    graph = q.default_opts(graphs=1)
+    nbytes = q.lib().qdwhp_svd_workspace(m, n, k, ctypes.byref(eager))
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    for rep, seed in enumerate([41, 41, 42]):
+        A, s = svd_geometric(m, n, seed, kappa=1e8, device=torch.device("cuda"))
+        g = _svd_fixed_ws(q, torch, A, k, graph, ws)
+        e = _svd_fixed_ws(q, torch, A, k, eager, ws)
+        for x, y in zip(g, e):
+            assert bool((x == y).all()), (rep, seed)
+
+
+def test_batched_with_graphs_twice():
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import eig_uniform
+    dev = torch.device("cuda")
+    specs = [dict(type="eig", A=eig_uniform(n, 50 + n, device=dev)[0], fraction=0.1) for n in (200, 260, 200)]
+    print("batched graphs", flush=True)
+    o = q.default_opts(graphs=1)
+    r1 = q.batched(specs, lanes=2, opts=o)
+    r2 = q.batched(specs, lanes=2, opts=o)
+    for sp, a, b in zip(specs, r1, r2):
+        alone = q.eig(sp["A"], fraction=sp["fraction"])
+        assert all(bool((x == y).all()) for x, y in zip(a, alone))
+        assert all(bool((x == y).all()) for x, y in zip(b, alone))
