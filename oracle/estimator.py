@@ -100,7 +100,7 @@ def target_count(n, k, boost=1):
     return min(n, boost * (k + max(16, int(math.ceil(0.1 * k)))))
 
 
-def _cut_below(est, kt):
+def _cut_below(est, kt, nonneg=False):
     """Threshold below the node at which the estimated count first reaches kt.
 
     Nodes are pooled over the runs and sorted downwards; the cut is placed
@@ -108,6 +108,11 @@ def _cut_below(est, kt):
     (more than 1e-6 of the estimated spectral spread below), so a cluster that
     several runs resolve as one node is kept whole.  Returns None if the count
     never reaches kt (everything wanted).
+
+    nonneg (nodes of A^T A, which span many decades when A is ill
+    conditioned): a node is distinct when it lies more than 1e-6 of the
+    node's own value below, and when no node is, the cut is halfway down to
+    the spectrum's lower end 0.
     """
     order = np.argsort(-est["nodes"], kind="stable")
     th = est["nodes"][order]
@@ -117,10 +122,12 @@ def _cut_below(est, kt):
         return None
     j = int(hit[0])
     spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
-    below = th[j + 1:][th[j + 1:] < th[j] - 1e-6 * spread]
+    gap = 1e-6 * abs(th[j]) if nonneg else 1e-6 * spread
+    below = th[j + 1:][th[j + 1:] < th[j] - gap]
     if len(below) == 0:
-        return None
-    return 0.5 * (th[j] + float(below[0]))
+        return 0.5 * th[j] if (nonneg and th[j] > 0.0) else None
+    nxt = max(float(below[0]), 0.0) if nonneg else float(below[0])
+    return 0.5 * (th[j] + nxt)
 
 
 def choose_tau(est, k, boost=1):
@@ -152,7 +159,7 @@ def choose_svd_threshold(est, k, boost=1):
     if alpha == 0.0:
         alpha = 1e-300
     kt = target_count(n, k, boost)
-    cut = _cut_below(est, kt)
+    cut = _cut_below(est, kt, nonneg=True)
     t = 0.0 if cut is None else max(cut, 0.0)
     s = min(1.0, max(1e-15, math.sqrt(t) / alpha))
     return alpha, s

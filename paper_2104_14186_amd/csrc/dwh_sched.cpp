@@ -61,7 +61,7 @@ int64_t target_count(int64_t n, int64_t k, int boost) {
 }
 
 bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weights, int64_t n,
-               int nv, double lmax, double lmin, int64_t kt, double* cut) {
+               int nv, double lmax, double lmin, int64_t kt, double* cut, bool nonneg) {
   if (kt >= n) return false;
   std::vector<size_t> order(nodes.size());
   std::iota(order.begin(), order.end(), 0);
@@ -77,10 +77,14 @@ bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weig
   if (j == order.size()) return false;
   const double spread = std::max({lmax - lmin, std::fabs(lmax), std::fabs(lmin), 1e-300});
   const double tj = nodes[order[j]];
+  // nonneg (nodes of A^T A, spanning many decades): distinct means more than
+  // a relative 1e-6 below, and with no such node the cut is halfway to 0
+  const double gap = nonneg ? 1e-6 * std::fabs(tj) : 1e-6 * spread;
   for (size_t i = j + 1; i < order.size(); ++i) {
     const double v = nodes[order[i]];
-    if (v < tj - 1e-6 * spread) { *cut = 0.5 * (tj + v); return true; }
+    if (v < tj - gap) { *cut = 0.5 * (tj + (nonneg ? std::max(v, 0.0) : v)); return true; }
   }
+  if (nonneg && tj > 0.0) { *cut = 0.5 * tj; return true; }
   return false;
 }
 

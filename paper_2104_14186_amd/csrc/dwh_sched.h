@@ -26,8 +26,10 @@ std::vector<DwhStep> svd_schedule(double s, double kappa_max, bool qr_first);
 
 // Threshold below the pooled Lanczos quadrature node at which the estimated
 // count first reaches kt; returns false when the count never reaches kt.
+// nonneg: nodes of A^T A (>= 0, many decades): distinctness is relative to
+// the node and, without a distinct node below, the cut is half the node.
 bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weights, int64_t n,
-               int nv, double lmax, double lmin, int64_t kt, double* cut);
+               int nv, double lmax, double lmin, int64_t kt, double* cut, bool nonneg = false);
 int64_t target_count(int64_t n, int64_t k, int boost);
 
 }  // namespace qdwhp

@@ -582,7 +582,7 @@ int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t 
         } else {
           double cut;
           const double t = cut_below(lz.nodes, lz.weights, nn, nv, lmax, lmin,
-                                     target_count(nn, k, boost), &cut) ? std::max(cut, 0.0) : 0.0;
+                                     target_count(nn, k, boost), &cut, true) ? std::max(cut, 0.0) : 0.0;
           sthr = std::min(1.0, std::max(1e-15, std::sqrt(t) / alpha));
         }
       }

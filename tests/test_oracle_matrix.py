@@ -254,3 +254,31 @@ def test_edge_cases():
     A = rng(10).standard_normal((37, 23))
     r = oracle.svd_partial(A, 5)
     assert np.allclose(r["S"], np.linalg.svd(A, compute_uv=False)[:5], rtol=1e-13)
+
+
+def test_svd_cut_is_relative_for_graded_spectra():
+    """Nodes of A^T A span many decades for ill-conditioned A: a node counts as
+    distinct on a relative scale, and without a lower node the cut is half
+    the node (never 0, which would map every singular value to 1)."""
+    from oracle.estimator import _cut_below, choose_svd_threshold
+    est = dict(n=100, nv=1, lmax=1.0, lmin=-1e-3,
+               nodes=np.array([1.0, 1e-3, 5e-7, 1e-9]), weights=np.array([0.1, 0.2, 0.3, 0.4]))
+    # the count reaches kt = 50 at the node 5e-7
+    assert _cut_below(est, 50) is None                       # absolute rule: nothing distinct below
+    assert _cut_below(est, 50, nonneg=True) == pytest.approx(0.5 * (5e-7 + 1e-9))
+    est2 = dict(est, nodes=np.array([1.0, 1e-3, 5e-7, 5e-7 * (1 - 1e-9)]))
+    assert _cut_below(est2, 50, nonneg=True) == pytest.approx(2.5e-7)
+    alpha, s = choose_svd_threshold(est, 40)
+    assert s > 1e-6 and alpha == 1.0
+
+
+def test_svd_graded_kappa_1e12_keeps_ell_below_n():
+    """A geometric spectrum down to 1e-12 with ~19% wanted: ell < n and the
+    top-k values are exact."""
+    from synthetic import svd_geometric
+    import oracle
+    A, sig = svd_geometric(256, 256, 4041, kappa=9.6e11)
+    k = 49
+    r = oracle.svd_partial(A, k=k)
+    assert r["ell"] < 256
+    assert np.max(np.abs(r["S"] - sig[:k]) / sig[:k]) <= 1e-12
