@@ -199,6 +199,7 @@ struct SymArgs {
   double* V; int64_t ldv;            // npad x npad
   double tol;
   double* offmax;                    // per sweep
+  int* act;                          // [nb/2]: 1 if the pair's rotation is not the identity
   int sweep; int step;
 };
 
@@ -235,7 +236,8 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
     atomic_max_nonneg(a.offmax + a.sweep, m);
   }
-  inner_jacobi(M, J, a.tol, false, QDWHP_JACOBI_INNER);
+  const int rotated = inner_jacobi(M, J, a.tol, false, QDWHP_JACOBI_INNER);
+  if (t == 0) a.act[blockIdx.x] = rotated > 0;
   // off-diagonal part of the rotated sub-problem goes back now, freeing M
   for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
@@ -267,6 +269,7 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   int64_t rem = lin;
   while (rem >= np - 1 - P) { rem -= np - 1 - P; ++P; }
   const int Q = P + 1 + (int)rem;
+  if (!a.act[P] && !a.act[Q]) return;   // both rotations are the identity
   int pP, qP, pQ, qQ;
   round_robin(a.nb, a.step, P, &pP, &qP);
   round_robin(a.nb, a.step, Q, &pQ, &qQ);
@@ -298,9 +301,10 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
 // (a broadcast).  Rows of a workgroup are consecutive, so each column access
 // is coalesced.
 __global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv, int64_t rows, int nb,
-                                                         int step, const double* Jb) {
+                                                         int step, const double* Jb, const int* act) {
   __shared__ double JQ[P2 * P2];   // column-major J_Q
   const int Q = blockIdx.y;
+  if (!act[Q]) return;             // identity rotation
   int p, q;
   round_robin(nb, step, Q, &p, &q);
   const double* J = Jb + (int64_t)Q * P2 * P2;
@@ -330,7 +334,7 @@ __global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv,
 struct SvjArgs {
   double* R; int64_t ldr; int64_t rows; int nb;
   double* V; int64_t ldv; int64_t vrows;
-  double* Jb; double tol; double* offmax; int sweep; int step;
+  double* Jb; double tol; double* offmax; int* act; int sweep; int step;
 };
 
 // One-sided step, split over rows so that every round keeps the device busy:
@@ -413,7 +417,8 @@ __global__ __launch_bounds__(NT) void svj_solve_kernel(SvjArgs a, const double* 
     for (int i = 1; i < NT / 64; ++i) m = fmax(m, red[i]);
     atomic_max_nonneg(a.offmax + a.sweep, m);
   }
-  inner_jacobi(M, J, a.tol, true, QDWHP_JACOBI_INNER);
+  const int rotated = inner_jacobi(M, J, a.tol, true, QDWHP_JACOBI_INNER);
+  if (t == 0) a.act[blockIdx.x] = rotated > 0;
   orthonormalize(J, M, X);
   double* Jout = a.Jb + (int64_t)blockIdx.x * P2 * P2;
   for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[e % P2][e / P2];
@@ -473,13 +478,30 @@ __global__ void scale_cols_kernel(double* R, int64_t ldr, int64_t rows, const do
   }
 }
 
-__global__ void frob_kernel(const double* H, int64_t ldh, int64_t n, double* out) {
+// ||H||_F in two fixed-order stages: column-strided partial sums per
+// workgroup, then one workgroup adds the partials.
+constexpr int FROB_WG = 256;
+__global__ void frob_part_kernel(const double* H, int64_t ldh, int64_t n, double* part) {
   __shared__ double red[256];
   double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < n * n; e += 256) {
-    const double v = H[(e % n) + (e / n) * ldh];
-    acc += v * v;
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x)
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+      const double v = H[i + j * ldh];
+      acc += v * v;
+    }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void frob_final_kernel(const double* part, int np, double* out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
@@ -522,12 +544,18 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   double* offmax = Jb + (int64_t)(nb / 2) * P2 * P2;
   int64_t* rank = (int64_t*)(offmax + 64);
   double* fro = (double*)(rank + np);
+  int* act = (int*)(fro + 8);
   fill(Hp, np, np, np, 0.0, 0.0, s);
   copy(H, ldh, Hp, np, n, n, s);
   fill(Vp, np, np, np, 0.0, 1.0, s);
   QDWHP_HIP(hipMemsetAsync(offmax, 0, 64 * sizeof(double), s));
-  frob_kernel<<<1, 256, 0, s>>>(Hp, np, np, fro);
-  QDWHP_LAUNCH_CHECK();
+  {   // the pair-rotation buffer is free until the sweeps start
+    const int g = (int)std::min<int64_t>(FROB_WG, np);
+    frob_part_kernel<<<g, 256, 0, s>>>(Hp, np, np, Jb);
+    QDWHP_LAUNCH_CHECK();
+    frob_final_kernel<<<1, 256, 0, s>>>(Jb, g, fro);
+    QDWHP_LAUNCH_CHECK();
+  }
   double hf = 0.0;
   QDWHP_HIP(hipMemcpyAsync(&hf, fro, sizeof(double), hipMemcpyDeviceToHost, s));
   QDWHP_HIP(hipStreamSynchronize(s));
@@ -537,6 +565,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   // eigenvector's residual is then at most ~2u ||H||_F
   a.tol = 2.0 * 1.1102230246251565e-16 * (hf > 0.0 ? hf / std::sqrt((double)n) : 1.0);
   a.offmax = offmax;
+  a.act = act;
   const int np2 = nb / 2;
   const int64_t ntiles = (int64_t)np2 * (np2 - 1) / 2;
   int sweeps = -1;
@@ -551,7 +580,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
         sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
         QDWHP_LAUNCH_CHECK();
       }
-      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb);
+      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
       QDWHP_LAUNCH_CHECK();
     }
     double off = 0.0;
@@ -589,13 +618,14 @@ int gesvj(double* R, int64_t rows, int64_t n, int64_t ldr, double* S, double* V,
   double* nrm = (double*)(rank + np);
   double* part = nrm + np;
   const int nchunk = (int)cdiv(rows, GR);
+  int* act = (int*)(part + (int64_t)(nb / 2) * nchunk * P2 * P2);
   fill(Rp, rows, np, rows, 0.0, 0.0, s);
   copy(R, ldr, Rp, rows, rows, n, s);
   fill(Vp, np, np, np, 0.0, 1.0, s);
   QDWHP_HIP(hipMemsetAsync(offmax, 0, 64 * sizeof(double), s));
   SvjArgs a;
   a.R = Rp; a.ldr = rows; a.rows = rows; a.nb = nb; a.V = Vp; a.ldv = np; a.vrows = n;
-  a.Jb = Jb; a.tol = 4e-16 * std::sqrt((double)rows); a.offmax = offmax;
+  a.Jb = Jb; a.tol = 4e-16 * std::sqrt((double)rows); a.offmax = offmax; a.act = act;
   int sweeps = -1;
   double prev = 0.0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
@@ -606,9 +636,9 @@ int gesvj(double* R, int64_t rows, int64_t n, int64_t ldr, double* S, double* V,
       QDWHP_LAUNCH_CHECK();
       svj_solve_kernel<<<nb / 2, NT, 0, s>>>(a, part, nchunk);
       QDWHP_LAUNCH_CHECK();
-      cols_update_kernel<<<dim3((unsigned)cdiv(rows, NT), nb / 2), NT, 0, s>>>(Rp, rows, rows, nb, st, Jb);
+      cols_update_kernel<<<dim3((unsigned)cdiv(rows, NT), nb / 2), NT, 0, s>>>(Rp, rows, rows, nb, st, Jb, a.act);
       QDWHP_LAUNCH_CHECK();
-      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), nb / 2), NT, 0, s>>>(Vp, np, n, nb, st, Jb);
+      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), nb / 2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
       QDWHP_LAUNCH_CHECK();
     }
     double off = 0.0;
