@@ -287,12 +287,14 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   __syncthreads();
   lds_mm(Y, false, JQ, X, 1.0, nullptr, 0.0);    // X = Y J_Q
   __syncthreads();
+  // both copies are written with consecutive lanes on consecutive rows
   for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
-    const int64_t gi = blk_index(pP, qP, i), gj = blk_index(pQ, qQ, j);
-    const double v = X[i][j];
-    a.H[gi + gj * a.ldh] = v;
-    a.H[gj + gi * a.ldh] = v;
+    a.H[blk_index(pP, qP, i) + blk_index(pQ, qQ, j) * a.ldh] = X[i][j];
+  }
+  for (int e = t; e < P2 * P2; e += NT) {
+    const int j = e % P2, i = e / P2;
+    a.H[blk_index(pQ, qQ, j) + blk_index(pP, qP, i) * a.ldh] = X[i][j];
   }
 }
 

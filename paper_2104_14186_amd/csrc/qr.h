@@ -1,5 +1,7 @@
 // Householder QR building blocks (see qr.hip).
 #pragma once
+#include <functional>
+
 #include "common.h"
 
 namespace qdwhp {
@@ -15,10 +17,15 @@ int64_t qr_scratch_doubles(int64_t m, int64_t n);
 QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n);
 inline int64_t qr_t_doubles(int64_t n) { return cdiv(n > 0 ? n : 1, QB) * QB * QB; }
 
+// Called after each panel (columns c0 .. c0+w-1 factored, their T built,
+// trailing columns not yet updated); returning true ends the factorization.
+using PanelWatch = std::function<bool(int64_t c0, int w)>;
+
 // In-place QR of A (m x n, m >= n): R above, reflectors below, tau[n];
 // per-panel T factors in Tall (QB x QB each, zero below the diagonal).
-void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-           const QrScratch& sc, hipStream_t s);
+// Returns the number of columns factored (n unless `watch` stopped early).
+int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch = nullptr);
 // Q (m x q) = H_1 ... H_upto E, E = columns c0 .. c0+q-1 of the identity.
 // C (m x q) <- H_1 ... H_upto C.
 void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,

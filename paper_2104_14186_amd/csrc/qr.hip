@@ -239,8 +239,8 @@ QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
   return s;
 }
 
-void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-           const QrScratch& sc, hipStream_t s) {
+int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch) {
   for (int64_t c0 = 0; c0 < n; c0 += QB) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
     const int64_t h = m - c0;
@@ -263,6 +263,7 @@ void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Ta
     double* T = Tall + (c0 / QB) * QB * QB;
     build_t_kernel<<<1, QB, 0, s>>>(sc.G, QB, tau + c0, T, QB, w);
     QDWHP_LAUNCH_CHECK();
+    if (watch && (*watch)(c0, w)) return c0 + w;   // the caller needs no further columns
     const int64_t nc = n - c0 - w;
     if (nc > 0) {
       double* Cm = A + c0 + (c0 + w) * lda;
@@ -281,6 +282,7 @@ void geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Ta
       dgemm(g3, s);
     }
   }
+  return n;
 }
 
 void orgqr(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,

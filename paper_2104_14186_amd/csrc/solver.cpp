@@ -244,6 +244,25 @@ double table1_iter_flops(const std::vector<DwhStep>& sched, double m, double n) 
   return f;
 }
 
+// Projector QR watch: after each panel, read its part of diag(R) (final
+// once the panel is factored) and stop at the first panel holding an entry
+// below tol, or a non-finite one: ind is the first such index, and only the
+// reflectors before it are used (Q2 = H_1 ... H_{ind-1} [0; I]).
+PanelWatch diag_watch(double* B, int64_t ldb, double* dbuf, double tol, std::vector<double>* d, hipStream_t s) {
+  return [=](int64_t c0, int w) -> bool {
+    diagonal(B + c0 + c0 * ldb, ldb, w, dbuf, s);
+    std::vector<double> part(w);
+    QDWHP_HIP(hipMemcpyAsync(part.data(), dbuf, sizeof(double) * w, hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipStreamSynchronize(s));
+    bool stop = false;
+    for (double v : part) {
+      d->push_back(v);
+      if (!std::isfinite(v) || std::fabs(v) < tol) stop = true;
+    }
+    return stop;
+  };
+}
+
 // The DWH steps of a solve, then the FP64 polish plan (0 = Newton-Schulz,
 // 1 = Halley (3,1,3) in Cholesky form) of the mixed-precision variant.
 // With opts.graphs the sequence is captured once per (buffers, sizes, step
@@ -411,11 +430,10 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       ev.mark(2, s);
       // ---- projector (X + I)/2, QR, ind (Algorithm 1)
       half_plus_identity(X, n, P.Z, n, n, s);
-      geqrf(P.Z, n, n, n, P.tau, P.Tall, P.qrs, s);
-      diagonal(P.Z, n, n, P.diag, s);
-      std::vector<double> d(n);
+      std::vector<double> d;
+      const PanelWatch watch = diag_watch(P.Z, n, P.diag, o.tol, &d, s);
+      geqrf(P.Z, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
       int hflags[8];
-      QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * n, hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipStreamSynchronize(s));
       ev.mark(3, s);
@@ -605,11 +623,10 @@ int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t 
       gb.B = X; gb.ldb = mm; gb.C = P.Z; gb.ldc = nn; gb.tiles = TILES_UPPER;
       dgemm(gb, s);
       mirror_upper(P.Z, nn, nn, s);
-      geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s);
-      diagonal(P.Z, nn, nn, P.diag, s);
-      std::vector<double> d(nn);
+      std::vector<double> d;
+      const PanelWatch watch = diag_watch(P.Z, nn, P.diag, o.tol, &d, s);
+      geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s, &watch);
       int hflags[8];
-      QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipStreamSynchronize(s));
       ev.mark(3, s);
