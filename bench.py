@@ -38,7 +38,101 @@ def parse():
     p.add_argument("--fraction", type=float, default=0.2)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to aim for")
+    p.add_argument("--no-serve", action="store_true", help="skip the batched and served request-mix legs")
+    p.add_argument("--gemm-probe", action="store_true",
+                   help="only the 1 GiB copy and the two dominant n^3 GEMM shapes of a Cholesky step "
+                        "(for HBM byte counters), then exit")
+    p.add_argument("--copy-probe", action="store_true",
+                   help="first copy 1 GiB device to device (calibrates HBM byte counters under rocprofv3 --pmc)")
+    p.add_argument("--serve-requests", type=int, default=48)
+    p.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate (requests/s)")
     return p.parse_args()
+
+
+def build_mix(torch, trace):
+    """Device matrices for a request trace (planted spectra, built before timing)."""
+    from synthetic import eig_uniform, svd_geometric
+    import numpy as np
+    dev = torch.device("cuda")
+    out = []
+    for r in trace:
+        if r["kind"] == "eig":
+            A, lam = eig_uniform(r["n"], r["seed"], device=dev)
+            out.append((dict(type="eig", A=A, fraction=r["fraction"]), np.sort(lam)[::-1]))
+        else:
+            A, sig = svd_geometric(r["n"], r["n"], r["seed"], kappa=r["kappa"], device=dev)
+            out.append((dict(type="svd", A=A, k=r["k"]), np.asarray(sig)))
+    return out
+
+
+def _vals(spec, res):
+    return (res[0] if spec["type"] == "eig" else res[1]).cpu().numpy()
+
+
+def _relerr(spec, res, exact):
+    import numpy as np
+    v = _vals(spec, res)
+    e = exact[:len(v)]
+    return float(np.max(np.abs(v - e) / np.abs(e)))
+
+
+def batched_leg(q, torch, mix):
+    """The same ragged batch solved one call at a time and with qdwhp_batched."""
+    specs = [m[0] for m in mix]
+    for sp in specs[:2]:
+        (q.eig(sp["A"], fraction=sp["fraction"]) if sp["type"] == "eig" else q.svd(sp["A"], sp["k"]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [(q.eig(sp["A"], fraction=sp["fraction"]) if sp["type"] == "eig" else q.svd(sp["A"], sp["k"]))
+           for sp in specs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    q.batched(specs[:4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = q.batched(specs)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    same = all(all(bool((x == y).all()) for x, y in zip(a, b)) for a, b in zip(seq, res))
+    err = max(_relerr(sp, r, m[1]) for sp, r, m in zip(specs, res, mix))
+    return {"problems": len(specs), "sequential_s": t_seq, "batched_s": t_bat,
+            "sequential_solves_per_s": len(specs) / t_seq, "batched_solves_per_s": len(specs) / t_bat,
+            "speedup": t_seq / t_bat, "lanes": q.tune_get("batch.lanes", 8),
+            "bitwise_equal_to_standalone": same, "max_rel_value_err": err}
+
+
+def serve_leg(q, torch, mix, trace, precision):
+    """Open-loop Poisson arrivals into the request server; latency = arrival to results ready."""
+    import numpy as np
+    opts = q.default_opts(precision=precision)
+    lat, qms, errs, done_t = [], [], [], []
+    with q.Server(arena_bytes=64 << 30, lanes=0, opts=opts) as srv:
+        warm = srv.submit(mix[0][0])
+        srv.poll(warm)
+        t0 = time.perf_counter()
+        tickets = []
+        for (spec, exact), r in zip(mix, trace):
+            delay = r["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(spec))
+        failed = []
+        for i, ((spec, exact), tk) in enumerate(zip(mix, tickets)):
+            try:
+                res, info, l, qm = srv.poll(tk)
+            except q.QdwhpError as e:
+                failed.append((i, e.status))
+                continue
+            lat.append(l); qms.append(qm)
+            done_t.append(time.perf_counter() - t0)
+            errs.append(_relerr(spec, res, exact))
+        span = time.perf_counter() - t0
+    lat = np.array(lat)
+    return {"precision": "fp64" if precision == 0 else "mixed_fp32", "requests": len(lat),
+            "offered_rate_per_s": len(trace) / trace[-1]["arrival"],
+            "solves_per_s": len(lat) / span, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_queue_ms": float(np.mean(qms)),
+            "max_rel_value_err": float(max(errs)), "failed": failed}
 
 
 def cpu_baseline(n_full, fraction, budget):
@@ -70,6 +164,33 @@ def cpu_baseline(n_full, fraction, budget):
                        f"max rel value err {err:.1e}")
 
 
+def gemm_probe(torch, dev, n):
+    """Copy calibration (1 GiB read + written, twice) and the dominant GEMMs of
+    a Cholesky-based step at size n: Z = X^T X (upper tiles) and X W (full)."""
+    import ctypes
+    import paper_2104_14186_amd as q
+    x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.mul(x, 2.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    X = torch.empty((n, n), dtype=torch.float64, device=dev)
+    W = torch.empty((n, n), dtype=torch.float64, device=dev)
+    Z = torch.empty((n, n), dtype=torch.float64, device=dev)
+    X.fill_(1.0 / n)
+    W.fill_(1.0 / n)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    L = q.lib()
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    for _ in range(2):
+        assert L.qdwhp_dgemm(1, 0, n, n, n, 1.0, p(X), n, p(X), n, 0.0, p(Z), n, 1, st) == 0
+        assert L.qdwhp_dgemm(0, 0, n, n, n, 1.0, p(X), n, p(W), n, 0.0, p(Z), n, 0, st) == 0
+    torch.cuda.synchronize()
+    print(json.dumps({"gemm_probe": n}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -81,6 +202,17 @@ def main():
     from synthetic import eig_clustered
 
     dev = torch.device("cuda:0")
+    if args.gemm_probe:
+        gemm_probe(torch, dev, args.n)
+        return
+    if args.copy_probe:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        x.fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)                       # 1 GiB read + 1 GiB written
+        torch.mul(x, 2.0, out=y)         # the same through an elementwise kernel
+        torch.cuda.synchronize()
+        del x, y
     n, f = args.n, args.fraction
     print(f"[bench] generating n={n} planted matrix", file=sys.stderr, flush=True)
     A, lam = eig_clustered(n, 1002, device=dev)
@@ -161,6 +293,19 @@ def main():
                      "launches": glaunch, "kernel_ms_per_step": gms / args.steps,
                      "algorithmic_flops_per_launch": gflops / max(glaunch, 1)},
     }
+    if not args.no_serve:
+        from synthetic import request_trace, CONFIG_SEEDS
+        trace = request_trace(args.serve_requests, args.serve_rate, CONFIG_SEEDS["trace"])
+        print("[bench] building request mix", file=sys.stderr, flush=True)
+        mix = build_mix(torch, trace)
+        print("[bench] batched leg", file=sys.stderr, flush=True)
+        out["batched"] = batched_leg(q, torch, mix[:24])
+        print("[bench] served leg fp64", file=sys.stderr, flush=True)
+        out["serving"] = serve_leg(q, torch, mix, trace, q.FP64)
+        print("[bench] served leg mixed", file=sys.stderr, flush=True)
+        out["serving_mixed"] = serve_leg(q, torch, mix, trace, q.MIXED_FP32)
+        out["serving"]["trace"] = (f"{len(trace)} requests, Poisson {args.serve_rate}/s, 60% EIG / 40% SVD, "
+                                   "n in {256..4096}, fraction U[1%,20%], SVD kappa 10^U[0,12]")
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, f, args.cpu_budget)
