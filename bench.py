@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--copy-probe", action="store_true",
                    help="first copy 1 GiB device to device (calibrates HBM byte counters under rocprofv3 --pmc)")
     p.add_argument("--serve-requests", type=int, default=48)
-    p.add_argument("--serve-rate", type=float, default=8.0, help="Poisson arrival rate (requests/s)")
+    p.add_argument("--serve-rate", type=float, default=3.0, help="Poisson arrival rate (requests/s)")
     return p.parse_args()
 
 
