@@ -8,7 +8,8 @@
 //   * two-sided (symmetric H): the 32x32 diagonal sub-problem of each pair
 //     gets one cyclic Jacobi sweep in LDS (16 disjoint rotations per round),
 //     giving an orthogonal J; then H <- J^T H J tile by tile (tile
-//     (P,Q) becomes J_P^T H_PQ J_Q) and V <- V J;
+//     (P,Q) becomes J_P^T H_PQ J_Q; H is kept block-upper, so each
+//     off-diagonal block is read and written once) and V <- V J;
 //   * one-sided (R): each pair forms the Gram matrix of its 32 columns,
 //     diagonalises it the same way and rotates the columns of R and V by J,
 //     making them mutually orthogonal.
@@ -207,6 +208,42 @@ __device__ inline int64_t blk_index(int p, int q, int i) {  // pair (p,q) local 
   return (i < JB) ? (int64_t)p * JB + i : (int64_t)q * JB + (i - JB);
 }
 
+// H is kept block-upper: a JB x JB block (bi, bj) is current only for
+// bi <= bj (diagonal blocks in full); block (bi, bj) with bi > bj is read as
+// the transpose of block (bj, bi) and never written.  Each sub-block of a
+// tile moves with one element per thread, the contiguous index on
+// consecutive lanes whichever way the block is stored.
+static_assert(JB * JB == NT, "one element of a JB x JB block per thread");
+
+__device__ inline void load_tile(const double* H, int64_t ld, int r0, int r1, int c0, int c1,
+                                 double (*X)[LDM]) {
+  const int a = threadIdx.x % JB, b = threadIdx.x / JB;
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+    const int si = sb & 1, sj = sb >> 1;
+    const int bi = si ? r1 : r0, bj = sj ? c1 : c0;
+    if (bi <= bj) X[si * JB + a][sj * JB + b] = H[(int64_t)bi * JB + a + ((int64_t)bj * JB + b) * ld];
+    else X[si * JB + b][sj * JB + a] = H[(int64_t)bj * JB + a + ((int64_t)bi * JB + b) * ld];
+  }
+}
+
+// Writes the sub-blocks of X that are stored (bi <= bj), transposing those
+// with bi > bj into their stored position; with skip_lower, blocks with
+// bi > bj are left alone (their transposes are written from the same tile);
+// with skip_diag, the diagonal entries of diagonal blocks are not written.
+__device__ inline void store_tile(double* H, int64_t ld, int r0, int r1, int c0, int c1,
+                                  const double (*X)[LDM], bool skip_lower, bool skip_diag = false) {
+  const int a = threadIdx.x % JB, b = threadIdx.x / JB;
+#pragma unroll
+  for (int sb = 0; sb < 4; ++sb) {
+    const int si = sb & 1, sj = sb >> 1;
+    const int bi = si ? r1 : r0, bj = sj ? c1 : c0;
+    if (skip_diag && bi == bj && a == b) continue;
+    if (bi <= bj) H[(int64_t)bi * JB + a + ((int64_t)bj * JB + b) * ld] = X[si * JB + a][sj * JB + b];
+    else if (!skip_lower) H[(int64_t)bj * JB + a + ((int64_t)bi * JB + b) * ld] = X[si * JB + b][sj * JB + a];
+  }
+}
+
 // One workgroup per pair: gather the pair's diagonal sub-problem,
 // diagonalise, re-orthonormalise J, store J and write back the rotated
 // sub-problem with its diagonal recomputed as diag(J^T M0 J).
@@ -219,11 +256,12 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
   const int t = threadIdx.x;
   int p, q;
   round_robin(a.nb, a.step, blockIdx.x, &p, &q);
+  load_tile(a.H, a.ldh, p, q, p, q, M);
+  __syncthreads();
   double off = 0.0;
   for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
-    const double v = a.H[blk_index(p, q, i) + blk_index(p, q, j) * a.ldh];
-    M[i][j] = v;
+    const double v = M[i][j];
     M0[i][j] = v;
     J[i][j] = (i == j) ? 1.0 : 0.0;
     if (i != j) off = fmax(off, fabs(v));
@@ -238,11 +276,9 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
   }
   const int rotated = inner_jacobi(M, J, a.tol, false, QDWHP_JACOBI_INNER);
   if (t == 0) a.act[blockIdx.x] = rotated > 0;
-  // off-diagonal part of the rotated sub-problem goes back now, freeing M
-  for (int e = t; e < P2 * P2; e += NT) {
-    const int i = e % P2, j = e / P2;
-    if (i != j) a.H[blk_index(p, q, i) + blk_index(p, q, j) * a.ldh] = M[i][j];
-  }
+  // the rotated sub-problem goes back now (its diagonal is rewritten below
+  // from the re-orthonormalised J), freeing M
+  store_tile(a.H, a.ldh, p, q, p, q, M, true, true);
   __syncthreads();
   orthonormalize(J, T, M);
   // diagonal of J^T M0 J with the orthonormalised J: T = M0 J, d_i = sum_k J[k][i] T[k][i]
@@ -276,9 +312,9 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   const int t = threadIdx.x;
   const double* JbP = a.Jb + (int64_t)P * P2 * P2;
   const double* JbQ = a.Jb + (int64_t)Q * P2 * P2;
+  load_tile(a.H, a.ldh, pP, qP, pQ, qQ, X);
   for (int e = t; e < P2 * P2; e += NT) {
     const int i = e % P2, j = e / P2;
-    X[i][j] = a.H[blk_index(pP, qP, i) + blk_index(pQ, qQ, j) * a.ldh];
     JP[i][j] = JbP[e];
     JQ[i][j] = JbQ[e];
   }
@@ -287,15 +323,9 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   __syncthreads();
   lds_mm(Y, false, JQ, X, 1.0, nullptr, 0.0);    // X = Y J_Q
   __syncthreads();
-  // both copies are written with consecutive lanes on consecutive rows
-  for (int e = t; e < P2 * P2; e += NT) {
-    const int i = e % P2, j = e / P2;
-    a.H[blk_index(pP, qP, i) + blk_index(pQ, qQ, j) * a.ldh] = X[i][j];
-  }
-  for (int e = t; e < P2 * P2; e += NT) {
-    const int j = e % P2, i = e / P2;
-    a.H[blk_index(pQ, qQ, j) + blk_index(pP, qP, i) * a.ldh] = X[i][j];
-  }
+  // pair blocks of P and Q are disjoint: every sub-block has exactly one
+  // stored copy, written from here
+  store_tile(a.H, a.ldh, pP, qP, pQ, qQ, X, false);
 }
 
 // V[:, pair Q] <- V[:, pair Q] J_Q: one thread per row holds the row's 2JB
