@@ -158,12 +158,15 @@ int qdwhp_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
  * C is m x n, op(A) m x k, op(B) k x n, all column-major FP64 on the device.
  * The dense product behind every step of the method (Gram matrix of Eq. (3),
  * Q1 Q2^T of Eq. (2), the Rayleigh-Ritz projections of Algorithms 1 and 2).
- * flags bit 0 (QDWHP_GEMM_UPPER): compute only the 128x128 tiles of C that
- * meet the upper triangle (C square; the strictly-lower part of diagonal
- * tiles is written, other lower tiles are left untouched).
+ * flags bit 0 (QDWHP_GEMM_UPPER): C is square and only its upper triangle
+ * is defined on exit (only the output tiles meeting it are computed; parts
+ * of the strictly-lower triangle may be overwritten).
  * flags bit 1 (QDWHP_GEMM_F32): operands are rounded to FP32 and multiplied
- * on the FP32 matrix cores with FP32 accumulation; alpha, beta and C stay
- * FP64 (the mixed-precision Cholesky-based step).
+ * on the FP32 matrix cores, the FP32 sums folded into FP64 every 32 terms of
+ * k; alpha, beta and C stay FP64 (the mixed-precision Cholesky-based step).
+ * Leading dimensions must be below 2^21 (QDWHP_ERR_HIP otherwise).  The
+ * result does not depend on the tile size chosen (tuning key
+ * "gemm.small_tiles").
  */
 #define QDWHP_GEMM_UPPER 1
 #define QDWHP_GEMM_F32   2
@@ -198,7 +201,9 @@ int qdwhp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau,
  * Q(:, c0:c0+q) columns of Q = H_1 ... H_n from qdwhp_geqrf output, written
  * to Q (m x q, ldq >= m): applies the reflectors to the columns c0.. of the
  * identity (the thin Q of Eq. (2) for c0 = 0, q = n; the trailing columns Q2
- * of Algorithm 1 for c0 = ind - 1).  work: qdwhp_geqrf_workspace(m, n).
+ * of Algorithm 1 for c0 = ind - 1).  work must be the workspace of the
+ * qdwhp_geqrf call that factored A, unchanged since: it holds the block
+ * reflector (T) factors, which carry tau (the tau argument is not read).
  */
 int qdwhp_orgqr(const double* A, int64_t m, int64_t n, int64_t lda,
                 const double* tau, int64_t c0, int64_t q, double* Q, int64_t ldq,
@@ -208,7 +213,9 @@ int qdwhp_orgqr(const double* A, int64_t m, int64_t n, int64_t lda,
  * All eigenpairs of the symmetric n x n matrix H by parallel-order block
  * Jacobi (the Rayleigh-Ritz solve of Algorithm 1): on exit w[n] holds the
  * eigenvalues in descending order and W (n x n, ldw >= n) the eigenvectors.
- * H is overwritten.  work: qdwhp_syev_workspace(n) bytes.
+ * H is read only (both triangles).  work: qdwhp_syev_workspace(n) bytes.
+ * *sweeps (optional) receives the sweep count; QDWHP_ERR_NOCONV if the
+ * stopping rule was not met within 60 sweeps.
  */
 size_t qdwhp_syev_workspace(int64_t n);
 int qdwhp_syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw,
@@ -216,8 +223,11 @@ int qdwhp_syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t 
 
 /*
  * All singular triplets of the square n x n matrix R by one-sided block
- * Jacobi (the small SVD of Algorithm 2): R is overwritten by U diag(S),
- * S[n] descending, V (n x n).  work: qdwhp_gesvj_workspace(n) bytes.
+ * Jacobi (the small SVD of Algorithm 2): R is overwritten by U (columns
+ * of unit norm, ordered like S), S[n] descending, V (n x n, ldv >= n).
+ * work: qdwhp_gesvj_workspace(n) bytes.  *sweeps (optional) receives the
+ * sweep count; QDWHP_ERR_NOCONV if the stopping rule was not met within 60
+ * sweeps.
  */
 size_t qdwhp_gesvj_workspace(int64_t n);
 int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double* V, int64_t ldv,
