@@ -61,23 +61,52 @@ __device__ inline double block_sum(double v, double* red) {
   return s;
 }
 
+// out[c] = sum over rows r0 <= r < r1 of Qr[r + c ldq] * w[r] for c < ncol,
+// 32 columns per pass: each thread keeps its partial sums in registers, one
+// wave reduction per column and one barrier per pass.  The arithmetic order
+// equals block_sum applied column by column.  red holds LZ_T/64 x 32 values.
+__device__ inline void block_dots(const double* Qr, int64_t ldq, int64_t r0, int64_t r1, const double* w,
+                                  int ncol, double* red, double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int c0 = 0; c0 < ncol; c0 += 32) {
+    double part[32];
+#pragma unroll
+    for (int k = 0; k < 32; ++k) part[k] = 0.0;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += LZ_T) {
+      const double x = w[r];
+#pragma unroll
+      for (int k = 0; k < 32; ++k)
+        if (c0 + k < ncol) part[k] += Qr[r + (int64_t)(c0 + k) * ldq] * x;
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k)
+      for (int o = 32; o > 0; o >>= 1) part[k] += __shfl_xor(part[k], o);
+    __syncthreads();
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 32; ++k) red[wv * 32 + k] = part[k];
+    __syncthreads();
+    if (threadIdx.x < 32 && c0 + (int)threadIdx.x < ncol) {
+      double sm = 0.0;
+      for (int i = 0; i < LZ_T / 64; ++i) sm += red[i * 32 + threadIdx.x];
+      out[c0 + threadIdx.x] = sm;
+    }
+  }
+  __syncthreads();
+}
+
 // part[run][chunk][c] = sum over the chunk's rows of Q_run[r][c] * w_run[r], c < ncol.
 __global__ __launch_bounds__(LZ_T) void dots_kernel(const double* Q, int64_t n, int64_t qstride,
                                                     const double* W, int64_t wstride, int ncol,
                                                     double* part, int nchunk, const int* active) {
-  __shared__ double red[LZ_T / 64];
+  __shared__ double red[LZ_T / 64 * 32];
   const int run = blockIdx.y, ch = blockIdx.x;
   if (active && !active[run]) return;
   const double* Qr = Q + run * qstride;
   const double* w = W + run * wstride;
   const int64_t r0 = (int64_t)ch * LZ_ROWS;
   const int64_t r1 = (r0 + LZ_ROWS < n) ? r0 + LZ_ROWS : n;
-  for (int c = 0; c < ncol; ++c) {
-    double acc = 0.0;
-    for (int64_t r = r0 + threadIdx.x; r < r1; r += LZ_T) acc += Qr[r + c * n] * w[r];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) part[((int64_t)run * nchunk + ch) * 128 + c] = s;
-  }
+  block_dots(Qr, n, r0, r1, w, ncol, red, part + ((int64_t)run * nchunk + ch) * 128);
 }
 
 // w_run <- w_run - Q_run d, with d = sum over chunks of part (fixed order).
@@ -164,6 +193,89 @@ __global__ void restart_gaussian_kernel(double* W, int64_t n, uint64_t seed, int
   double* w = W + run * n;
   w[2 * p] = rad * cs;
   if (2 * p + 1 < n) w[2 * p + 1] = rad * sn;
+}
+
+// Gaussian entry r of stream `stream` (the layout of gaussian_kernel).
+__device__ inline double gaussian_entry(int64_t r, uint64_t seed, uint64_t stream) {
+  const int64_t p = r >> 1;
+  uint32_t c[4] = {(uint32_t)p, (uint32_t)((uint64_t)p >> 32), (uint32_t)stream, 0u};
+  philox10(c, seed);
+  const double sc = 1.1102230246251565e-16;
+  const double u1 = ((double)(c[0] >> 5) * 67108864.0 + (double)(c[1] >> 6) + 0.5) * sc;
+  const double u2 = ((double)(c[2] >> 5) * 67108864.0 + (double)(c[3] >> 6) + 0.5) * sc;
+  const double rad = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos(6.283185307179586 * u2, &sn, &cs);
+  return (r & 1) ? rad * sn : rad * cs;
+}
+
+// Two passes of classical Gram-Schmidt of w against q_0..q_j by one
+// workgroup (rows r = t + LZ_T i of each thread), in the arithmetic order of
+// dots_kernel / sub_kernel with a single row chunk; d0 (optional) receives
+// the first pass's coefficients.
+__device__ inline void cgs2_block(const double* Qr, int64_t n, double* w, int ncol, double* d,
+                                  double* red, double* d0) {
+  for (int pass = 0; pass < 2; ++pass) {
+    block_dots(Qr, n, 0, n, w, ncol, red, d);
+    if (pass == 0 && d0)
+      for (int c = threadIdx.x; c < ncol; c += LZ_T) d0[c] = d[c];
+    for (int64_t r = threadIdx.x; r < n; r += LZ_T) {
+      double acc = w[r];
+      for (int c = 0; c < ncol; ++c) acc -= Qr[r + c * n] * d[c];
+      w[r] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// Everything of Lanczos step j after the operator product, for n <= LZ_ROWS,
+// in one launch (one workgroup per run): re-orthogonalisation, norm, the
+// step bookkeeping of step_kernel, the restart of a run that broke down, and
+// q_{j+1}.  Same results as the multi-launch sequence.
+__global__ __launch_bounds__(LZ_T) void step_fused_kernel(double* Q, int64_t n, int64_t qstride, double* W,
+                                                          int nv, int m, int j, uint64_t seed, double* dvec,
+                                                          double* alpha, double* beta, double* amax,
+                                                          int* active) {
+  __shared__ double red[LZ_T / 64 * 32];
+  __shared__ double d[128];
+  __shared__ double d0[128];
+  __shared__ double nrm_s;
+  __shared__ int restart_s;
+  const int run = blockIdx.x;
+  double* Qr = Q + run * qstride;
+  double* w = W + run * n;
+  (void)dvec;
+  cgs2_block(Qr, n, w, j + 1, d, red, d0);
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += LZ_T) acc += w[r] * w[r];
+  const double ss = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    const double b = sqrt(ss);
+    const double a = d0[j];   // first-pass coefficient of q_j
+    alpha[run * m + j] = a;
+    const double am = fmax(amax[run], fabs(a) + (j > 0 ? beta[run * m + j - 1] : 0.0));
+    amax[run] = am;
+    int act = 0;
+    if (j == m - 1) beta[run * m + j] = b;
+    else if (b <= 1e-10 * am) { beta[run * m + j] = 0.0; act = 1; }
+    else beta[run * m + j] = b;
+    active[run] = act;
+    nrm_s = b;
+    restart_s = act;
+  }
+  __syncthreads();
+  double nr = nrm_s;
+  if (restart_s) {   // fresh random direction, orthogonalised against the basis
+    const uint64_t stream = (uint64_t)nv + (uint64_t)run * m + j;
+    for (int64_t r = threadIdx.x; r < n; r += LZ_T) w[r] = gaussian_entry(r, seed, stream);
+    __syncthreads();
+    cgs2_block(Qr, n, w, j + 1, d, red, nullptr);
+    double a2 = 0.0;
+    for (int64_t r = threadIdx.x; r < n; r += LZ_T) a2 += w[r] * w[r];
+    nr = sqrt(block_sum(a2, red));
+  }
+  double* qn = Qr + (int64_t)(j + 1) * n;
+  for (int64_t r = threadIdx.x; r < n; r += LZ_T) qn[r] = (nr > 0.0) ? w[r] / nr : 0.0;
 }
 
 // Eigenvalues of each run's m x m tridiagonal (diagonal alpha, off-diagonal
@@ -283,6 +395,11 @@ LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t se
   for (int j = 0; j < m; ++j) {
     // w = Op q_j for all runs (columns at stride qs)
     op.apply(Q + (int64_t)j * n, qs, Wv, n, tmp, s);
+    if (nchunk == 1) {   // one workgroup per run covers the vector: one launch for the rest
+      step_fused_kernel<<<nv, LZ_T, 0, s>>>(Q, n, qs, Wv, nv, m, j, seed, dvec, alpha, beta, amax, d_active);
+      QDWHP_LAUNCH_CHECK();
+      continue;
+    }
     // two passes of classical Gram-Schmidt against q_0..q_j
     for (int pass = 0; pass < 2; ++pass) {
       dots_kernel<<<gdots, LZ_T, 0, s>>>(Q, n, qs, Wv, n, j + 1, part, nchunk, nullptr);
