@@ -61,6 +61,20 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
   const double* piv_in = a.piv + ((j + 2) & 1) * QB;
   double* piv_out = a.piv + ((j + 1) & 1) * QB;
 
+  // One row per thread (panels up to QT * NWG_MAX rows): the row's values in
+  // columns j and j+1 .. j+CH are loaded first, so their latency overlaps the
+  // reduction of the statistics that define reflector j.
+  const bool one_row = (a.rpt == 1);
+  const int64_t r1 = (int64_t)g * QT + t;
+  const bool have1 = one_row && r1 < a.h;
+  const int jn1 = j + 1;
+  double pj = 0.0, pre[CH];
+  if (have1) {
+    if (j >= 0) pj = P[r1 + j * ld];
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) pre[cc] = (jn1 + cc < w) ? P[r1 + (int64_t)(jn1 + cc) * ld] : 0.0;
+  }
+
   double tau = 0.0, scale = 0.0, beta = 0.0;
   if (j >= 0) {
     {  // column c summed by two threads over alternate partials, 8 chains each
@@ -91,6 +105,74 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
     if (t < w && t > j) sh_w[t] = piv_in[t] + scale * sh_s[t];
     if (g == 0 && t == 0) a.tau[j] = tau;
     __syncthreads();
+  }
+
+  if (one_row) {
+    const int jn = jn1;
+    const int64_t r = have1 ? r1 : -1;
+    double v = 0.0;
+    if (r >= 0 && j >= 0) {
+      if (r > j) { v = pj * scale; P[r + j * ld] = v; }
+      else if (r == j) P[j + j * ld] = beta;
+    }
+    const bool below = (r >= 0 && j >= 0 && r > j), pivrow = (r >= 0 && j >= 0 && r == j);
+    const double f = below ? tau * v : (pivrow ? tau : 0.0);
+    double x = 0.0;
+    if (r >= 0 && jn < w) x = pre[0] - f * sh_w[jn];
+    const bool active = (r >= 0) && (r >= jn || pivrow);   // rows above the next pivot stay put
+    double cur[CH];
+#pragma unroll
+    for (int cc = 0; cc < CH; ++cc) cur[cc] = pre[cc];
+    for (int cb = jn; cb < w; cb += CH) {
+      double nxt[CH];
+      const int cbn = cb + CH;
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc)
+        nxt[cc] = (have1 && active && cbn + cc < w) ? P[r + (int64_t)(cbn + cc) * ld] : 0.0;
+      double acc[CH];
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) acc[cc] = 0.0;
+      if (active) {
+#pragma unroll
+        for (int cc = 0; cc < CH; ++cc) {
+          if (cb + cc < w) {
+            cur[cc] -= f * sh_w[cb + cc];
+            if (r > jn) acc[cc] += x * cur[cc];
+          }
+        }
+        if (below || pivrow) {
+#pragma unroll
+          for (int cc = 0; cc < CH; ++cc)
+            if (cb + cc < w) P[r + (int64_t)(cb + cc) * ld] = cur[cc];
+        }
+        if (r == jn) {
+#pragma unroll
+          for (int cc = 0; cc < CH; ++cc)
+            if (cb + cc < w) piv_out[cb + cc] = cur[cc];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) sh_acc[t][cc] = acc[cc];
+      __syncthreads();
+      {
+        const int cc = t & (CH - 1), seg = t / CH;
+        double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < CH; ++i) s4[i & 3] += sh_acc[seg * CH + i][cc];
+        sh_seg[seg][cc] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+      }
+      __syncthreads();
+      if (t < CH && cb + t < w) {
+        double sm = 0.0;
+#pragma unroll
+        for (int seg = 0; seg < QT / CH; ++seg) sm += sh_seg[seg][t];
+        part_out[(int64_t)g * QB + cb + t] = sm;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int cc = 0; cc < CH; ++cc) cur[cc] = nxt[cc];
+    }
+    return;
   }
 
   const int64_t rbase = (int64_t)g * QT * a.rpt;
