@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, dou
                                                      int bs, int* flag) {
   __shared__ double S[NB][NB + 1];
   __shared__ double X[NB][NB + 1];
-  __shared__ double piv;
+  __shared__ double rpiv;
+  __shared__ double rd[NB];
   const int t = threadIdx.x;
   for (int e = t; e < NB * NB; e += 256) {
     const int r = e % NB, c = e / NB;
@@ -44,12 +45,12 @@ __global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, dou
     if (t == 0) {
       double d = S[j][j];
       if (!(d > 0.0) || !isfinite(d)) { *flag = 1; d = 1.0; }
-      piv = sqrt(d);
-      S[j][j] = piv;
+      const double p = sqrt(d);
+      S[j][j] = p;
+      rpiv = 1.0 / p;
     }
     __syncthreads();
-    const double p = piv;
-    if (t > j && t < bs) S[j][t] /= p;
+    if (t > j && t < bs) S[j][t] *= rpiv;
     __syncthreads();
     for (int e = t; e < NB * NB; e += 256) {
       const int r = e % NB, c = e / NB;
@@ -57,14 +58,18 @@ __global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, dou
     }
     __syncthreads();
   }
-  // back substitution W X = I, one column of X per thread (X upper triangular)
+  // back substitution W X = I, one column of X per thread (X upper
+  // triangular); the diagonal reciprocals are formed once, so the dependent
+  // chain of each column has no division
+  if (t < bs) rd[t] = 1.0 / S[t][t];
+  __syncthreads();
   if (t < bs) {
     const int c = t;
-    X[c][c] = 1.0 / S[c][c];
+    X[c][c] = rd[c];
     for (int i = c - 1; i >= 0; --i) {
       double acc = 0.0;
       for (int k = i + 1; k <= c; ++k) acc += S[i][k] * X[k][c];
-      X[i][c] = -acc / S[i][i];
+      X[i][c] = -acc * rd[i];
     }
   }
   __syncthreads();
