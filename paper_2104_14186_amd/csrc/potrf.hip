@@ -52,9 +52,13 @@ __global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, dou
     __syncthreads();
     if (t > j && t < bs) S[j][t] *= rpiv;
     __syncthreads();
-    for (int e = t; e < NB * NB; e += 256) {
-      const int r = e % NB, c = e / NB;
-      if (r > j && r <= c && c < bs) S[r][c] -= S[j][r] * S[j][c];
+    // trailing update without branches, so the 16 independent read-modify-
+    // writes of a thread issue together
+#pragma unroll
+    for (int u = 0; u < NB * NB / 256; ++u) {
+      const int e = t + 256 * u, r = e % NB, c = e / NB;
+      const double f = (r > j && r <= c && c < bs) ? S[j][r] : 0.0;
+      S[r][c] -= f * S[j][c];
     }
     __syncthreads();
   }
@@ -67,9 +71,16 @@ __global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, dou
     const int c = t;
     X[c][c] = rd[c];
     for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= c; ++k) acc += S[i][k] * X[k][c];
-      X[i][c] = -acc * rd[i];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   // independent chains
+      int k = i + 1;
+      for (; k + 3 <= c; k += 4) {
+        a0 += S[i][k] * X[k][c];
+        a1 += S[i][k + 1] * X[k + 1][c];
+        a2 += S[i][k + 2] * X[k + 2][c];
+        a3 += S[i][k + 3] * X[k + 3][c];
+      }
+      for (; k <= c; ++k) a0 += S[i][k] * X[k][c];
+      X[i][c] = -((a0 + a1) + (a2 + a3)) * rd[i];
     }
   }
   __syncthreads();
