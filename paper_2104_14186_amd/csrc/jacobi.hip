@@ -35,9 +35,6 @@ namespace {
 constexpr int P2 = 2 * JB;     // size of a pair sub-problem
 constexpr int LDM = P2 + 1;
 constexpr int NT = 256;        // threads of the pair / tile kernels
-constexpr int TD = 16;         // lds_mm: TD x TD threads, each an RB x RB block of outputs
-constexpr int RB = P2 / TD;
-static_assert(TD * TD == NT, "lds_mm thread grid");
 constexpr int ROT = P2 / 2;    // rotations per round
 
 // Pair (p, q) of step `step` in the circle method over nb (even) players.
@@ -147,36 +144,32 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
   return sw;
 }
 
-// C = op(A) B for P2 x P2 LDS matrices (op = transpose when ta), RB x RB
-// outputs per thread.  C must not alias A or B.
+// C = alpha op(A) B (+ beta D) for P2 x P2 LDS matrices (op = transpose when
+// ta) on the FP64 matrix cores: the NT / 64 waves each own one 16 x 16 block
+// of C and run P2 / 4 v_mfma_f64_16x16x4f64 steps (operand lane l holds
+// A[l%16][l/16] and B[l/16][l%16]; result element r of lane l is
+// C[l/16 + 4r][l%16]).  C must not alias A or B.
+static_assert(P2 == 32 && NT == 256, "one 16x16 output block per wave");
 __device__ inline void lds_mm(const double (*A)[LDM], bool ta, const double (*B)[LDM],
                               double (*C)[LDM], double alpha, const double (*D)[LDM], double beta) {
-  const int t = threadIdx.x;
-  const int i0 = (t % TD) * RB, j0 = (t / TD) * RB;
-  double acc[RB][RB];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int bi = (wv & 1) * 16, bj = (wv >> 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int a = 0; a < RB; ++a)
-#pragma unroll
-    for (int b = 0; b < RB; ++b) acc[a][b] = 0.0;
-  for (int k = 0; k < P2; ++k) {
-    double av[RB], bv[RB];
-#pragma unroll
-    for (int a = 0; a < RB; ++a) av[a] = ta ? A[k][i0 + a] : A[i0 + a][k];
-#pragma unroll
-    for (int b = 0; b < RB; ++b) bv[b] = B[k][j0 + b];
-#pragma unroll
-    for (int a = 0; a < RB; ++a)
-#pragma unroll
-      for (int b = 0; b < RB; ++b) acc[a][b] += av[a] * bv[b];
+  for (int k0 = 0; k0 < P2; k0 += 4) {
+    const int k = k0 + lk;
+    const double av = ta ? A[k][bi + li] : A[bi + li][k];
+    const double bv = B[k][bj + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
   }
 #pragma unroll
-  for (int a = 0; a < RB; ++a)
-#pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      double v = alpha * acc[a][b];
-      if (D) v += beta * D[i0 + a][j0 + b];
-      C[i0 + a][j0 + b] = v;
-    }
+  for (int r = 0; r < 4; ++r) {
+    const int row = bi + lk + 4 * r, col = bj + li;
+    double v = alpha * acc[r];
+    if (D) v += beta * D[row][col];
+    C[row][col] = v;
+  }
 }
 
 // J <- J (3I - J^T J) / 2: one Newton-Schulz step towards the nearest
@@ -383,12 +376,12 @@ __global__ __launch_bounds__(NT) void svj_gram_kernel(SvjArgs a, double* part, i
   const int t = threadIdx.x;
   int p, q;
   round_robin(a.nb, a.step, blockIdx.y, &p, &q);
-  const int i0 = (t % TD) * RB, j0 = (t / TD) * RB;
-  double g[RB][RB];
-#pragma unroll
-  for (int u = 0; u < RB; ++u)
-#pragma unroll
-    for (int v = 0; v < RB; ++v) g[u][v] = 0.0;
+  // Gram X^T X of the chunk's rows on the FP64 matrix cores: wave w owns the
+  // 16 x 16 block (bi, bj) and accumulates over the rows in steps of 4
+  const int lane = t & 63, wv = t >> 6;
+  const int bi = (wv & 1) * 16, bj = (wv >> 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
   const int64_t rbeg = (int64_t)blockIdx.x * GR;
   const int64_t rend = (rbeg + GR < a.rows) ? rbeg + GR : a.rows;
   for (int64_t r0 = rbeg; r0 < rend; r0 += P2) {
@@ -398,24 +391,16 @@ __global__ __launch_bounds__(NT) void svj_gram_kernel(SvjArgs a, double* part, i
       X[i][j] = (r < rend) ? a.R[r + blk_index(p, q, j) * a.ldr] : 0.0;
     }
     __syncthreads();
-    for (int k = 0; k < P2; ++k) {
-      double av[RB], bv[RB];
 #pragma unroll
-      for (int u = 0; u < RB; ++u) av[u] = X[k][i0 + u];
-#pragma unroll
-      for (int v = 0; v < RB; ++v) bv[v] = X[k][j0 + v];
-#pragma unroll
-      for (int u = 0; u < RB; ++u)
-#pragma unroll
-        for (int v = 0; v < RB; ++v) g[u][v] += av[u] * bv[v];
+    for (int k0 = 0; k0 < P2; k0 += 4) {
+      const int k = k0 + lk;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[k][bi + li], X[k][bj + li], acc, 0, 0, 0);
     }
     __syncthreads();
   }
   double* out = part + ((int64_t)blockIdx.y * nchunk + blockIdx.x) * P2 * P2;
 #pragma unroll
-  for (int u = 0; u < RB; ++u)
-#pragma unroll
-    for (int v = 0; v < RB; ++v) out[(i0 + u) + (j0 + v) * P2] = g[u][v];
+  for (int r = 0; r < 4; ++r) out[(bi + lk + 4 * r) + (bj + li) * P2] = acc[r];
 }
 
 __global__ __launch_bounds__(NT) void svj_solve_kernel(SvjArgs a, const double* part, int nchunk) {
