@@ -320,7 +320,9 @@ int qdwhp_serve_destroy(qdwhp_server* srv);
  * Named integer parameters read by launch-shape decisions, written by the
  * autotuner (or by hand).  Keys: "gemm.small_tiles" (a GEMM whose 128x128
  * tile count is below this value runs with 64x64 tiles; default 96),
- * "batch.lanes" (default 8), "serve.lanes" (default 8).  Unset keys keep
+ * "batch.lanes" (default 8), "serve.lanes" (default 8), "jacobi.fused_max"
+ * (two-sided Jacobi problems up to this size update H and V in one launch
+ * per round; default 2048).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.
  */
 int qdwhp_tune_set(const char* key, int64_t value);

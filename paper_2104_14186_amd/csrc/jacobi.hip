@@ -19,6 +19,7 @@
 // steps into the eigenvalues and residuals.
 // Off-diagonal magnitudes seen at the start of each pair solve are max-reduced
 // per sweep (an order-independent atomic max) and decide convergence.
+#include "qdwhp.h"
 #include "common.h"
 #include "jacobi.h"
 
@@ -287,13 +288,8 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
 }
 
 // Tile (P, Q), P < Q over pair indices: H_PQ <- J_P^T H_PQ J_Q, mirrored to H_QP.
-__global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
-  __shared__ double X[P2][LDM];
-  __shared__ double Y[P2][LDM];
-  __shared__ double JP[P2][LDM];
-  __shared__ double JQ[P2][LDM];
+__device__ __forceinline__ void tile_update(const SymArgs& a, int64_t lin, double (*X)[LDM], double (*Y)[LDM]) {
   const int np = a.nb / 2;
-  const int64_t lin = blockIdx.x;
   int P = 0;
   int64_t rem = lin;
   while (rem >= np - 1 - P) { rem -= np - 1 - P; ++P; }
@@ -302,19 +298,36 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
   int pP, qP, pQ, qQ;
   round_robin(a.nb, a.step, P, &pP, &qP);
   round_robin(a.nb, a.step, Q, &pQ, &qQ);
-  const int t = threadIdx.x;
+  // The rotations enter the two MFMA products as register operands read
+  // straight from global memory (J column-major: J[i][j] at Jb[i + j P2]);
+  // wave w owns the 16 x 16 output block (bi, bj).
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int bi = (wv & 1) * 16, bj = (wv >> 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
   const double* JbP = a.Jb + (int64_t)P * P2 * P2;
   const double* JbQ = a.Jb + (int64_t)Q * P2 * P2;
-  load_tile(a.H, a.ldh, pP, qP, pQ, qQ, X);
-  for (int e = t; e < P2 * P2; e += NT) {
-    const int i = e % P2, j = e / P2;
-    JP[i][j] = JbP[e];
-    JQ[i][j] = JbQ[e];
+  double jp[P2 / 4], jq[P2 / 4];
+#pragma unroll
+  for (int s4 = 0; s4 < P2 / 4; ++s4) {
+    const int k = 4 * s4 + lk;
+    jp[s4] = JbP[k + (bi + li) * P2];   // (J_P^T)[bi + li][k]
+    jq[s4] = JbQ[k + (bj + li) * P2];   // J_Q[k][bj + li]
   }
+  load_tile(a.H, a.ldh, pP, qP, pQ, qQ, X);
   __syncthreads();
-  lds_mm(JP, true, X, Y, 1.0, nullptr, 0.0);     // Y = J_P^T X
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < P2 / 4; ++s4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(jp[s4], X[4 * s4 + lk][bj + li], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) Y[bi + lk + 4 * r][bj + li] = acc[r];   // Y = J_P^T X
   __syncthreads();
-  lds_mm(Y, false, JQ, X, 1.0, nullptr, 0.0);    // X = Y J_Q
+  acc = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < P2 / 4; ++s4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[bi + li][4 * s4 + lk], jq[s4], acc, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[bi + lk + 4 * r][bj + li] = acc[r];   // X = Y J_Q
   __syncthreads();
   // pair blocks of P and Q are disjoint: every sub-block has exactly one
   // stored copy, written from here
@@ -325,17 +338,15 @@ __global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
 // entries in registers; J_Q sits in LDS and every lane reads the same entry
 // (a broadcast).  Rows of a workgroup are consecutive, so each column access
 // is coalesced.
-__global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv, int64_t rows, int nb,
-                                                         int step, const double* Jb, const int* act) {
-  __shared__ double JQ[P2 * P2];   // column-major J_Q
-  const int Q = blockIdx.y;
+__device__ __forceinline__ void cols_rotate(double* V, int64_t ldv, int64_t rows, int nb, int step,
+                                            const double* Jb, const int* act, int Q, int64_t rb, double* JQ) {
   if (!act[Q]) return;             // identity rotation
   int p, q;
   round_robin(nb, step, Q, &p, &q);
   const double* J = Jb + (int64_t)Q * P2 * P2;
   for (int e = threadIdx.x; e < P2 * P2; e += NT) JQ[e] = J[e];
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * NT + threadIdx.x;
+  const int64_t r = rb * NT + threadIdx.x;
   if (r >= rows) return;
   double x[P2];
 #pragma unroll
@@ -351,6 +362,49 @@ __global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv,
       for (int u = 0; u < 8; ++u) y[u] += x[k] * JQ[k + (j0 + u) * P2];
 #pragma unroll
     for (int u = 0; u < 8; ++u) V[r + blk_index(p, q, j0 + u) * ldv] = y[u];
+  }
+}
+
+__global__ __launch_bounds__(NT) void cols_update_kernel(double* V, int64_t ldv, int64_t rows, int nb,
+                                                         int step, const double* Jb, const int* act) {
+  __shared__ double JQ[P2 * P2];   // column-major J_Q
+  cols_rotate(V, ldv, rows, nb, step, Jb, act, blockIdx.y, blockIdx.x, JQ);
+}
+
+// Rotations of the one-sided round applied to R (rows1 rows) and V (rows2
+// rows) in one launch: the first rb1 x pairs workgroups take R.
+__global__ __launch_bounds__(NT) void cols_update2_kernel(double* R, int64_t ldr, int64_t rows1, int64_t rb1,
+                                                          double* V, int64_t ldv, int64_t rows2, int64_t rb2,
+                                                          int nb, int step, const double* Jb, const int* act) {
+  __shared__ double JQ[P2 * P2];
+  const int64_t b = blockIdx.x;
+  const int64_t npair = nb / 2;
+  if (b < rb1 * npair) cols_rotate(R, ldr, rows1, nb, step, Jb, act, (int)(b / rb1), b % rb1, JQ);
+  else {
+    const int64_t c = b - rb1 * npair;
+    cols_rotate(V, ldv, rows2, nb, step, Jb, act, (int)(c / rb2), c % rb2, JQ);
+  }
+}
+
+__global__ __launch_bounds__(NT) void sym_update_kernel(SymArgs a) {
+  __shared__ double X[P2][LDM];
+  __shared__ double Y[P2][LDM];
+  tile_update(a, blockIdx.x, X, Y);
+}
+
+// The two updates of a two-sided round in one launch (they only share the
+// rotations): the first ntiles workgroups update tiles of H, the rest
+// rotate row blocks of V.  It carries the register needs of both paths, so
+// it is used where launches dominate (small ell) and the two kernels above
+// where bandwidth does.
+__global__ __launch_bounds__(NT) void round_update_kernel(SymArgs a, int64_t ntiles, int64_t rowblocks) {
+  __shared__ double smem[2 * P2 * LDM];
+  const int64_t b = blockIdx.x;
+  if (b < ntiles) {
+    tile_update(a, b, (double (*)[LDM])smem, (double (*)[LDM])(smem + P2 * LDM));
+  } else {
+    const int64_t idx = b - ntiles;
+    cols_rotate(a.V, a.ldv, a.n, a.nb, a.step, a.Jb, a.act, (int)(idx / rowblocks), idx % rowblocks, smem);
   }
 }
 
@@ -585,6 +639,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   a.act = act;
   const int np2 = nb / 2;
   const int64_t ntiles = (int64_t)np2 * (np2 - 1) / 2;
+  const bool fused = n <= qdwhp_tune_get("jacobi.fused_max", 2048);
   int sweeps = -1;
   double prev = 0.0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
@@ -593,12 +648,18 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
       a.step = st;
       sym_pair_kernel<<<np2, NT, 0, s>>>(a);
       QDWHP_LAUNCH_CHECK();
-      if (ntiles > 0) {
-        sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
+      if (fused) {
+        const int64_t rowblocks = cdiv(n, NT);
+        round_update_kernel<<<(unsigned)(ntiles + rowblocks * np2), NT, 0, s>>>(a, ntiles, rowblocks);
+        QDWHP_LAUNCH_CHECK();
+      } else {
+        if (ntiles > 0) {
+          sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
+          QDWHP_LAUNCH_CHECK();
+        }
+        cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
         QDWHP_LAUNCH_CHECK();
       }
-      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
-      QDWHP_LAUNCH_CHECK();
     }
     double off = 0.0;
     QDWHP_HIP(hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -653,10 +714,12 @@ int gesvj(double* R, int64_t rows, int64_t n, int64_t ldr, double* S, double* V,
       QDWHP_LAUNCH_CHECK();
       svj_solve_kernel<<<nb / 2, NT, 0, s>>>(a, part, nchunk);
       QDWHP_LAUNCH_CHECK();
-      cols_update_kernel<<<dim3((unsigned)cdiv(rows, NT), nb / 2), NT, 0, s>>>(Rp, rows, rows, nb, st, Jb, a.act);
-      QDWHP_LAUNCH_CHECK();
-      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), nb / 2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
-      QDWHP_LAUNCH_CHECK();
+      {
+        const int64_t rb1 = cdiv(rows, NT), rb2 = cdiv(n, NT);
+        cols_update2_kernel<<<(unsigned)((rb1 + rb2) * (nb / 2)), NT, 0, s>>>(Rp, rows, rows, rb1, Vp, np, n, rb2,
+                                                                              nb, st, Jb, a.act);
+        QDWHP_LAUNCH_CHECK();
+      }
     }
     double off = 0.0;
     QDWHP_HIP(hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s));
