@@ -54,16 +54,20 @@ __device__ inline void atomic_max_nonneg(double* addr, double v) {
 
 // Cyclic Jacobi on the P2 x P2 symmetric M (LDS), accumulating J (LDS, starts
 // as identity), with NT threads.  A rotation is skipped when |m_pq| <= tol
-// (abs) or <= tol * sqrt(m_pp m_qq) (relative).  Row and column updates stage
-// every value a thread touches in registers before storing (an LDS store
-// between two loads would serialise them).
+// (abs) or <= tol * sqrt(m_pp m_qq) (relative).  The ROT rotations of a round
+// are disjoint, so they cut M into ROT x ROT blocks of 2 x 2 (row pair x column
+// pair): one thread owns one block and applies the row rotation then the
+// column rotation to it (the same order of operations as a full row pass
+// followed by a full column pass), and rotates the matching 2 x 2 block of J.
+// No thread reads what another writes within a round, so a round takes two
+// barriers: after the rotations are formed and after they are applied.
+static_assert(NT == ROT * ROT, "one thread per 2x2 block of a round");
 __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool relative,
                             int max_sweeps) {
   __shared__ double cs[ROT][2];
-  __shared__ int pidx[ROT][2];
   __shared__ int any;
-  constexpr int PER = ROT * P2 / NT;   // (rotation, index) pairs per thread
   const int t = threadIdx.x;
+  const int kr = t / ROT, kc = t % ROT;   // row pair, column pair of this thread
   int sw = 0;
   for (; sw < max_sweeps; ++sw) {
     if (t == 0) any = 0;
@@ -87,54 +91,33 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
           s = tt * c;
           any = 1;
         }
-        cs[t][0] = c; cs[t][1] = s; pidx[t][0] = p; pidx[t][1] = q;
+        cs[t][0] = c; cs[t][1] = s;
       }
+      int p, q, u, v;
+      round_robin(P2, r, kr, &p, &q);
+      round_robin(P2, r, kc, &u, &v);
       __syncthreads();
-      {  // rows: M <- J_r^T M
-        double mp[PER], mq[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = t + NT * u, k = e / P2, j = e % P2;
-          mp[u] = M[pidx[k][0]][j];
-          mq[u] = M[pidx[k][1]][j];
+      const double cr = cs[kr][0], sr = cs[kr][1];
+      const double cc = cs[kc][0], sc = cs[kc][1];
+      if (sr != 0.0 || sc != 0.0) {
+        double a = M[p][u], b = M[p][v], c = M[q][u], d = M[q][v];
+        if (sr != 0.0) {   // rows: M <- J_r^T M
+          const double a1 = cr * a - sr * c, c1 = sr * a + cr * c;
+          const double b1 = cr * b - sr * d, d1 = sr * b + cr * d;
+          a = a1; b = b1; c = c1; d = d1;
         }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = t + NT * u, k = e / P2, j = e % P2;
-          const double c = cs[k][0], s = cs[k][1];
-          if (s != 0.0) {
-            M[pidx[k][0]][j] = c * mp[u] - s * mq[u];
-            M[pidx[k][1]][j] = s * mp[u] + c * mq[u];
-          }
+        if (sc != 0.0) {   // columns: M <- M J_r
+          const double a1 = cc * a - sc * b, b1 = sc * a + cc * b;
+          const double c1 = cc * c - sc * d, d1 = sc * c + cc * d;
+          a = a1; b = b1; c = c1; d = d1;
         }
+        if (kr == kc) { b = 0.0; c = 0.0; }   // the pair's own off-diagonal
+        M[p][u] = a; M[p][v] = b; M[q][u] = c; M[q][v] = d;
       }
-      __syncthreads();
-      {  // columns: M <- M J_r, J <- J J_r
-        double mp[PER], mq[PER], jp[PER], jq[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = t + NT * u, k = e / P2, i = e % P2;
-          mp[u] = M[i][pidx[k][0]]; mq[u] = M[i][pidx[k][1]];
-          jp[u] = J[i][pidx[k][0]]; jq[u] = J[i][pidx[k][1]];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int e = t + NT * u, k = e / P2, i = e % P2;
-          const double c = cs[k][0], s = cs[k][1];
-          if (s != 0.0) {
-            M[i][pidx[k][0]] = c * mp[u] - s * mq[u];
-            M[i][pidx[k][1]] = s * mp[u] + c * mq[u];
-            J[i][pidx[k][0]] = c * jp[u] - s * jq[u];
-            J[i][pidx[k][1]] = s * jp[u] + c * jq[u];
-          }
-        }
-      }
-      __syncthreads();
-      if (t < ROT && cs[t][1] != 0.0) {
-        const int p = pidx[t][0], q = pidx[t][1];
-        M[p][q] = 0.0; M[q][p] = 0.0;
+      if (sc != 0.0) {     // J <- J J_r on rows p, q
+        const double a = J[p][u], b = J[p][v], c = J[q][u], d = J[q][v];
+        J[p][u] = cc * a - sc * b; J[p][v] = sc * a + cc * b;
+        J[q][u] = cc * c - sc * d; J[q][v] = sc * c + cc * d;
       }
       __syncthreads();
     }
