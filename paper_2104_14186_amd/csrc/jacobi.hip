@@ -173,7 +173,7 @@ __device__ void orthonormalize(double (*J)[LDM], double (*T)[LDM], double (*U)[L
 struct SymArgs {
   double* H; int64_t ldh; int nb;   // padded to nb*JB, zero outside n
   int64_t n;
-  double* Jb;                        // [nb/2][P2*P2]
+  double* Jb;                        // [nb/2][P2*P2], fragment order
   double* V; int64_t ldv;            // npad x npad
   double tol;
   double* offmax;                    // per sweep
@@ -184,6 +184,14 @@ struct SymArgs {
 __device__ inline int64_t blk_index(int p, int q, int i) {  // pair (p,q) local index i -> global
   return (i < JB) ? (int64_t)p * JB + i : (int64_t)q * JB + (i - JB);
 }
+
+// Pair rotations are stored in the operand order of the FP64 MFMA so that
+// every wave loads its operand fragments with contiguous 512-byte reads:
+// slot e = 512 h + 64 s + l (h: 16-column half, s: k-step of 4 rows, l:
+// lane) holds J[4s + l/16][16h + l%16]; frag_row / frag_col invert it.
+__device__ inline int frag_row(int e) { return 4 * ((e / 64) % 8) + (e % 64) / 16; }
+__device__ inline int frag_col(int e) { return 16 * (e / 512) + e % 16; }
+static_assert(P2 == 32, "fragment order assumes 32 x 32 rotations");
 
 // H is kept block-upper: a JB x JB block (bi, bj) is current only for
 // bi <= bj (diagonal blocks in full); block (bi, bj) with bi > bj is read as
@@ -262,7 +270,7 @@ __global__ __launch_bounds__(NT) void sym_pair_kernel(SymArgs a) {
   lds_mm(M0, false, J, T, 1.0, nullptr, 0.0);
   __syncthreads();
   double* Jout = a.Jb + (int64_t)blockIdx.x * P2 * P2;
-  for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[e % P2][e / P2];
+  for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[frag_row(e)][frag_col(e)];
   if (t < P2) {
     double acc = 0.0;
     for (int k = 0; k < P2; ++k) acc += J[k][t] * T[k][t];
@@ -277,26 +285,28 @@ __device__ __forceinline__ void tile_update(const SymArgs& a, int64_t lin, doubl
   int64_t rem = lin;
   while (rem >= np - 1 - P) { rem -= np - 1 - P; ++P; }
   const int Q = P + 1 + (int)rem;
-  if (!a.act[P] && !a.act[Q]) return;   // both rotations are the identity
   int pP, qP, pQ, qQ;
   round_robin(a.nb, a.step, P, &pP, &qP);
   round_robin(a.nb, a.step, Q, &pQ, &qQ);
-  // The rotations enter the two MFMA products as register operands read
-  // straight from global memory (J column-major: J[i][j] at Jb[i + j P2]);
-  // wave w owns the 16 x 16 output block (bi, bj).
+  // The rotations enter the two MFMA products as register operands loaded
+  // in fragment order; wave w owns the 16 x 16 output block (bi, bj), and
+  // its J_P^T operand is the fragment half bi / 16 of J_P, its J_Q operand
+  // the half bj / 16 of J_Q.
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int bi = (wv & 1) * 16, bj = (wv >> 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
-  const double* JbP = a.Jb + (int64_t)P * P2 * P2;
-  const double* JbQ = a.Jb + (int64_t)Q * P2 * P2;
+  const double* FP = a.Jb + (int64_t)P * P2 * P2 + bi * P2 + lane;
+  const double* FQ = a.Jb + (int64_t)Q * P2 * P2 + bj * P2 + lane;
   double jp[P2 / 4], jq[P2 / 4];
 #pragma unroll
   for (int s4 = 0; s4 < P2 / 4; ++s4) {
-    const int k = 4 * s4 + lk;
-    jp[s4] = JbP[k + (bi + li) * P2];   // (J_P^T)[bi + li][k]
-    jq[s4] = JbQ[k + (bj + li) * P2];   // J_Q[k][bj + li]
+    jp[s4] = FP[64 * s4];   // J_P[4 s4 + lk][bi + li] = (J_P^T)[bi + li][4 s4 + lk]
+    jq[s4] = FQ[64 * s4];   // J_Q[4 s4 + lk][bj + li]
   }
   load_tile(a.H, a.ldh, pP, qP, pQ, qQ, X);
+  // the skip test comes after the loads are issued so that its latency
+  // overlaps theirs (the flags are uniform over the workgroup)
+  if (!a.act[P] && !a.act[Q]) return;   // both rotations are the identity
   __syncthreads();
   v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -327,7 +337,7 @@ __device__ __forceinline__ void cols_rotate(double* V, int64_t ldv, int64_t rows
   int p, q;
   round_robin(nb, step, Q, &p, &q);
   const double* J = Jb + (int64_t)Q * P2 * P2;
-  for (int e = threadIdx.x; e < P2 * P2; e += NT) JQ[e] = J[e];
+  for (int e = threadIdx.x; e < P2 * P2; e += NT) JQ[frag_row(e) + frag_col(e) * P2] = J[e];
   __syncthreads();
   const int64_t r = rb * NT + threadIdx.x;
   if (r >= rows) return;
@@ -475,7 +485,7 @@ __global__ __launch_bounds__(NT) void svj_solve_kernel(SvjArgs a, const double* 
   if (t == 0) a.act[blockIdx.x] = rotated > 0;
   orthonormalize(J, M, X);
   double* Jout = a.Jb + (int64_t)blockIdx.x * P2 * P2;
-  for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[e % P2][e / P2];
+  for (int e = t; e < P2 * P2; e += NT) Jout[e] = J[frag_row(e)][frag_col(e)];
 }
 
 // Rank of each of the first n values by descending key (ties by index).
