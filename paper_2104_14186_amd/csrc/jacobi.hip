@@ -19,6 +19,10 @@
 // steps into the eigenvalues and residuals.
 // Off-diagonal magnitudes seen at the start of each pair solve are max-reduced
 // per sweep (an order-independent atomic max) and decide convergence.
+#include <map>
+#include <memory>
+#include <mutex>
+#include <vector>
 #include "qdwhp.h"
 #include "common.h"
 #include "jacobi.h"
@@ -587,13 +591,61 @@ bool converged(double off, double prev, double tol, int sw) {
   return sw >= 3 && off <= 32.0 * tol && off > 0.25 * prev;
 }
 
+// The eigenvector update V <- V J of a two-sided round only needs that
+// round's rotations, so above the fused size it runs on a helper stream,
+// overlapping the next rounds' pair solves and tile updates.  The rotations
+// and skip flags of kRing consecutive rounds live in a ring of slots; a
+// round waits for the update that last read its slot before refilling it.
+constexpr int kRing = 4;
+
+struct AuxSet {
+  hipStream_t s;
+  hipEvent_t ready[kRing], done[kRing];
+};
+
+std::mutex aux_mu;
+std::map<int, std::vector<AuxSet*>> aux_free;   // per device; sets live until the process ends
+
+class AuxLease {
+ public:
+  explicit AuxLease(int dev) : dev_(dev) {
+    {
+      std::lock_guard<std::mutex> g(aux_mu);
+      auto& v = aux_free[dev];
+      if (!v.empty()) { set_ = v.back(); v.pop_back(); }
+    }
+    if (!set_) {
+      AuxSet* a = new AuxSet;
+      QDWHP_HIP(hipStreamCreateWithFlags(&a->s, hipStreamNonBlocking));
+      for (int i = 0; i < kRing; ++i) {
+        QDWHP_HIP(hipEventCreateWithFlags(&a->ready[i], hipEventDisableTiming));
+        QDWHP_HIP(hipEventCreateWithFlags(&a->done[i], hipEventDisableTiming));
+      }
+      set_ = a;
+    }
+  }
+  ~AuxLease() {
+    // work still queued (an error path) finishes before the set is reused
+    (void)hipStreamSynchronize(set_->s);
+    std::lock_guard<std::mutex> g(aux_mu);
+    aux_free[dev_].push_back(set_);
+  }
+  AuxSet* operator->() const { return set_; }
+  AuxLease(const AuxLease&) = delete;
+  AuxLease& operator=(const AuxLease&) = delete;
+
+ private:
+  int dev_;
+  AuxSet* set_ = nullptr;
+};
+
 }  // namespace
 
 int64_t jacobi_padded(int64_t n) { int64_t nb = cdiv(n > 0 ? n : 1, JB); if (nb & 1) ++nb; if (nb < 2) nb = 2; return nb * JB; }
 
 int64_t syev_scratch_doubles(int64_t n) {
   const int64_t np = jacobi_padded(n);
-  return np * np * 2 + (np / JB / 2) * P2 * P2 + 64 + 2 * np + 256;
+  return np * np * 2 + kRing * (np / JB / 2) * P2 * P2 + 64 + 2 * np + kRing * (np / JB / 2) + 256;
 }
 
 // H (n x n, ldh) is copied into a padded work matrix; results: w[n] descending,
@@ -604,11 +656,13 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   const int nb = (int)(np / JB);
   double* Hp = scratch;
   double* Vp = Hp + np * np;
-  double* Jb = Vp + np * np;
-  double* offmax = Jb + (int64_t)(nb / 2) * P2 * P2;
+  const int np2 = nb / 2;
+  const int64_t jslot = (int64_t)np2 * P2 * P2;
+  double* Jb = Vp + np * np;                 // kRing slots of np2 rotations
+  double* offmax = Jb + kRing * jslot;
   int64_t* rank = (int64_t*)(offmax + 64);
   double* fro = (double*)(rank + np);
-  int* act = (int*)(fro + 8);
+  int* act = (int*)(fro + 8);                // kRing slots of np2 flags
   fill(Hp, np, np, np, 0.0, 0.0, s);
   copy(H, ldh, Hp, np, n, n, s);
   fill(Vp, np, np, np, 0.0, 1.0, s);
@@ -630,29 +684,43 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   a.tol = 2.0 * 1.1102230246251565e-16 * (hf > 0.0 ? hf / std::sqrt((double)n) : 1.0);
   a.offmax = offmax;
   a.act = act;
-  const int np2 = nb / 2;
   const int64_t ntiles = (int64_t)np2 * (np2 - 1) / 2;
   const bool fused = n <= qdwhp_tune_get("jacobi.fused_max", 2048);
+  int dev = 0;
+  QDWHP_HIP(hipGetDevice(&dev));
+  std::unique_ptr<AuxLease> aux;
+  if (!fused) aux.reset(new AuxLease(dev));
   int sweeps = -1;
   double prev = 0.0;
+  int64_t round = 0;
   for (int sw = 0; sw < kMaxSweeps; ++sw) {
     a.sweep = sw;
-    for (int st = 0; st < nb - 1; ++st) {
+    for (int st = 0; st < nb - 1; ++st, ++round) {
       a.step = st;
-      sym_pair_kernel<<<np2, NT, 0, s>>>(a);
-      QDWHP_LAUNCH_CHECK();
       if (fused) {
+        sym_pair_kernel<<<np2, NT, 0, s>>>(a);
+        QDWHP_LAUNCH_CHECK();
         const int64_t rowblocks = cdiv(n, NT);
         round_update_kernel<<<(unsigned)(ntiles + rowblocks * np2), NT, 0, s>>>(a, ntiles, rowblocks);
         QDWHP_LAUNCH_CHECK();
-      } else {
-        if (ntiles > 0) {
-          sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
-          QDWHP_LAUNCH_CHECK();
-        }
-        cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s>>>(Vp, np, n, nb, st, Jb, a.act);
+        continue;
+      }
+      const int slot = (int)(round % kRing);
+      a.Jb = Jb + slot * jslot;
+      a.act = act + slot * np2;
+      if (round >= kRing) QDWHP_HIP(hipStreamWaitEvent(s, (*aux)->done[slot], 0));
+      sym_pair_kernel<<<np2, NT, 0, s>>>(a);
+      QDWHP_LAUNCH_CHECK();
+      QDWHP_HIP(hipEventRecord((*aux)->ready[slot], s));
+      if (ntiles > 0) {
+        sym_update_kernel<<<(unsigned)ntiles, NT, 0, s>>>(a);
         QDWHP_LAUNCH_CHECK();
       }
+      hipStream_t s2 = (*aux)->s;
+      QDWHP_HIP(hipStreamWaitEvent(s2, (*aux)->ready[slot], 0));
+      cols_update_kernel<<<dim3((unsigned)cdiv(n, NT), np2), NT, 0, s2>>>(Vp, np, n, nb, st, a.Jb, a.act);
+      QDWHP_LAUNCH_CHECK();
+      QDWHP_HIP(hipEventRecord((*aux)->done[slot], s2));
     }
     double off = 0.0;
     QDWHP_HIP(hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -660,6 +728,8 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
     if (converged(off, prev, a.tol, sw)) { sweeps = sw + 1; break; }
     prev = off;
   }
+  if (aux && round > 0)   // the last eigenvector updates precede the gather below
+    QDWHP_HIP(hipStreamWaitEvent(s, (*aux)->done[(int)((round - 1) % kRing)], 0));
   // eigenvalues: diagonal of the first n positions; sort descending
   rank_kernel<<<(unsigned)cdiv(n, 256), 256, 0, s>>>(Hp, np + 1, n, rank);
   QDWHP_LAUNCH_CHECK();

@@ -120,6 +120,32 @@ def test_syev(n):
     assert np.abs(W.T @ W - np.eye(n)).max() < 5e-15 * max(1, np.sqrt(n))
 
 
+@pytest.mark.parametrize("n", [100, 333])
+def test_syev_helper_stream_path_matches_single_launch_rounds(n):
+    """Above the fused size the eigenvector update of each round runs on a
+    helper stream from a ring of rotation slots; it applies the same
+    arithmetic as the one-launch round, so the results are identical."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(n + 11)
+    G = g.standard_normal((n, n))
+    H = torch.from_numpy(0.5 * (G + G.T)).cuda()
+    print(f"syev streams n={n}", flush=True)
+    out = []
+    old = q.tune_get("jacobi.fused_max", 2048)
+    try:
+        for thr in (1 << 40, 0, 0):   # fused, then the helper-stream path twice
+            q.tune_set("jacobi.fused_max", thr)
+            w, W, sw = q.syev(H)
+            torch.cuda.synchronize()
+            out.append((w.clone(), W.clone(), sw))
+    finally:
+        q.tune_set("jacobi.fused_max", old)
+    for w, W, sw in out[1:]:
+        assert sw == out[0][2]
+        assert bool((w == out[0][0]).all()) and bool((W == out[0][1]).all())
+
+
 @pytest.mark.parametrize("n", [1, 2, 32, 45, 200])
 def test_gesvj(n):
     torch = _torch()
