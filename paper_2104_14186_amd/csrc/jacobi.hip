@@ -103,8 +103,10 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
       __syncthreads();
       const double cr = cs[kr][0], sr = cs[kr][1];
       const double cc = cs[kc][0], sc = cs[kc][1];
+      // every load of the round is issued before the first store
+      double a = M[p][u], b = M[p][v], c = M[q][u], d = M[q][v];
+      const double ja = J[p][u], jb = J[p][v], jc = J[q][u], jd = J[q][v];
       if (sr != 0.0 || sc != 0.0) {
-        double a = M[p][u], b = M[p][v], c = M[q][u], d = M[q][v];
         if (sr != 0.0) {   // rows: M <- J_r^T M
           const double a1 = cr * a - sr * c, c1 = sr * a + cr * c;
           const double b1 = cr * b - sr * d, d1 = sr * b + cr * d;
@@ -119,9 +121,8 @@ __device__ int inner_jacobi(double (*M)[LDM], double (*J)[LDM], double tol, bool
         M[p][u] = a; M[p][v] = b; M[q][u] = c; M[q][v] = d;
       }
       if (sc != 0.0) {     // J <- J J_r on rows p, q
-        const double a = J[p][u], b = J[p][v], c = J[q][u], d = J[q][v];
-        J[p][u] = cc * a - sc * b; J[p][v] = sc * a + cc * b;
-        J[q][u] = cc * c - sc * d; J[q][v] = sc * c + cc * d;
+        J[p][u] = cc * ja - sc * jb; J[p][v] = sc * ja + cc * jb;
+        J[q][u] = cc * jc - sc * jd; J[q][v] = sc * jc + cc * jd;
       }
       __syncthreads();
     }
