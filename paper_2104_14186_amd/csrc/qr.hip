@@ -5,7 +5,11 @@
 // (Sec. 4.1, Theorem 1 and "Choosing the subspace size").
 //
 // Blocked right-looking factorization with panels of QB = 128 columns:
-//  * panel: one launch per column over the whole grid.  Launch j forms
+//  * panel: factored in sub-panels of QI = 32 columns, each finished
+//    sub-panel applied to the rest of the panel as a blocked update (the
+//    same T / three-GEMM form as the trailing update), so the per-column
+//    launches sweep at most 32 columns;
+//  * column step: one launch per column over the whole grid.  Launch j forms
 //    reflector j from column statistics reduced from the previous launch
 //    (norm of the column below the pivot, its dot products with the other
 //    panel columns, and the pivot row), applies it to this workgroup's rows,
@@ -26,6 +30,7 @@ constexpr int CH = 32;          // columns per register chunk
 constexpr int RPT_MAX = 8;      // rows per thread
 constexpr int QT = 256;         // threads per workgroup
 constexpr int NWG_MAX = 64;     // workgroups per column launch
+constexpr int QI = 32;          // sub-panel width of the column launches
 
 struct Panel {
   double* P; int64_t ld; int64_t h; int w;
@@ -321,48 +326,74 @@ QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
   return s;
 }
 
+namespace {
+
+// T (w x w, ld QB) of the compact WY form of the w reflectors stored below
+// the diagonal of V (h x w): G = V^T V, then the T recurrence.
+void build_t(const double* V, int64_t h, int w, int64_t ld, const double* tau, double* T,
+             const QrScratch& sc, hipStream_t s) {
+  Gemm g;
+  g.M = w; g.N = w; g.K = h; g.A = V; g.lda = ld; g.ta = true; g.a_unit_lower = true;
+  g.B = V; g.ldb = ld; g.b_unit_lower = true; g.C = sc.G; g.ldc = QB;
+  g.ws = sc.ws; g.ws_doubles = sc.ws_doubles;
+  dgemm(g, s);
+  build_t_kernel<<<1, QB, 0, s>>>(sc.G, QB, tau, T, QB, w);
+  QDWHP_LAUNCH_CHECK();
+}
+
+// C (h x nc, ld) <- (I - V T^T V^T) C: W1 = V^T C, W2 = T^T W1, C -= V W2.
+void apply_qt(const double* V, int64_t h, int w, int64_t ld, const double* T, double* C, int64_t nc,
+              const QrScratch& sc, hipStream_t s) {
+  Gemm g1;   // W1 = V^T C
+  g1.M = w; g1.N = nc; g1.K = h; g1.A = V; g1.lda = ld; g1.ta = true; g1.a_unit_lower = true;
+  g1.B = C; g1.ldb = ld; g1.C = sc.W1; g1.ldc = QB; g1.ws = sc.ws; g1.ws_doubles = sc.ws_doubles;
+  dgemm(g1, s);
+  Gemm g2;   // W2 = T^T W1
+  g2.M = w; g2.N = nc; g2.K = w; g2.A = T; g2.lda = QB; g2.ta = true;
+  g2.B = sc.W1; g2.ldb = QB; g2.C = sc.W2; g2.ldc = QB;
+  dgemm(g2, s);
+  Gemm g3;   // C -= V W2
+  g3.M = h; g3.N = nc; g3.K = w; g3.alpha = -1.0; g3.beta = 1.0;
+  g3.A = V; g3.lda = ld; g3.a_unit_lower = true; g3.B = sc.W2; g3.ldb = QB;
+  g3.C = C; g3.ldc = ld;
+  dgemm(g3, s);
+}
+
+}  // namespace
+
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
               const QrScratch& sc, hipStream_t s, const PanelWatch* watch) {
   for (int64_t c0 = 0; c0 < n; c0 += QB) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
     const int64_t h = m - c0;
-    Panel p;
-    p.P = A + c0 + c0 * lda; p.ld = lda; p.h = h; p.w = w;
-    p.tau = tau + c0; p.part = sc.part; p.piv = sc.piv;
-    p.rpt = (int)cdiv(h, (int64_t)QT * NWG_MAX);
-    if (p.rpt > RPT_MAX) throw HipError{hipErrorInvalidValue};   // h > 131072 rows
-    p.nwg = (int)cdiv(h, (int64_t)QT * p.rpt);
-    for (int j = -1; j < w; ++j) {
-      qr_col_kernel<<<p.nwg, QT, 0, s>>>(p, j);
-      QDWHP_LAUNCH_CHECK();
-    }
-    // G = V^T V, then T
-    Gemm g;
-    g.M = w; g.N = w; g.K = h; g.A = p.P; g.lda = lda; g.ta = true; g.a_unit_lower = true;
-    g.B = p.P; g.ldb = lda; g.b_unit_lower = true; g.C = sc.G; g.ldc = QB;
-    g.ws = sc.ws; g.ws_doubles = sc.ws_doubles;
-    dgemm(g, s);
+    double* V = A + c0 + c0 * lda;
     double* T = Tall + (c0 / QB) * QB * QB;
-    build_t_kernel<<<1, QB, 0, s>>>(sc.G, QB, tau + c0, T, QB, w);
-    QDWHP_LAUNCH_CHECK();
+    // The panel itself is factored in sub-panels of QI columns: the column
+    // launches only sweep their sub-panel, and each finished sub-panel's
+    // reflectors reach the rest of the panel as one blocked update (its T is
+    // built in the panel's T slot, which the panel's own T overwrites below).
+    for (int j0 = 0; j0 < w; j0 += QI) {
+      const int wi = (w - j0) < QI ? (w - j0) : QI;
+      Panel p;
+      p.P = V + j0 + j0 * lda; p.ld = lda; p.h = h - j0; p.w = wi;
+      p.tau = tau + c0 + j0; p.part = sc.part; p.piv = sc.piv;
+      p.rpt = (int)cdiv(p.h, (int64_t)QT * NWG_MAX);
+      if (p.rpt > RPT_MAX) throw HipError{hipErrorInvalidValue};   // h > 131072 rows
+      p.nwg = (int)cdiv(p.h, (int64_t)QT * p.rpt);
+      for (int j = -1; j < wi; ++j) {
+        qr_col_kernel<<<p.nwg, QT, 0, s>>>(p, j);
+        QDWHP_LAUNCH_CHECK();
+      }
+      const int rest = w - j0 - wi;
+      if (rest > 0) {
+        build_t(p.P, p.h, wi, lda, p.tau, T, sc, s);
+        apply_qt(p.P, p.h, wi, lda, T, p.P + (int64_t)wi * lda, rest, sc, s);
+      }
+    }
+    build_t(V, h, w, lda, tau + c0, T, sc, s);
     if (watch && (*watch)(c0, w)) return c0 + w;   // the caller needs no further columns
     const int64_t nc = n - c0 - w;
-    if (nc > 0) {
-      double* Cm = A + c0 + (c0 + w) * lda;
-      Gemm g1;   // W1 = V^T C
-      g1.M = w; g1.N = nc; g1.K = h; g1.A = p.P; g1.lda = lda; g1.ta = true; g1.a_unit_lower = true;
-      g1.B = Cm; g1.ldb = lda; g1.C = sc.W1; g1.ldc = QB; g1.ws = sc.ws; g1.ws_doubles = sc.ws_doubles;
-      dgemm(g1, s);
-      Gemm g2;   // W2 = T^T W1
-      g2.M = w; g2.N = nc; g2.K = w; g2.A = T; g2.lda = QB; g2.ta = true;
-      g2.B = sc.W1; g2.ldb = QB; g2.C = sc.W2; g2.ldc = QB;
-      dgemm(g2, s);
-      Gemm g3;   // C -= V W2
-      g3.M = h; g3.N = nc; g3.K = w; g3.alpha = -1.0; g3.beta = 1.0;
-      g3.A = p.P; g3.lda = lda; g3.a_unit_lower = true; g3.B = sc.W2; g3.ldb = QB;
-      g3.C = Cm; g3.ldc = lda;
-      dgemm(g3, s);
-    }
+    if (nc > 0) apply_qt(V, h, w, lda, T, A + c0 + (c0 + w) * lda, nc, sc, s);
   }
   return n;
 }
