@@ -199,7 +199,8 @@ int qdwhp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau,
 
 /*
  * Q(:, c0:c0+q) columns of Q = H_1 ... H_n from qdwhp_geqrf output, written
- * to Q (m x q, ldq >= m): applies the reflectors to the columns c0.. of the
+ * to Q (m x q, ldq >= m; q <= n, c0 + q <= m, else -7: the workspace holds
+ * block products for at most n columns): applies the reflectors to the columns c0.. of the
  * identity (the thin Q of Eq. (2) for c0 = 0, q = n; the trailing columns Q2
  * of Algorithm 1 for c0 = ind - 1).  work must be the workspace of the
  * qdwhp_geqrf call that factored A, unchanged since: it holds the block

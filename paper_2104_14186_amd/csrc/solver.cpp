@@ -775,7 +775,7 @@ extern "C" int qdwhp_orgqr(const double* A, int64_t m, int64_t n, int64_t lda, c
   if (n < 1 || n > m) return -3;
   if (lda < m) return -4;
   if (c0 < 0 || c0 > m) return -6;
-  if (q < 0 || c0 + q > m) return -7;
+  if (q < 0 || q > n || c0 + q > m) return -7;
   if (!Q) return -8;
   if (ldq < m) return -9;
   if (!work) return -10;

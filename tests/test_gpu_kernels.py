@@ -73,7 +73,8 @@ def test_spd_inverse(n):
     assert np.abs(Zi - ref).max() / np.abs(ref).max() < 1e-13 * np.linalg.cond(Z)
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (40, 40), (300, 129), (513, 256), (1024, 512), (700, 700)])
+@pytest.mark.parametrize("m,n", [(1, 1), (40, 40), (300, 129), (513, 256), (1024, 512), (700, 700),
+                                 (1000, 385)])
 def test_qr(m, n):
     torch = _torch()
     import paper_2104_14186_amd as q
@@ -88,12 +89,12 @@ def test_qr(m, n):
     assert np.abs(np.abs(np.diag(R)) - np.abs(np.diag(Rl))).max() < 1e-12 * np.abs(Rl).max()
 
 
-def test_qr_trailing_columns():
+@pytest.mark.parametrize("n,c0", [(300, 170), (700, 300)])
+def test_qr_trailing_columns(n, c0):
     """Columns c0.. of Q of a square matrix (the Q2 of the projector)."""
     torch = _torch()
     import paper_2104_14186_amd as q
     g = np.random.default_rng(11)
-    n, c0 = 300, 170
     A = g.standard_normal((n, n))
     print("qr trailing columns", flush=True)
     Qc, R, _ = q.qr(torch.from_numpy(A).cuda(), c0=c0, q=n - c0)
