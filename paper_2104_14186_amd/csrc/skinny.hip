@@ -1,0 +1,113 @@
+// Products with few right-hand columns, C (m x nv) = alpha A (m x k) B
+// (k x nv), for the Krylov blocks of the estimator (a few Lanczos steps open
+// Algorithms 1 and 2).  With nv = 8 such a product is bound by reading A
+// once from HBM; a 64-wide matrix-core tile would spend 8x its work on
+// padding and leave most of the chip idle.  One thread per row of A: for
+// each k it reads A[i][k] (consecutive rows on consecutive lanes) and
+// updates nv sums with B[k][:] from LDS.  k is split over workgroups;
+// partial sums are added in split order by a second kernel, so results
+// are reproducible bit for bit.
+#include "common.h"
+#include "skinny.h"
+
+namespace qdwhp {
+namespace {
+
+constexpr int ST = 256;   // threads (rows) per workgroup
+constexpr int KC = 128;   // k values staged per pass
+
+template <int NVC>
+__global__ __launch_bounds__(ST) void skinny_kernel(const double* A, int64_t lda, int64_t m, int64_t k,
+                                                    const double* B, int64_t ldb, int nv, int64_t kchunk,
+                                                    double* part) {
+  __shared__ double Bs[KC][NVC];
+  const int64_t i = (int64_t)blockIdx.x * ST + threadIdx.x;
+  const int64_t k0 = (int64_t)blockIdx.y * kchunk;
+  const int64_t k1 = (k0 + kchunk < k) ? k0 + kchunk : k;
+  double acc[NVC];
+#pragma unroll
+  for (int j = 0; j < NVC; ++j) acc[j] = 0.0;
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+    const int kn = (int)((k1 - kb) < KC ? (k1 - kb) : KC);
+    __syncthreads();
+    for (int e = threadIdx.x; e < KC * NVC; e += ST) {
+      const int kk = e % KC, j = e / KC;
+      Bs[kk][j] = (kk < kn && j < nv) ? B[(kb + kk) + (int64_t)j * ldb] : 0.0;
+    }
+    __syncthreads();
+    if (i < m) {
+      const double* Ai = A + i + kb * lda;
+      int kk = 0;
+      for (; kk + 4 <= kn; kk += 4) {   // four independent loads in flight
+        const double a0 = Ai[(int64_t)kk * lda], a1 = Ai[(int64_t)(kk + 1) * lda];
+        const double a2 = Ai[(int64_t)(kk + 2) * lda], a3 = Ai[(int64_t)(kk + 3) * lda];
+#pragma unroll
+        for (int j = 0; j < NVC; ++j) {
+          acc[j] += a0 * Bs[kk][j];
+          acc[j] += a1 * Bs[kk + 1][j];
+          acc[j] += a2 * Bs[kk + 2][j];
+          acc[j] += a3 * Bs[kk + 3][j];
+        }
+      }
+      for (; kk < kn; ++kk) {
+        const double a = Ai[(int64_t)kk * lda];
+#pragma unroll
+        for (int j = 0; j < NVC; ++j) acc[j] += a * Bs[kk][j];
+      }
+    }
+  }
+  if (i < m) {
+    double* p = part + (int64_t)blockIdx.y * m * NVC;
+#pragma unroll
+    for (int j = 0; j < NVC; ++j)
+      if (j < nv) p[i + (int64_t)j * m] = acc[j];
+  }
+}
+
+__global__ void skinny_reduce(const double* part, int64_t m, int nvc, int nv, int splits, double alpha,
+                              double* C, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= m || j >= nv) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += part[(int64_t)z * m * nvc + i + (int64_t)j * m];
+  C[i + (int64_t)j * ldc] = alpha * s;
+}
+
+template <int NVC>
+void launch(const double* A, int64_t lda, int64_t m, int64_t k, const double* B, int64_t ldb, int nv,
+            double alpha, double* C, int64_t ldc, double* ws, int64_t ws_doubles, hipStream_t s) {
+  const int64_t rb = cdiv(m, ST);
+  int64_t S = cdiv(1024, rb);                       // about 1024 workgroups
+  const int64_t smax_k = cdiv(k, 4 * KC);            // at least 4 staged passes per split
+  if (S > smax_k) S = smax_k;
+  const int64_t smax_ws = ws_doubles / (m * NVC);
+  if (S > smax_ws) S = smax_ws;
+  if (S > 64) S = 64;
+  if (S < 1) throw HipError{hipErrorInvalidValue};   // workspace below one split
+  const int64_t kchunk = cdiv(cdiv(k, S), KC) * KC;
+  S = cdiv(k, kchunk);
+  skinny_kernel<NVC><<<dim3((unsigned)rb, (unsigned)S), ST, 0, s>>>(A, lda, m, k, B, ldb, nv, kchunk, ws);
+  QDWHP_LAUNCH_CHECK();
+  skinny_reduce<<<dim3((unsigned)cdiv(m, 256), (unsigned)nv), 256, 0, s>>>(ws, m, NVC, nv, (int)S, alpha, C, ldc);
+  QDWHP_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+int64_t skinny_ws_doubles(int64_t m, int nv) { return m * (nv <= 8 ? 8 : nv <= 16 ? 16 : 32); }
+
+void skinny_gemm(const double* A, int64_t lda, int64_t m, int64_t k, const double* B, int64_t ldb, int nv,
+                 double alpha, double* C, int64_t ldc, double* ws, int64_t ws_doubles, hipStream_t s) {
+  if (m <= 0 || nv <= 0) return;
+  if (nv > 32) throw HipError{hipErrorInvalidValue};
+  if (k <= 0) {
+    fill(C, m, nv, ldc, 0.0, 0.0, s);
+    return;
+  }
+  if (nv <= 8) launch<8>(A, lda, m, k, B, ldb, nv, alpha, C, ldc, ws, ws_doubles, s);
+  else if (nv <= 16) launch<16>(A, lda, m, k, B, ldb, nv, alpha, C, ldc, ws, ws_doubles, s);
+  else launch<32>(A, lda, m, k, B, ldb, nv, alpha, C, ldc, ws, ws_doubles, s);
+}
+
+}  // namespace qdwhp

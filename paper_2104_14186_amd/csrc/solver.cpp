@@ -20,6 +20,7 @@
 #include "elem.h"
 #include "jacobi.h"
 #include "lanczos.h"
+#include "skinny.h"
 #include "qr.h"
 
 using namespace qdwhp;
@@ -360,10 +361,8 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       LanczosOp op;
       op.rows_tmp = 1;
       op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
-        Gemm g;
-        g.M = n; g.N = nv; g.K = n; g.alpha = sgn; g.A = A; g.lda = lda; g.B = in; g.ldb = ldi;
-        g.C = out; g.ldc = ldo;
-        dgemm(g, st);
+        // the big work block is free until the iterations start
+        skinny_gemm(A, lda, n, n, in, ldi, nv, sgn, out, ldo, P.big, P.big_doubles, st);
       };
       lz = lanczos(op, n, nv, (int)msteps, o.seed, P.lz, s);
       if (lz.sweeps < 0) {   // a non-finite input shows up here first
@@ -557,14 +556,25 @@ int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t 
       LanczosOp op;
       op.rows_tmp = mm;
       op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double* tmp, hipStream_t st) {
-        Gemm g;   // tmp = M in   (mm x nv)
-        g.M = mm; g.N = nv; g.K = nn; g.A = A; g.lda = lda; g.ta = tr; g.B = in; g.ldb = ldi;
-        g.C = tmp; g.ldc = mm;
-        dgemm(g, st);
-        Gemm h;   // out = M^T tmp (nn x nv)
-        h.M = nn; h.N = nv; h.K = mm; h.A = A; h.lda = lda; h.ta = !tr; h.B = tmp; h.ldb = mm;
-        h.C = out; h.ldc = ldo;
-        dgemm(h, st);
+        // tmp = M in (mm x nv), out = M^T tmp (nn x nv); the product with A
+        // untransposed runs as a skinny product (the big work block is free
+        // until the iterations start), the transposed one as a GEMM
+        if (!tr) {
+          skinny_gemm(A, lda, mm, nn, in, ldi, nv, 1.0, tmp, mm, P.big, P.big_doubles, st);
+        } else {
+          Gemm g;
+          g.M = mm; g.N = nv; g.K = nn; g.A = A; g.lda = lda; g.ta = true; g.B = in; g.ldb = ldi;
+          g.C = tmp; g.ldc = mm;
+          dgemm(g, st);
+        }
+        if (tr) {
+          skinny_gemm(A, lda, nn, mm, tmp, mm, nv, 1.0, out, ldo, P.big, P.big_doubles, st);
+        } else {
+          Gemm h;
+          h.M = nn; h.N = nv; h.K = mm; h.A = A; h.lda = lda; h.ta = true; h.B = tmp; h.ldb = mm;
+          h.C = out; h.ldc = ldo;
+          dgemm(h, st);
+        }
       };
       lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
       if (lz.sweeps < 0) {   // a non-finite input shows up here first
