@@ -59,15 +59,21 @@ template <> struct MfmaT<true> {
 // contiguous range of the tile list.  Full launches walk groups of GM tile
 // rows column by column (workgroups resident together share A and B slices);
 // upper-triangle launches enumerate exactly the tiles with tm <= tn, column by
-// column, so every XCD gets the same number of tiles.
+// column, so every XCD gets the same number of tiles.  When the K range of an
+// upper-triangle launch follows the tile column (order != 0), the tiles'
+// work grows or shrinks along that enumeration and contiguous ranges would
+// give the first XCD many times the work of the last: such launches deal
+// the tiles round-robin in order of decreasing work instead (even shares
+// per XCD, light tiles last).
 __device__ inline int64_t xcd_remap(int64_t w, int64_t W) {
   const int64_t q = W / 8, r = W % 8, xcd = w % 8, loc = w / 8;
   return (xcd < r) ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
 }
-__device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, int64_t* tm, int64_t* tn) {
+__device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, int order, int64_t* tm,
+                               int64_t* tn) {
   if (upper) {
     const int64_t W = gx * (gx + 1) / 2;
-    const int64_t L = xcd_remap(w, W);
+    const int64_t L = (order == 0) ? xcd_remap(w, W) : (order > 0 ? w : W - 1 - w);
     int64_t c = (int64_t)((sqrt(8.0 * (double)L + 1.0) - 1.0) / 2.0);
     while (c * (c + 1) / 2 > L) --c;
     while ((c + 1) * (c + 2) / 2 <= L) ++c;
@@ -305,7 +311,9 @@ __global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(
   __shared__ typename MfmaT<F32>::elem As[2][BK * (BT + PAD)];
   __shared__ typename MfmaT<F32>::elem Bs[2][BK * (BT + PAD)];
   int64_t tm, tn;
-  tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, &tm, &tn);
+  // k >= tile column: early columns carry the most work; k < column end: late ones
+  const int order = (g.klo == KLO_COL) ? 1 : (g.khi == KHI_COL ? -1 : 0);
+  tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, order, &tm, &tn);
   gemm_tile<TA, TB, F32, BT>(g, tm, tn, blockIdx.z, As, Bs);
 }
 
