@@ -131,8 +131,17 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
     if (klo < z * kc) klo = z * kc;
     if (khi > (z + 1) * kc) khi = (z + 1) * kc;
   }
-  // tiles that need no bounds or structure masks use straight-line loads
-  const bool interior = row0 + TM <= M && col0 + TN <= N && !aul && !bul;
+  // slices that need no bounds or structure masks use straight-line loads:
+  // the tile lies inside C, the slice inside [klo, khi), and a unit-lower
+  // operand's slice lies strictly below its diagonal (stored row > stored
+  // column for every element), which for Householder vectors is all but
+  // the slices that meet the top block
+  const bool interior = row0 + TM <= M && col0 + TN <= N;
+  auto mask_free = [&](int64_t k0) {
+    const bool af = !aul || (TA ? k0 >= row0 + TM : row0 >= k0 + BK);
+    const bool bf = !bul || (TB ? col0 >= k0 + BK : k0 >= col0 + TN);
+    return af && bf;
+  };
 
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
@@ -190,7 +199,7 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
 
   auto load = [&](int64_t k0) {
     const __amdgpu_buffer_rsrc_t rsa = slice_a(k0), rsb = slice_b(k0);
-    if (interior && k0 + BK <= khi) {
+    if (interior && k0 + BK <= khi && mask_free(k0)) {
 #pragma unroll
       for (int r = 0; r < TNLD; ++r) ra[r] = (E)ld(rsa, aoff[r]);
 #pragma unroll
