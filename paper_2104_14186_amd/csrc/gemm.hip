@@ -474,7 +474,8 @@ void dgemm(const Gemm& g0, hipStream_t s) {
     throw HipError{hipErrorInvalidValue};   // leading dimension too large
   const int64_t tiles = ((g.tiles == TILES_UPPER) ? tm * (tm + 1) / 2 : tm * tn) * g.batch;
   if (g.batch == 1 && g.ws && g.tiles == TILES_ALL && tiles < 160 && g.K >= 4 * BK * 8) {
-    int64_t S = cdiv(320, tiles);
+    // as many K shares as fill the chip's 512 resident workgroups (two per CU) in one pass
+    int64_t S = 512 / tiles;
     const int64_t kmax = g.K / (BK * 8);
     if (S > kmax) S = kmax;
     const int64_t cap = g.ws_doubles / (g.M * g.N);

@@ -287,9 +287,17 @@ __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ld
     const int i = t;
     L[i][i] = tau[i];                       // T(i,i), stored at L[i][i]
     for (int j = i + 1; j < w; ++j) {
-      double acc = 0.0;
-      for (int k = i; k < j; ++k) acc += L[k][i] * L[k][j];   // T(i,k) = L[k][i]; G(k,j) = L[k][j]
-      L[j][i] = -tau[j] * acc;
+      // T(i,k) = L[k][i]; G(k,j) = L[k][j]; four independent chains
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      int k = i;
+      for (; k + 4 <= j; k += 4) {
+        a0 += L[k][i] * L[k][j];
+        a1 += L[k + 1][i] * L[k + 1][j];
+        a2 += L[k + 2][i] * L[k + 2][j];
+        a3 += L[k + 3][i] * L[k + 3][j];
+      }
+      for (; k < j; ++k) a0 += L[k][i] * L[k][j];
+      L[j][i] = -tau[j] * ((a0 + a1) + (a2 + a3));
     }
   }
   __syncthreads();
