@@ -550,6 +550,29 @@ __global__ void scale_cols_kernel(double* R, int64_t ldr, int64_t rows, const do
 // ||H||_F in two fixed-order stages: column-strided partial sums per
 // workgroup, then one workgroup adds the partials.
 constexpr int FROB_WG = 256;
+
+// Largest off-diagonal magnitude of the block-upper H (n x n, ld ldh; the
+// stored rows of column j are those of blocks up to j's), max-combined into
+// *out (>= 0, zeroed by the caller); a NaN counts as infinite.
+__global__ void off_max_kernel(const double* H, int64_t ldh, int64_t n, double* out) {
+  __shared__ double red[4];
+  double m = 0.0;
+  for (int64_t j = blockIdx.x; j < n; j += gridDim.x) {
+    const int64_t rows = (j / JB + 1) * JB < n ? (j / JB + 1) * JB : n;
+    for (int64_t i = threadIdx.x; i < rows; i += blockDim.x) {
+      const double a = fabs(H[i + j * ldh]);
+      if (i != j && !(a <= m)) m = (a == a) ? a : INFINITY;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = fmax(r, red[w]);
+    atomic_max_nonneg(out, r);
+  }
+}
 __global__ void frob_part_kernel(const double* H, int64_t ldh, int64_t n, double* part) {
   __shared__ double red[256];
   double acc = 0.0;
@@ -646,7 +669,7 @@ int64_t jacobi_padded(int64_t n) { int64_t nb = cdiv(n > 0 ? n : 1, JB); if (nb 
 
 int64_t syev_scratch_doubles(int64_t n) {
   const int64_t np = jacobi_padded(n);
-  return np * np * 2 + kRing * (np / JB / 2) * P2 * P2 + 64 + 2 * np + kRing * (np / JB / 2) + 256;
+  return np * np * 2 + kRing * (np / JB / 2) * P2 * P2 + 128 + 2 * np + kRing * (np / JB / 2) + 256;
 }
 
 // H (n x n, ldh) is copied into a padded work matrix; results: w[n] descending,
@@ -660,14 +683,14 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   const int np2 = nb / 2;
   const int64_t jslot = (int64_t)np2 * P2 * P2;
   double* Jb = Vp + np * np;                 // kRing slots of np2 rotations
-  double* offmax = Jb + kRing * jslot;
-  int64_t* rank = (int64_t*)(offmax + 64);
+  double* offmax = Jb + kRing * jslot;       // [0, 64): pair measure per sweep; [64, 128): end of sweep
+  int64_t* rank = (int64_t*)(offmax + 128);
   double* fro = (double*)(rank + np);
   int* act = (int*)(fro + 8);                // kRing slots of np2 flags
   fill(Hp, np, np, np, 0.0, 0.0, s);
   copy(H, ldh, Hp, np, n, n, s);
   fill(Vp, np, np, np, 0.0, 1.0, s);
-  QDWHP_HIP(hipMemsetAsync(offmax, 0, 64 * sizeof(double), s));
+  QDWHP_HIP(hipMemsetAsync(offmax, 0, 128 * sizeof(double), s));
   {   // the pair-rotation buffer is free until the sweeps start
     const int g = (int)std::min<int64_t>(FROB_WG, np);
     frob_part_kernel<<<g, 256, 0, s>>>(Hp, np, np, Jb);
@@ -723,10 +746,16 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
       QDWHP_LAUNCH_CHECK();
       QDWHP_HIP(hipEventRecord((*aux)->done[slot], s2));
     }
-    double off = 0.0;
+    // the off-diagonal part as the sweep leaves it: at or below tol, the next
+    // sweep would rotate nothing (every |h_pq| <= tol is skipped), so it is
+    // not run
+    off_max_kernel<<<256, 256, 0, s>>>(Hp, np, np, offmax + 64 + sw);
+    QDWHP_LAUNCH_CHECK();
+    double off = 0.0, endm = 0.0;
     QDWHP_HIP(hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipMemcpyAsync(&endm, offmax + 64 + sw, sizeof(double), hipMemcpyDeviceToHost, s));
     QDWHP_HIP(hipStreamSynchronize(s));
-    if (converged(off, prev, a.tol, sw)) { sweeps = sw + 1; break; }
+    if (converged(off, prev, a.tol, sw) || endm <= a.tol) { sweeps = sw + 1; break; }
     prev = off;
   }
   if (aux && round > 0)   // the last eigenvector updates precede the gather below
