@@ -320,7 +320,8 @@ int qdwhp_serve_destroy(qdwhp_server* srv);
 /*
  * Named integer parameters read by launch-shape decisions, written by the
  * autotuner (or by hand).  Keys: "gemm.small_tiles" (a GEMM whose 128x128
- * tile count is below this value runs with 64x64 tiles; default 96),
+ * tile count is below this value runs with 64x64 tiles; default 96; GEMMs
+ * with k <= 128 and FP32-operand GEMMs always take 64x64 tiles),
  * "batch.lanes" (default 8), "serve.lanes" (default 8), "jacobi.fused_max"
  * (two-sided Jacobi problems up to this size update H and V in one launch
  * per round; default 2048).  Unset keys keep
