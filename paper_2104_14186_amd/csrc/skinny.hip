@@ -1,5 +1,5 @@
 // Products with few right-hand columns, C (m x nv) = alpha A (m x k) B
-// (k x nv), for the Krylov blocks of the estimator (a few Lanczos steps open
+// (k x nv) and C (n x nv) = alpha A^T B, for the Krylov blocks of the estimator (a few Lanczos steps open
 // Algorithms 1 and 2).  With nv = 8 such a product is bound by reading A
 // once from HBM; a 64-wide matrix-core tile would spend 8x its work on
 // padding and leave most of the chip idle.  One thread per row of A: for
@@ -93,7 +93,67 @@ void launch(const double* A, int64_t lda, int64_t m, int64_t k, const double* B,
   QDWHP_LAUNCH_CHECK();
 }
 
+// C (n x nv) = alpha A^T B for A m x n (lda), B m x nv: CT columns of A per
+// workgroup; a thread runs over rows t, t + ST, ... of its columns and keeps
+// CT x NVC sums, which the workgroup then adds (butterflies inside each
+// wave, then the four waves in order), so results are reproducible.
+constexpr int CT = 8;   // columns of A per workgroup
+
+template <int NVC>
+__global__ __launch_bounds__(ST) void skinny_t_kernel(const double* A, int64_t lda, int64_t m, int64_t n,
+                                                      const double* B, int64_t ldb, int nv, double alpha,
+                                                      double* C, int64_t ldc) {
+  __shared__ double red[ST / 64][CT * NVC];
+  const int64_t c0 = (int64_t)blockIdx.x * CT;
+  double acc[CT][NVC];
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int j = 0; j < NVC; ++j) acc[c][j] = 0.0;
+  for (int64_t r = threadIdx.x; r < m; r += ST) {
+    double b[NVC], a[CT];
+#pragma unroll
+    for (int j = 0; j < NVC; ++j) b[j] = (j < nv) ? B[r + (int64_t)j * ldb] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) a[c] = (c0 + c < n) ? A[r + (c0 + c) * lda] : 0.0;
+#pragma unroll
+    for (int c = 0; c < CT; ++c)
+#pragma unroll
+      for (int j = 0; j < NVC; ++j) acc[c][j] += a[c] * b[j];
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < CT; ++c)
+#pragma unroll
+    for (int j = 0; j < NVC; ++j) {
+      double v = acc[c][j];
+      for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+      if (lane == 0) red[wv][c * NVC + j] = v;
+    }
+  __syncthreads();
+  for (int e = threadIdx.x; e < CT * NVC; e += ST) {
+    const int c = e / NVC, j = e % NVC;
+    if (c0 + c < n && j < nv) {
+      double v = red[0][e];
+      for (int w = 1; w < ST / 64; ++w) v += red[w][e];
+      C[(c0 + c) + (int64_t)j * ldc] = alpha * v;
+    }
+  }
+}
+
 }  // namespace
+
+void skinny_gemm_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* B, int64_t ldb, int nv,
+                   double alpha, double* C, int64_t ldc, hipStream_t s) {
+  if (n <= 0 || nv <= 0) return;
+  if (nv > 8) throw HipError{hipErrorInvalidValue};
+  if (m <= 0) {
+    fill(C, n, nv, ldc, 0.0, 0.0, s);
+    return;
+  }
+  skinny_t_kernel<8><<<(unsigned)cdiv(n, CT), ST, 0, s>>>(A, lda, m, n, B, ldb, nv, alpha, C, ldc);
+  QDWHP_LAUNCH_CHECK();
+}
 
 int64_t skinny_ws_doubles(int64_t m, int nv) { return m * (nv <= 8 ? 8 : nv <= 16 ? 16 : 32); }
 

@@ -556,24 +556,25 @@ int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t 
       LanczosOp op;
       op.rows_tmp = mm;
       op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double* tmp, hipStream_t st) {
-        // tmp = M in (mm x nv), out = M^T tmp (nn x nv); the product with A
-        // untransposed runs as a skinny product (the big work block is free
-        // until the iterations start), the transposed one as a GEMM
+        // tmp = M in (mm x nv), out = M^T tmp (nn x nv), as skinny products
+        // (the big work block is free until the iterations start); the
+        // transposed kernel takes up to 8 columns, wider blocks use the GEMM
+        auto at_b = [&](int64_t rows, int64_t cols, const double* B, int64_t ldb, double* C, int64_t ldc) {
+          if (nv <= 8) {
+            skinny_gemm_t(A, lda, rows, cols, B, ldb, nv, 1.0, C, ldc, st);
+          } else {
+            Gemm g;
+            g.M = cols; g.N = nv; g.K = rows; g.A = A; g.lda = lda; g.ta = true; g.B = B; g.ldb = ldb;
+            g.C = C; g.ldc = ldc;
+            dgemm(g, st);
+          }
+        };
         if (!tr) {
           skinny_gemm(A, lda, mm, nn, in, ldi, nv, 1.0, tmp, mm, P.big, P.big_doubles, st);
+          at_b(mm, nn, tmp, mm, out, ldo);
         } else {
-          Gemm g;
-          g.M = mm; g.N = nv; g.K = nn; g.A = A; g.lda = lda; g.ta = true; g.B = in; g.ldb = ldi;
-          g.C = tmp; g.ldc = mm;
-          dgemm(g, st);
-        }
-        if (tr) {
+          at_b(nn, mm, in, ldi, tmp, mm);
           skinny_gemm(A, lda, nn, mm, tmp, mm, nv, 1.0, out, ldo, P.big, P.big_doubles, st);
-        } else {
-          Gemm h;
-          h.M = nn; h.N = nv; h.K = mm; h.A = A; h.lda = lda; h.ta = true; h.B = tmp; h.ldb = mm;
-          h.C = out; h.ldc = ldo;
-          dgemm(h, st);
         }
       };
       lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
