@@ -272,21 +272,29 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
 
 // T (w x w, upper) of the compact WY form from G = V^T V and tau:
 // T(j,j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One LDS array
-// holds G above the diagonal and T^T on and below it.  Thread i owns row i of
-// T and runs over j (rows are independent).
+// holds G above the diagonal and T^T on and below it.
+//   1. the diagonal blocks of TL = 32 by the recurrence, thread i owning row
+//      i of its block (rows are independent);
+//   2. blocks merged pairwise, 32 -> 64 -> 128: for consecutive reflector
+//      sets with factors T1, T2 the merged factor has the off-diagonal block
+//      T12 = -T1 (V1^T V2) T2 = -T1 G12 T2, formed as Y = G12 T2 (T2 upper)
+//      then -T1 Y (T1 upper), 32 columns of Y at a time in LDS.
+// The recurrence alone would leave row 0 a chain of w^2/2 dependent steps.
+constexpr int TL = 32;
 __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
                                                      double* T, int64_t ldt, int w) {
-  __shared__ double L[QB][QB + 1];
+  __shared__ double L[QB][QB];          // row pitch QB: the diagonal walk of step 1 has odd stride
+  __shared__ double Ys[2 * TL][TL + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < QB * QB; e += QB) {
-    const int r = e % QB, c = e / QB;
-    L[r][c] = (r < c && r < w && c < w) ? G[r + (int64_t)c * ldg] : 0.0;
+  for (int e = t; e < w * w; e += QB) {   // only the w x w corner is used
+    const int r = e % w, c = e / w;
+    L[r][c] = (r < c) ? G[r + (int64_t)c * ldg] : 0.0;
   }
   __syncthreads();
   if (t < w) {
-    const int i = t;
+    const int i = t, jend = ((i / TL + 1) * TL < w) ? (i / TL + 1) * TL : w;
     L[i][i] = tau[i];                       // T(i,i), stored at L[i][i]
-    for (int j = i + 1; j < w; ++j) {
+    for (int j = i + 1; j < jend; ++j) {
       // T(i,k) = L[k][i]; G(k,j) = L[k][j]; four independent chains
       double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
       int k = i;
@@ -301,9 +309,51 @@ __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ld
     }
   }
   __syncthreads();
-  for (int e = t; e < QB * QB; e += QB) {
-    const int r = e % QB, c = e / QB;
-    if (r < w && c < w) T[r + (int64_t)c * ldt] = (r <= c) ? L[c][r] : 0.0;
+  for (int sz = TL; sz < w; sz *= 2) {            // merge blocks of sz into 2 sz
+    // combos a0 = 0, 2 sz, ...; each takes sz rows of Ys, TL columns at a time
+    const int ncombo = (QB / (2 * sz)) < 1 ? 1 : QB / (2 * sz);
+    for (int cb = 0; cb < sz; cb += TL) {
+      // Y(r, c) = sum_{k <= c} G(a0 + r, a0 + sz + k) T(a0 + sz + k, a0 + sz + c)
+      for (int e = t; e < ncombo * sz * TL; e += QB) {
+        const int cc = e % TL, r = (e / TL) % sz, q = e / (TL * sz);
+        const int a0 = q * 2 * sz, c = cb + cc;
+        if (a0 + sz + c >= w) continue;
+        const int bj = a0 + sz;
+        double a0s = 0.0, a1s = 0.0, a2s = 0.0, a3s = 0.0;   // independent chains
+        int k = 0;
+        for (; k + 3 <= c; k += 4) {
+          a0s += L[a0 + r][bj + k] * L[bj + c][bj + k];
+          a1s += L[a0 + r][bj + k + 1] * L[bj + c][bj + k + 1];
+          a2s += L[a0 + r][bj + k + 2] * L[bj + c][bj + k + 2];
+          a3s += L[a0 + r][bj + k + 3] * L[bj + c][bj + k + 3];
+        }
+        for (; k <= c; ++k) a0s += L[a0 + r][bj + k] * L[bj + c][bj + k];
+        Ys[q * sz + r][cc] = (a0s + a1s) + (a2s + a3s);
+      }
+      __syncthreads();
+      // T(a0 + r, a0 + sz + c) = -sum_{k >= r} T(a0 + r, a0 + k) Y(k, c)
+      for (int e = t; e < ncombo * sz * TL; e += QB) {
+        const int cc = e % TL, r = (e / TL) % sz, q = e / (TL * sz);
+        const int a0 = q * 2 * sz, c = cb + cc;
+        if (a0 + sz + c >= w) continue;
+        const int yb = q * sz;
+        double a0s = 0.0, a1s = 0.0, a2s = 0.0, a3s = 0.0;
+        int k = r;
+        for (; k + 4 <= sz; k += 4) {
+          a0s += L[a0 + k][a0 + r] * Ys[yb + k][cc];
+          a1s += L[a0 + k + 1][a0 + r] * Ys[yb + k + 1][cc];
+          a2s += L[a0 + k + 2][a0 + r] * Ys[yb + k + 2][cc];
+          a3s += L[a0 + k + 3][a0 + r] * Ys[yb + k + 3][cc];
+        }
+        for (; k < sz; ++k) a0s += L[a0 + k][a0 + r] * Ys[yb + k][cc];
+        L[a0 + sz + c][a0 + r] = -((a0s + a1s) + (a2s + a3s));
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < w * w; e += QB) {
+    const int r = e % w, c = e / w;
+    T[r + (int64_t)c * ldt] = (r <= c) ? L[c][r] : 0.0;
   }
 }
 
