@@ -64,7 +64,8 @@ template <> struct MfmaT<true> {
 // work grows or shrinks along that enumeration and contiguous ranges would
 // give the first XCD many times the work of the last: such launches deal
 // the tiles round-robin in order of decreasing work instead (even shares
-// per XCD, light tiles last).
+// per XCD, light tiles last).  Full launches whose K range follows the tile
+// row (row groups are contiguous in the enumeration) are dealt the same way.
 __device__ inline int64_t xcd_remap(int64_t w, int64_t W) {
   const int64_t q = W / 8, r = W % 8, xcd = w % 8, loc = w / 8;
   return (xcd < r) ? xcd * (q + 1) + loc : r * (q + 1) + (xcd - r) * q + loc;
@@ -81,7 +82,7 @@ __device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, in
     *tm = L - c * (c + 1) / 2;
     return;
   }
-  const int64_t L = xcd_remap(w, gx * gy);
+  const int64_t L = (order == 0) ? xcd_remap(w, gx * gy) : (order > 0 ? w : gx * gy - 1 - w);
   const int64_t per = (int64_t)GM * gy;
   const int64_t grp = L / per, first = grp * GM;
   const int64_t gm = (gx - first < GM) ? gx - first : GM;
@@ -320,8 +321,12 @@ __global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(
   __shared__ typename MfmaT<F32>::elem As[2][BK * (BT + PAD)];
   __shared__ typename MfmaT<F32>::elem Bs[2][BK * (BT + PAD)];
   int64_t tm, tn;
-  // k >= tile column: early columns carry the most work; k < column end: late ones
-  const int order = (g.klo == KLO_COL) ? 1 : (g.khi == KHI_COL ? -1 : 0);
+  // upper launches: k >= tile column puts the work in early columns, k < column
+  // end in late ones; full launches: the same along rows (their enumeration
+  // walks row groups)
+  const int order = (g.tiles == TILES_UPPER)
+                        ? ((g.klo == KLO_COL) ? 1 : (g.khi == KHI_COL ? -1 : 0))
+                        : ((g.klo == KLO_ROW) ? 1 : (g.khi == KHI_ROW ? -1 : 0));
   tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, order, &tm, &tn);
   gemm_tile<TA, TB, F32, BT>(g, tm, tn, blockIdx.z, As, Bs);
 }
