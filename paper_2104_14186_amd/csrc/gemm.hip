@@ -323,10 +323,11 @@ __global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(
   int64_t tm, tn;
   // upper launches: k >= tile column puts the work in early columns, k < column
   // end in late ones; full launches: the same along rows (their enumeration
-  // walks row groups)
+  // walks row groups), and k < column end puts it at the end of every row
+  // group (reversed, the heavy tiles go first and the light ones fill the tail)
   const int order = (g.tiles == TILES_UPPER)
                         ? ((g.klo == KLO_COL) ? 1 : (g.khi == KHI_COL ? -1 : 0))
-                        : ((g.klo == KLO_ROW) ? 1 : (g.khi == KHI_ROW ? -1 : 0));
+                        : ((g.klo == KLO_ROW) ? 1 : ((g.khi == KHI_ROW || g.khi == KHI_COL) ? -1 : 0));
   tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, order, &tm, &tn);
   gemm_tile<TA, TB, F32, BT>(g, tm, tn, blockIdx.z, As, Bs);
 }
