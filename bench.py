@@ -165,8 +165,10 @@ def cpu_baseline(n_full, fraction, budget):
 
 
 def gemm_probe(torch, dev, n):
-    """Copy calibration (1 GiB read + written, twice) and the dominant GEMMs of
-    a Cholesky-based step at size n: Z = X^T X (upper tiles) and X W (full)."""
+    """Copy calibration (1 GiB read + written, twice), the dominant GEMMs of
+    a Cholesky-based step at size n: Z = X^T X (upper tiles) and X W (full),
+    in FP64 and with FP32 operands (twice each), and a Householder QR of an
+    n x n/8 matrix (the panel kernels of the projector and stacked QRs)."""
     import ctypes
     import paper_2104_14186_amd as q
     x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
@@ -184,11 +186,22 @@ def gemm_probe(torch, dev, n):
     st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     L = q.lib()
     p = lambda t: ctypes.c_void_p(t.data_ptr())
-    for _ in range(2):
-        assert L.qdwhp_dgemm(1, 0, n, n, n, 1.0, p(X), n, p(X), n, 0.0, p(Z), n, 1, st) == 0
-        assert L.qdwhp_dgemm(0, 0, n, n, n, 1.0, p(X), n, p(W), n, 0.0, p(Z), n, 0, st) == 0
+    for f32 in (0, 2):
+        for _ in range(2):
+            assert L.qdwhp_dgemm(1, 0, n, n, n, 1.0, p(X), n, p(X), n, 0.0, p(Z), n, 1 | f32, st) == 0
+            assert L.qdwhp_dgemm(0, 0, n, n, n, 1.0, p(X), n, p(W), n, 0.0, p(Z), n, f32, st) == 0
     torch.cuda.synchronize()
-    print(json.dumps({"gemm_probe": n}), flush=True)
+    del W, Z
+    nc = max(1, n // 8)
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    P = torch.randn((nc, n), dtype=torch.float64, device=dev, generator=g)   # column-major n x nc
+    tau = torch.empty(nc, dtype=torch.float64, device=dev)
+    nbytes = L.qdwhp_geqrf_workspace(n, nc)
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=dev)
+    assert L.qdwhp_geqrf(p(P), n, nc, n, p(tau), p(ws), nbytes, st) == 0
+    torch.cuda.synchronize()
+    print(json.dumps({"gemm_probe": n, "qr_probe": [n, nc]}), flush=True)
 
 
 def main():
