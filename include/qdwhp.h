@@ -110,6 +110,9 @@ typedef struct {
                               Q2, Rayleigh-Ritz products, small solve, vectors, total */
   double  flops_table1;    /* useful flops by the paper's Table 1 accounting        */
   int     status;          /* mirrors the return value                              */
+  int64_t rr_split;        /* EIG: size r of the exact spectral split of the
+                              Rayleigh-Ritz matrix solved by Jacobi (0: the whole
+                              ell x ell matrix was)                                */
 } qdwhp_info;
 
 void qdwhp_opts_default(qdwhp_opts* opts);
@@ -324,7 +327,12 @@ int qdwhp_serve_destroy(qdwhp_server* srv);
  * with k <= 128 and FP32-operand GEMMs always take 64x64 tiles),
  * "batch.lanes" (default 8), "serve.lanes" (default 8), "jacobi.fused_max"
  * (two-sided Jacobi problems up to this size update H and V in one launch
- * per round; default 2048).  Unset keys keep
+ * per round; default 2048), "rr.split_min" and "rr.split_pct" (EIG
+ * Rayleigh-Ritz matrices of at least split_min rows (default 3000) whose
+ * wanted part, with a margin of max(16, k/32), is at most split_pct percent
+ * of them (default 85) are first split exactly at a Lanczos-placed shift by
+ * a converged QDWH polar decomposition, and only the wanted block goes to
+ * Jacobi).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.
  */
 int qdwhp_tune_set(const char* key, int64_t value);

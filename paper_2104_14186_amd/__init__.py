@@ -46,7 +46,8 @@ class Info(ctypes.Structure):
                 ("n_iter", ctypes.c_int), ("kinds", ctypes.c_int * 16),
                 ("weights", (ctypes.c_double * 3) * 16), ("retries", ctypes.c_int),
                 ("jacobi_sweeps", ctypes.c_int), ("ms", ctypes.c_double * 8),
-                ("flops_table1", ctypes.c_double), ("status", ctypes.c_int)]
+                ("flops_table1", ctypes.c_double), ("status", ctypes.c_int),
+                ("rr_split", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_

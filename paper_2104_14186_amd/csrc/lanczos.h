@@ -30,6 +30,9 @@ struct LanczosResult {
 };
 
 int64_t lanczos_doubles(int64_t n, int64_t rows_op, int nv, int m);
+// out[0 .. count) = Gaussian entries 0 .. count-1 of Philox stream `stream`
+// (the layout above).
+void gaussian_fill(double* out, int64_t count, uint64_t seed, uint64_t stream, hipStream_t s);
 LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t seed, double* ws,
                       hipStream_t s);
 

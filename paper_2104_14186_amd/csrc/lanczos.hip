@@ -355,6 +355,12 @@ int64_t lanczos_doubles(int64_t n, int64_t rows_op, int nv, int m) {
          + 4 * N + 3 * N + 2 * nv + 256;       // tridiagonal scratch, nodes, amax/flags
 }
 
+void gaussian_fill(double* out, int64_t count, uint64_t seed, uint64_t stream, hipStream_t s) {
+  if (count <= 0) return;
+  gaussian_kernel<<<(unsigned)cdiv(cdiv(count, 2), 256), 256, 0, s>>>(out, count, seed, stream);
+  QDWHP_LAUNCH_CHECK();
+}
+
 // Runs the Lanczos processes; `op` applies the operator to nv columns.
 LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t seed, double* ws,
                       hipStream_t s) {

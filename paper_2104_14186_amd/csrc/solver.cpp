@@ -306,6 +306,150 @@ void run_iterations(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, con
   body(X, Xn, nullptr);
 }
 
+// Orthonormal basis of the columns of Y (rows x r, ld rows) by one Cholesky
+// QR round: Q = Y W^{-1} with W^T W = Y^T Y.  gram: r x r; spd:
+// spd_inverse_doubles(r).  Sets *flag on a non-positive pivot.
+void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd, double* Q, int* flag,
+             hipStream_t s) {
+  Gemm g;
+  g.M = r; g.N = r; g.K = rows; g.A = Y; g.lda = rows; g.ta = true; g.B = Y; g.ldb = rows;
+  g.C = gram; g.ldc = r; g.tiles = TILES_UPPER;
+  dgemm(g, s);
+  chol_inverse_factor(gram, r, r, spd, flag, s);
+  Gemm t;
+  t.M = rows; t.N = r; t.K = r; t.A = Y; t.lda = rows; t.B = spd; t.ldb = r; t.C = Q; t.ldc = rows;
+  t.khi = KHI_COL;
+  dgemm(t, s);
+}
+
+// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
+// Sec. 2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate of
+// H's spectrum so that about k + margin eigenvalues lie above it; the
+// polar factor of (H - sigma I) / alpha, taken to convergence by the
+// scalar schedule of Sec. 3.1 from a lower bound 1e-12, is sign(H - sigma I),
+// so C = (I + X) / 2 projects onto the invariant subspace of the r
+// eigenvalues above sigma.  Two subspace passes (C Omega, then C Q1, each
+// orthonormalised) give an orthonormal basis Q1 of range(C); the r x r
+// problem Q1^T H Q1 holds exactly those eigenvalues and is solved by Jacobi.
+// The split is checked: every column of H Q1 - Q1 (Q1^T H Q1) must be below
+// 5e-14 ||H||, else (or when r < k, a pivot fails, or the buffers are too
+// small) it returns 0 and H is untouched for the plain solve.  On success
+// vals[0 .. r) holds the eigenvalues (descending), vals[r .. ell) -1e300,
+// Wv (ell x r, ld ell) the eigenvectors; returns r.
+//   ybuf (ybuf_doubles): free during the call; zbuf = Wv (zbuf_doubles);
+//   jscr: scratch of at least syev_scratch_doubles(ell).
+int64_t rr_split(const double* H, int64_t ell, int64_t k, const qdwhp_opts& o, const Plan& P, double* ybuf,
+                 int64_t ybuf_doubles, double* Wv, int64_t zbuf_doubles, double* jscr, double* vals,
+                 int* sweeps, hipStream_t s) {
+  const int64_t e2 = ell * ell;
+  const int nv = lz_vectors(o);
+  const int64_t margin = std::max<int64_t>(16, k / 32);
+  if (ell < qdwhp_tune_get("rr.split_min", 3000) || 100 * (k + margin) > qdwhp_tune_get("rr.split_pct", 85) * ell)
+    return 0;
+  const int64_t wsd = skinny_ws_doubles(ell, nv);
+  if (ybuf_doubles < 5 * e2 + wsd + 1024 || zbuf_doubles < 4 * e2 + 2 * ell) return 0;
+  double* X = ybuf;
+  double* Xn = X + e2;
+  double* Cp = Xn + e2;          // Z of the steps, then the projector C
+  double* Q1 = Cp + e2;          // ell x r
+  double* H1 = Q1 + e2;          // r x r
+  double* ws = H1 + e2;
+  double* big = Wv;              // step buffers, then the subspace passes
+  // ---- sigma from a Lanczos estimate of H's spectrum
+  LanczosOp op;
+  op.rows_tmp = 1;
+  op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
+    skinny_gemm(H, ell, ell, ell, in, ldi, nv, 1.0, out, ldo, ws, wsd, st);
+  };
+  const LanczosResult lz = lanczos(op, ell, nv, (int)lz_steps(o, ell), o.seed + 1, P.lz, s);
+  if (lz.sweeps < 0) return 0;
+  double lmax = -std::numeric_limits<double>::infinity(), lmin = std::numeric_limits<double>::infinity();
+  for (size_t i = 0; i < lz.nodes.size(); ++i) {
+    lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
+    lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
+  }
+  double sigma = 0.0;
+  if (!cut_below(lz.nodes, lz.weights, ell, nv, lmax, lmin, k + margin, &sigma)) return 0;
+  const double alpha = 1.05 * std::max(lmax - sigma, sigma - lmin);
+  const double hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) return 0;
+  // ---- X -> sign((H - sigma I) / alpha)
+  eig_x0(H, ell, X, ell, ell, 1.0 / alpha, -sigma, -1.0, 0.0, s);
+  StepBufs sb;
+  sb.Z = Cp; sb.spd = big; sb.W = big; sb.Q = big + 2 * e2;
+  sb.tau = P.tau; sb.Tall = P.Tall; sb.qrs = P.qrs; sb.flag = P.flags;
+  const std::vector<DwhStep> sched = svd_schedule(1e-12, o.kappa_max, false);
+  run_iterations(X, Xn, ell, ell, true, sched, false, {}, P, sb, false, s);
+  half_plus_identity(X, ell, Cp, ell, ell, s);
+  std::vector<double> d(ell);
+  diagonal(Cp, ell, ell, P.diag, s);
+  QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+  int hf = 0;
+  QDWHP_HIP(hipMemcpyAsync(&hf, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  auto failed = [&]() {
+    QDWHP_HIP(hipMemsetAsync(P.flags, 0, sizeof(int), s));
+    return (int64_t)0;
+  };
+  if (hf) return failed();
+  double tr = 0.0;
+  for (double v : d) tr += v;
+  if (!std::isfinite(tr)) return 0;
+  const int64_t r = (int64_t)std::llround(tr);
+  if (r < k || r >= ell) return 0;
+  // ---- orthonormal basis of range(C): C Omega, then C Q1
+  double* G = big;               // ell x r
+  double* Yb = G + ell * r;      // ell x r
+  double* gram = Yb + ell * r;   // r x r
+  double* spd = gram + r * r;    // spd_inverse_doubles(r)
+  if (zbuf_doubles < 2 * ell * r + r * r + spd_inverse_doubles(r)) return 0;
+  gaussian_fill(G, ell * r, o.seed + 2, 0, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    Gemm g;
+    g.M = ell; g.N = r; g.K = ell; g.A = Cp; g.lda = ell; g.B = pass ? Q1 : G; g.ldb = ell;
+    g.C = Yb; g.ldc = ell;
+    dgemm(g, s);
+    chol_qr(Yb, ell, r, gram, spd, Q1, P.flags, s);
+  }
+  // ---- H1 = Q1^T H Q1 and the check of the split
+  {
+    Gemm g;
+    g.M = ell; g.N = r; g.K = ell; g.A = H; g.lda = ell; g.B = Q1; g.ldb = ell; g.C = Yb; g.ldc = ell;
+    dgemm(g, s);
+    Gemm h;
+    h.M = r; h.N = r; h.K = ell; h.A = Q1; h.lda = ell; h.ta = true; h.B = Yb; h.ldb = ell;
+    h.C = H1; h.ldc = r;
+    dgemm(h, s);
+    symmetrize(H1, r, r, s);
+    Gemm e;   // Yb <- H Q1 - Q1 H1
+    e.M = ell; e.N = r; e.K = r; e.alpha = -1.0; e.beta = 1.0; e.A = Q1; e.lda = ell; e.B = H1; e.ldb = r;
+    e.C = Yb; e.ldc = ell;
+    dgemm(e, s);
+    Gemm n2;  // column norms^2 of the residual on the diagonal of Yb^T Yb
+    n2.M = r; n2.N = r; n2.K = ell; n2.A = Yb; n2.lda = ell; n2.ta = true; n2.B = Yb; n2.ldb = ell;
+    n2.C = gram; n2.ldc = r; n2.tiles = TILES_UPPER;
+    dgemm(n2, s);
+    std::vector<double> cn(r);
+    diagonal(gram, r, r, P.diag, s);
+    QDWHP_HIP(hipMemcpyAsync(cn.data(), P.diag, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipMemcpyAsync(&hf, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipStreamSynchronize(s));
+    if (hf) return failed();
+    double worst = 0.0;
+    for (double v : cn) worst = std::max(worst, std::isfinite(v) ? v : 1e300);
+    if (!(std::sqrt(worst) <= 5e-14 * hnorm)) return 0;
+  }
+  // ---- Jacobi on the wanted block; eigenvectors Q1 W1
+  double* W1 = X;                // r x r (the iterate is no longer needed)
+  *sweeps = syev(H1, r, r, vals, W1, r, jscr, s);
+  if (*sweeps < 0) return 0;
+  fill(vals + r, ell - r, 1, ell - r, -1e300, -1e300, s);
+  Gemm v;
+  v.M = ell; v.N = r; v.K = r; v.A = Q1; v.lda = ell; v.B = W1; v.ldb = r; v.C = Wv; v.ldc = ell;
+  dgemm(v, s);
+  return r;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -460,7 +604,9 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       symmetrize(H, ell, ell, s);
       ev.mark(5, s);
       Wv = P.Z;
-      const int sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
+      int sweeps = -1;
+      info->rr_split = rr_split(H, ell, k, o, P, Y, n * n, Wv, n * n, P.big + ell * ell, P.vals, &sweeps, s);
+      if (info->rr_split == 0) sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
       info->jacobi_sweeps = sweeps;
       if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);
       theta.resize(ell);
