@@ -298,7 +298,7 @@ def main():
         "mfma_frac_table1": d["flops_table1"] / (ms_step * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
         "phases_ms": dict(zip(["estimator", "iterations", "projector_qr", "q2", "rr_products",
                                "small_solve", "vectors", "total"], [round(x, 2) for x in d["ms"]])),
-        "solver": {kk: d[kk] for kk in ["ell", "ind", "kinds", "jacobi_sweeps", "tau", "retries"]},
+        "solver": {kk: d[kk] for kk in ["ell", "ind", "kinds", "jacobi_sweeps", "rr_split", "tau", "retries"]},
         "accuracy": {"max_rel_value_err": rel, "sampled_residual": resid},
         "roofline": {"bound": "mfma", "kernel": "dgemm_kernel (FP64 v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
