@@ -323,8 +323,8 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
 }
 
 // Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
-// Sec. 2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate of
-// H's spectrum so that about k + margin eigenvalues lie above it; the
+// Sec. 2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
+// that about k + margin eigenvalues lie above it; the
 // polar factor of (H - sigma I) / alpha, taken to convergence by the
 // scalar schedule of Sec. 3.1 from a lower bound 1e-12, is sign(H - sigma I),
 // so C = (I + X) / 2 projects onto the invariant subspace of the r
@@ -336,11 +336,18 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
 // small) it returns 0 and H is untouched for the plain solve.  On success
 // vals[0 .. r) holds the eigenvalues (descending), vals[r .. ell) -1e300,
 // Wv (ell x r, ld ell) the eigenvectors; returns r.
+//   top: the estimator's quadrature of the n x n operator (nullptr when the
+//   solve replays a given threshold or retried it).  Every eigenvalue of that operator
+//   above the threshold tau is an eigenvalue of H (Q2 contains its
+//   eigenvectors, Theorem 1), and a cut for k + margin < the threshold's
+//   target lies at or above tau, so the counts the quadrature gives there
+//   are counts of H's eigenvalues and its bounds bound H's spectrum.
+//   Without it a Lanczos run on H itself places sigma.
 //   ybuf (ybuf_doubles): free during the call; zbuf = Wv (zbuf_doubles);
 //   jscr: scratch of at least syev_scratch_doubles(ell).
-int64_t rr_split(const double* H, int64_t ell, int64_t k, const qdwhp_opts& o, const Plan& P, double* ybuf,
-                 int64_t ybuf_doubles, double* Wv, int64_t zbuf_doubles, double* jscr, double* vals,
-                 int* sweeps, hipStream_t s) {
+int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const LanczosResult* top, double top_lmax,
+                 double top_lmin, const qdwhp_opts& o, const Plan& P, double* ybuf, int64_t ybuf_doubles,
+                 double* Wv, int64_t zbuf_doubles, double* jscr, double* vals, int* sweeps, hipStream_t s) {
   const int64_t e2 = ell * ell;
   const int nv = lz_vectors(o);
   const int64_t margin = std::max<int64_t>(16, k / 32);
@@ -348,55 +355,69 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, const qdwhp_opts& o, c
     return 0;
   const int64_t wsd = skinny_ws_doubles(ell, nv);
   if (ybuf_doubles < 5 * e2 + wsd + 1024 || zbuf_doubles < 4 * e2 + 2 * ell) return 0;
-  double* X = ybuf;
-  double* Xn = X + e2;
-  double* Cp = Xn + e2;          // Z of the steps, then the projector C
+  double* Cp = ybuf + 2 * e2;    // Z of the steps, then the projector C (iterates X, Xn before it)
   double* Q1 = Cp + e2;          // ell x r
   double* H1 = Q1 + e2;          // r x r
   double* ws = H1 + e2;
   double* big = Wv;              // step buffers, then the subspace passes
-  // ---- sigma from a Lanczos estimate of H's spectrum
-  LanczosOp op;
-  op.rows_tmp = 1;
-  op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
-    skinny_gemm(H, ell, ell, ell, in, ldi, nv, 1.0, out, ldo, ws, wsd, st);
-  };
-  const LanczosResult lz = lanczos(op, ell, nv, (int)lz_steps(o, ell), o.seed + 1, P.lz, s);
-  if (lz.sweeps < 0) return 0;
-  double lmax = -std::numeric_limits<double>::infinity(), lmin = std::numeric_limits<double>::infinity();
-  for (size_t i = 0; i < lz.nodes.size(); ++i) {
-    lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
-    lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
-  }
-  double sigma = 0.0;
-  if (!cut_below(lz.nodes, lz.weights, ell, nv, lmax, lmin, k + margin, &sigma)) return 0;
-  const double alpha = 1.05 * std::max(lmax - sigma, sigma - lmin);
-  const double hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
-  if (!(alpha > 0.0) || !std::isfinite(alpha)) return 0;
-  // ---- X -> sign((H - sigma I) / alpha)
-  eig_x0(H, ell, X, ell, ell, 1.0 / alpha, -sigma, -1.0, 0.0, s);
-  StepBufs sb;
-  sb.Z = Cp; sb.spd = big; sb.W = big; sb.Q = big + 2 * e2;
-  sb.tau = P.tau; sb.Tall = P.Tall; sb.qrs = P.qrs; sb.flag = P.flags;
-  const std::vector<DwhStep> sched = svd_schedule(1e-12, o.kappa_max, false);
-  run_iterations(X, Xn, ell, ell, true, sched, false, {}, P, sb, false, s);
-  half_plus_identity(X, ell, Cp, ell, ell, s);
-  std::vector<double> d(ell);
-  diagonal(Cp, ell, ell, P.diag, s);
-  QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+  // ---- sigma from a Lanczos estimate (the estimator's quadrature first;
+  // if that over-counts, so that fewer than k eigenvalues lie above sigma,
+  // a Lanczos run on H itself places it again)
+  const bool have_top = top && !top->nodes.empty();
+  int64_t r = 0;
+  double sigma = 0.0, alpha = 0.0, hnorm = 0.0;
   int hf = 0;
-  QDWHP_HIP(hipMemcpyAsync(&hf, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
-  QDWHP_HIP(hipStreamSynchronize(s));
   auto failed = [&]() {
     QDWHP_HIP(hipMemsetAsync(P.flags, 0, sizeof(int), s));
     return (int64_t)0;
   };
-  if (hf) return failed();
-  double tr = 0.0;
-  for (double v : d) tr += v;
-  if (!std::isfinite(tr)) return 0;
-  const int64_t r = (int64_t)std::llround(tr);
-  if (r < k || r >= ell) return 0;
+  for (int attempt = have_top ? 0 : 1; attempt < 2; ++attempt) {
+    double lmax = top_lmax, lmin = top_lmin;
+    if (attempt == 0) {
+      if (!cut_below(top->nodes, top->weights, n, top->nv, lmax, lmin, k + margin, &sigma)) continue;
+    } else {
+      LanczosOp op;
+      op.rows_tmp = 1;
+      op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
+        skinny_gemm(H, ell, ell, ell, in, ldi, nv, 1.0, out, ldo, ws, wsd, st);
+      };
+      const LanczosResult lz = lanczos(op, ell, nv, (int)lz_steps(o, ell), o.seed + 1, P.lz, s);
+      if (lz.sweeps < 0) return 0;
+      lmax = -std::numeric_limits<double>::infinity();
+      lmin = std::numeric_limits<double>::infinity();
+      for (size_t i = 0; i < lz.nodes.size(); ++i) {
+        lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
+        lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
+      }
+      if (!cut_below(lz.nodes, lz.weights, ell, nv, lmax, lmin, k + margin, &sigma)) return 0;
+    }
+    alpha = 1.05 * std::max(lmax - sigma, sigma - lmin);
+    hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return 0;
+    // ---- X -> sign((H - sigma I) / alpha)
+    double* X = ybuf;
+    double* Xn = X + e2;
+    eig_x0(H, ell, X, ell, ell, 1.0 / alpha, -sigma, -1.0, 0.0, s);
+    StepBufs sb;
+    sb.Z = Cp; sb.spd = big; sb.W = big; sb.Q = big + 2 * e2;
+    sb.tau = P.tau; sb.Tall = P.Tall; sb.qrs = P.qrs; sb.flag = P.flags;
+    const std::vector<DwhStep> sched = svd_schedule(1e-12, o.kappa_max, false);
+    run_iterations(X, Xn, ell, ell, true, sched, false, {}, P, sb, false, s);
+    half_plus_identity(X, ell, Cp, ell, ell, s);
+    std::vector<double> d(ell);
+    diagonal(Cp, ell, ell, P.diag, s);
+    QDWHP_HIP(hipMemcpyAsync(d.data(), P.diag, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipMemcpyAsync(&hf, P.flags, sizeof(int), hipMemcpyDeviceToHost, s));
+    QDWHP_HIP(hipStreamSynchronize(s));
+    if (hf) return failed();
+    double tr = 0.0;
+    for (double v : d) tr += v;
+    if (!std::isfinite(tr)) return 0;
+    r = (int64_t)std::llround(tr);
+    if (r >= ell) return 0;
+    if (r >= k) break;
+  }
+  if (r < k) return 0;
   // ---- orthonormal basis of range(C): C Omega, then C Q1
   double* G = big;               // ell x r
   double* Yb = G + ell * r;      // ell x r
@@ -440,7 +461,7 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, const qdwhp_opts& o, c
     if (!(std::sqrt(worst) <= 5e-14 * hnorm)) return 0;
   }
   // ---- Jacobi on the wanted block; eigenvectors Q1 W1
-  double* W1 = X;                // r x r (the iterate is no longer needed)
+  double* W1 = ybuf;             // r x r (the iterates are no longer needed)
   *sweeps = syev(H1, r, r, vals, W1, r, jscr, s);
   if (*sweeps < 0) return 0;
   fill(vals + r, ell - r, 1, ell - r, -1e300, -1e300, s);
@@ -605,7 +626,10 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       ev.mark(5, s);
       Wv = P.Z;
       int sweeps = -1;
-      info->rr_split = rr_split(H, ell, k, o, P, Y, n * n, Wv, n * n, P.big + ell * ell, P.vals, &sweeps, s);
+      // the estimator's quadrature places the split unless it already
+      // over-counted once (a retried threshold)
+      info->rr_split = rr_split(H, ell, k, n, (replay || boost > 1) ? nullptr : &lz, lmax, lmin, o, P, Y, n * n,
+                                Wv, n * n, P.big + ell * ell, P.vals, &sweeps, s);
       if (info->rr_split == 0) sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
       info->jacobi_sweeps = sweeps;
       if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);

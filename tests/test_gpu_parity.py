@@ -47,29 +47,33 @@ def test_eig_vs_oracle(n, f, seed, which):
     assert abs(info["ell"] - r["ell"]) <= 2
 
 
-@pytest.mark.parametrize("n,f,seed,which,kind", [(800, 0.2, 21, "largest", "uniform"),
-                                                 (700, 0.15, 22, "smallest", "uniform"),
-                                                 (800, 0.2, 23, "largest", "clustered")])
-def test_eig_rr_split_vs_oracle(n, f, seed, which, kind):
+@pytest.mark.parametrize("n,f,seed,which,kind,replay", [(800, 0.2, 21, "largest", "uniform", False),
+                                                        (700, 0.15, 22, "smallest", "uniform", False),
+                                                        (800, 0.2, 23, "largest", "clustered", False),
+                                                        (800, 0.2, 24, "largest", "clustered", True)])
+def test_eig_rr_split_vs_oracle(n, f, seed, which, kind, replay):
     """The exact spectral split of the Rayleigh-Ritz matrix (a converged QDWH
     polar decomposition at a Lanczos-placed shift, Jacobi on the wanted
     block only), forced at small sizes, against the oracle (which solves the
-    whole Rayleigh-Ritz matrix) and the planted spectrum."""
+    whole Rayleigh-Ritz matrix) and the planted spectrum.  The shift comes
+    from the estimator's quadrature, or (replayed threshold, no estimator
+    run) from a Lanczos run on the Rayleigh-Ritz matrix itself."""
     torch, q = _gpu()
     A, lam = (eig_uniform if kind == "uniform" else eig_clustered)(n, seed)
-    print(f"eig rr split n={n} f={f} which={which} {kind}", flush=True)
+    print(f"eig rr split n={n} f={f} which={which} {kind} replay={replay}", flush=True)
+    r = oracle.eig_partial(A, fraction=f, which=which)
+    opts = q.default_opts(tau=r["tau"], mu=r["mu"], rho=r["rho"]) if replay else None
     keys = {"rr.split_min": (64, 3000), "rr.split_pct": (100, 85)}   # forced, default
     old = {key: q.tune_get(key, d) for key, (_, d) in keys.items()}
     try:
         for key, (v, _) in keys.items():
             q.tune_set(key, v)
-        w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, which=which, return_info=True)
+        w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, which=which, opts=opts, return_info=True)
         torch.cuda.synchronize()
     finally:
         for key, v in old.items():
             q.tune_set(key, v)
     w, V = w.cpu().numpy(), V.cpu().numpy()
-    r = oracle.eig_partial(A, fraction=f, which=which)
     k = r["k"]
     print(f"  k={k} ell={info['ell']} split={info['rr_split']} sweeps={info['jacobi_sweeps']}", flush=True)
     assert k <= info["rr_split"] < info["ell"]
