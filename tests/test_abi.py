@@ -59,3 +59,36 @@ def test_host_only_calls():
     assert L.qdwhp_eig(None, 4, 4, 0.5, 0, None, None, 4, None, 0, None, None, None) == -1
     assert L.qdwhp_batched(-1, None, None, 0, None, 0, None, None, None) == -1
     assert L.qdwhp_serve_submit(None, None, None) == -1
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of qdwhp_opts, qdwhp_info and qdwhp_problem have the
+    size and field offsets that a C compiler gives the header's structs (a
+    mismatch would let the library write past the caller's struct)."""
+    import shutil
+    import subprocess
+    import paper_2104_14186_amd as q
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"qdwhp_opts": q.Opts, "qdwhp_info": q.Info, "qdwhp_problem": q.Problem}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qdwhp.h"', "int main(void) {"]
+    for cname, cls in mirrors.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            cname, what, val = line.split()
+            got[(cname, what)] = int(val)
+    for cname, cls in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for field, _ in cls._fields_:
+            assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
