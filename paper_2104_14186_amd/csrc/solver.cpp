@@ -323,7 +323,7 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
 }
 
 // Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
-// Sec. 2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
+// Sec. 3.2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
 // that about k + margin eigenvalues lie above it; the
 // polar factor of (H - sigma I) / alpha, taken to convergence by the
 // scalar schedule of Sec. 3.1 from a lower bound 1e-12, is sign(H - sigma I),
