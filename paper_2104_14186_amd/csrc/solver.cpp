@@ -322,11 +322,47 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
   dgemm(t, s);
 }
 
-// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
+// The step of Eq. (2) for the split's polar decomposition with the QR of
+// W = [sqrt(c) X; I] (2n x n) taken by shifted Cholesky QR in three rounds
+// (one round with the Gram shifted by 11 (2n^2 + n(n+1)) u ||W||^2 so that
+// its Cholesky factor exists for any cond(W) <= 1/u, then two plain
+// rounds, which make Q orthonormal to working accuracy): every round is a
+// Gram, the Cholesky-inverse of Eq. (3)'s step and a triangular product,
+// so the step has no per-column launches.  X+ = (b/c) X + (a - b/c)/sqrt(c)
+// Q1 Q2^T as in Eq. (2).  W and Q: 2n x n each; G: n x n; spd:
+// spd_inverse_doubles(n).  ||X||_2 <= 1 is assumed for the shift.
+void cholqr_step(double* X, int64_t n, double a, double b, double c, double* W, double* Q, double* G,
+                 double* spd, int* flag, hipStream_t s) {
+  const int64_t n2 = 2 * n;
+  stacked(X, n, W, n2, n, n, std::sqrt(c), s);
+  double* src = W;
+  double* dst = Q;
+  for (int round = 0; round < 3; ++round) {
+    Gemm g;
+    g.M = n; g.N = n; g.K = n2; g.A = src; g.lda = n2; g.ta = true; g.B = src; g.ldb = n2;
+    g.C = G; g.ldc = n; g.tiles = TILES_UPPER;
+    if (round == 0) g.diag = 11.0 * (double)(n2 * n + n * (n + 1)) * 1.1102230246251565e-16 * (c + 1.0);
+    dgemm(g, s);
+    chol_inverse_factor(G, n, n, spd, flag, s);
+    Gemm t;
+    t.M = n2; t.N = n; t.K = n; t.A = src; t.lda = n2; t.B = spd; t.ldb = n; t.C = dst; t.ldc = n2;
+    t.khi = KHI_COL;
+    dgemm(t, s);
+    std::swap(src, dst);
+  }
+  Gemm f;   // src holds Q after the three rounds
+  f.M = n; f.N = n; f.K = n; f.alpha = (a - b / c) / std::sqrt(c); f.beta = b / c;
+  f.A = src; f.lda = n2; f.B = src + n; f.ldb = n2; f.tb = true; f.C = X; f.ldc = n;
+  dgemm(f, s);
+  symmetrize(X, n, n, s);
+}
+
+// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
 // Sec. 3.2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
 // that about k + margin eigenvalues lie above it; the
 // polar factor of (H - sigma I) / alpha, taken to convergence by the
-// scalar schedule of Sec. 3.1 from a lower bound 1e-12, is sign(H - sigma I),
+// scalar schedule of Sec. 3.1 from a lower bound 1e-12 (its QR-form steps
+// by shifted Cholesky QR, cholqr_step), is sign(H - sigma I),
 // so C = (I + X) / 2 projects onto the invariant subspace of the r
 // eigenvalues above sigma.  Two subspace passes (C Omega, then C Q1, each
 // orthonormalised) give an orthonormal basis Q1 of range(C); the r x r
@@ -354,7 +390,7 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
   if (ell < qdwhp_tune_get("rr.split_min", 3000) || 100 * (k + margin) > qdwhp_tune_get("rr.split_pct", 85) * ell)
     return 0;
   const int64_t wsd = skinny_ws_doubles(ell, nv);
-  if (ybuf_doubles < 5 * e2 + wsd + 1024 || zbuf_doubles < 4 * e2 + 2 * ell) return 0;
+  if (ybuf_doubles < 5 * e2 + wsd + 1024 || zbuf_doubles < 4 * e2 + spd_inverse_doubles(ell) + 2 * ell) return 0;
   double* Cp = ybuf + 2 * e2;    // Z of the steps, then the projector C (iterates X, Xn before it)
   double* Q1 = Cp + e2;          // ell x r
   double* H1 = Q1 + e2;          // r x r
@@ -401,8 +437,10 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
     StepBufs sb;
     sb.Z = Cp; sb.spd = big; sb.W = big; sb.Q = big + 2 * e2;
     sb.tau = P.tau; sb.Tall = P.Tall; sb.qrs = P.qrs; sb.flag = P.flags;
-    const std::vector<DwhStep> sched = svd_schedule(1e-12, o.kappa_max, false);
-    run_iterations(X, Xn, ell, ell, true, sched, false, {}, P, sb, false, s);
+    for (const DwhStep& st : svd_schedule(1e-12, o.kappa_max, false)) {
+      if (st.kind == 1) cholqr_step(X, ell, st.a, st.b, st.c, big, big + 2 * e2, Cp, big + 4 * e2, P.flags, s);
+      else chol_step(X, Xn, ell, ell, st.a, st.b, st.c, true, sb, s);
+    }
     half_plus_identity(X, ell, Cp, ell, ell, s);
     std::vector<double> d(ell);
     diagonal(Cp, ell, ell, P.diag, s);
