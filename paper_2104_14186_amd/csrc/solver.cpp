@@ -357,28 +357,28 @@ void cholqr_step(double* X, int64_t n, double a, double b, double c, double* W, 
   symmetrize(X, n, n, s);
 }
 
-// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
+// Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
 // Sec. 3.2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
-// that about k + margin eigenvalues lie above it; the
-// polar factor of (H - sigma I) / alpha, taken to convergence by the
-// scalar schedule of Sec. 3.1 from a lower bound 1e-12 (its QR-form steps
-// by shifted Cholesky QR, cholqr_step), is sign(H - sigma I),
-// so C = (I + X) / 2 projects onto the invariant subspace of the r
-// eigenvalues above sigma.  Two subspace passes (C Omega, then C Q1, each
-// orthonormalised) give an orthonormal basis Q1 of range(C); the r x r
-// problem Q1^T H Q1 holds exactly those eigenvalues and is solved by Jacobi.
-// The split is checked: every column of H Q1 - Q1 (Q1^T H Q1) must be below
-// 5e-14 ||H||, else (or when r < k, a pivot fails, or the buffers are too
-// small) it returns 0 and H is untouched for the plain solve.  On success
-// vals[0 .. r) holds the eigenvalues (descending), vals[r .. ell) -1e300,
-// Wv (ell x r, ld ell) the eigenvectors; returns r.
-//   top: the estimator's quadrature of the n x n operator (nullptr when the
-//   solve replays a given threshold or retried it).  Every eigenvalue of that operator
-//   above the threshold tau is an eigenvalue of H (Q2 contains its
-//   eigenvectors, Theorem 1), and a cut for k + margin < the threshold's
-//   target lies at or above tau, so the counts the quadrature gives there
-//   are counts of H's eigenvalues and its bounds bound H's spectrum.
-//   Without it a Lanczos run on H itself places sigma.
+// that about k + margin eigenvalues lie above it; the polar factor of
+// (H - sigma I) / alpha, taken to convergence by the scalar schedule of
+// Sec. 3.1 from a lower bound 1e-12 (its QR-form steps by shifted Cholesky
+// QR, cholqr_step), is sign(H - sigma I), so C = (I + X) / 2 projects onto
+// the invariant subspace of the r eigenvalues above sigma.  Two subspace
+// passes (C Omega, then C Q1, each orthonormalised) give an orthonormal
+// basis Q1 of range(C); the r x r problem Q1^T H Q1 holds exactly those
+// eigenvalues and is solved by Jacobi.  The split is checked: every column
+// of H Q1 - Q1 (Q1^T H Q1) must be below 5e-14 ||H||, else (or when r < k,
+// a pivot fails, or the buffers are too small) it returns 0 and H is
+// untouched for the plain solve.  On success vals[0 .. r) holds the
+// eigenvalues (descending), vals[r .. ell) -1e300, Wv (ell x r, ld ell)
+// the eigenvectors; returns r.
+//   top: the estimator's quadrature of the n x n operator (nullptr when
+//   the solve replays a given threshold or retried it).  Every eigenvalue
+//   of that operator above the threshold tau is an eigenvalue of H (Q2
+//   contains its eigenvectors, Theorem 1), and a cut for k + margin < the
+//   threshold's target lies at or above tau, so the counts the quadrature
+//   gives there are counts of H's eigenvalues and its bounds bound H's
+//   spectrum.  Without it a Lanczos run on H itself places sigma.
 //   ybuf (ybuf_doubles): free during the call; zbuf = Wv (zbuf_doubles);
 //   jscr: scratch of at least syev_scratch_doubles(ell).
 int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const LanczosResult* top, double top_lmax,
