@@ -135,6 +135,11 @@ size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdwhp_opts* op
  * eigenvectors, each column's largest-magnitude entry positive).  `info` may
  * be NULL.  Arguments: 1 A, 2 n, 3 lda, 4 fraction, 5 which, 6 w, 7 V, 8 ldv,
  * 9 work, 10 lwork, 11 opts (NULL = defaults), 12 stream, 13 info.
+ * A large ell x ell Rayleigh-Ritz matrix (tuning keys "rr.split_min",
+ * "rr.split_pct") is first split exactly by the polar factor of a shifted
+ * copy (Sec. 3.2) and only its wanted block goes to Jacobi; the split is
+ * verified and otherwise the whole matrix is solved, so results meet the
+ * same bounds either way (info->rr_split reports which).
  */
 int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fraction, int which,
               double* w, double* V, int64_t ldv, void* work, size_t lwork,
