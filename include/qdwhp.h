@@ -60,14 +60,18 @@ extern "C" {
 /* ---- options (host struct; fill with qdwhp_opts_default) ------------- */
 typedef struct {
   double   tol;            /* 0.05: threshold on |R_ii| (Sec. 4.1 after Theorem 1:
-                              tol = Omega(1) trades ell against accuracy; the paper's
-                              example value 0.01 leaves backward errors near 1e-13,
-                              0.05 keeps them near 1e-14 for a few % larger ell)    */
+                              tol = Omega(1) trades ell against accuracy).  The
+                              paper's value 0.01 is accepted; with it the method
+                              itself (as written, in plain FP64) leaves residuals
+                              up to ~1.7e-13 ||A|| on kappa = 1e16 SVD inputs,
+                              0.05 keeps them near 1e-14 for a few % larger ell  */
   double   s_eig;          /* 0.2 : EIG shift / l_0 (Sec. 4.1, "Choosing s")         */
   int      eig_iters;      /* 3   : EIG iterations, type (27,26) (Sec. 4.1)          */
   double   kappa_max;      /* 100 : a step is QR-based when its bound on cond(Z)
                                     exceeds this (Sec. 4.2 advises QR when ill-conditioned) */
-  int      svd_qr_first;   /* 1   : SVD step 0 QR-based (Table 1 counts one QR step)  */
+  int      svd_qr_first;   /* 0   : SVD step 0 QR-based when s < 1e-3 (Sec. 4.2),
+                                    any step QR-based while 1 + c_k > kappa_max;
+                              1   : step 0 always QR-based (Table 1 counts one)     */
   int      precision;      /* QDWHP_FP64, or QDWHP_MIXED_FP32: the Gram matrix and
                               the two triangular products of every Cholesky-based
                               step on FP32 matrix cores; QR-based steps, the

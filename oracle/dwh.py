@@ -65,24 +65,30 @@ def iteration_count(l0, max_iter=12):
     return k
 
 
-def svd_schedule(s, kappa_max=100.0, qr_first=True, max_iter=12):
+QR_FIRST_BELOW = 1e-3   # Sec. 4.2: QR-based first step when s << 1 ("say s < 1e-3")
+
+
+def svd_schedule(s, kappa_max=100.0, qr_first=None, max_iter=12):
     """Weights and kinds for QDWHpartial-SVD (Algorithm 2): start from l_0 = s,
     stop at |l_k - 1| < 5u.
 
     Kind of each step: Sec. 4.2 advises the QR-based Eq. (2) for the first
-    iteration when s is small; Table 1 counts one QR iteration for the SVD.
-    Reading: step 0 is QR when ``qr_first``; any step is QR while the bound
-    1 + c_k on the condition number of Z_k = I + c_k X_k^T X_k exceeds
-    ``kappa_max`` (the singular values of X_k lie in [l_k, 1]); otherwise the
-    Cholesky-based Eq. (3).
+    iteration when s << 1 (s < 1e-3); Cholesky-based Eq. (3) steps are safe
+    once Z_k = I + c_k X_k^T X_k is well conditioned (Sec. 3.1), and since
+    the singular values of X_k lie in [0, 1], 1 + c_k bounds cond(Z_k).
+    Reading: a step is QR-based while 1 + c_k exceeds ``kappa_max`` (which
+    covers the s < 1e-3 rule: c_0 > 1.6e4 there), Cholesky-based otherwise.
+    ``qr_first`` None follows that rule; True forces step 0 to be QR-based
+    (Table 1 counts one QR-based iteration for the SVD); False never forces it.
     Returns a list of dicts with keys a, b, c, kind ('qr'|'chol'), l (l_k before the step).
     """
+    force = (float(s) < QR_FIRST_BELOW) if qr_first is None else bool(qr_first)
     sched = []
     l = float(s)
     while abs(l - 1.0) >= 5.0 * U_ROUND and len(sched) < max_iter:
         a, b, c = dwh_weights(l)
         kappa = 1.0 + c
-        kind = "qr" if ((qr_first and not sched) or kappa > kappa_max) else "chol"
+        kind = "qr" if ((force and not sched) or kappa > kappa_max) else "chol"
         sched.append(dict(a=a, b=b, c=c, kind=kind, l=l))
         l = next_l(l, a, b, c)
     return sched

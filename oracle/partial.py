@@ -16,13 +16,14 @@ Readings (the paper is silent or ambiguous on these):
   * X_k is symmetrised after every EIG step (it is symmetric in exact
     arithmetic); the Rayleigh-Ritz matrix is symmetrised too;
   * the threshold tol is applied to |R_ii| of the QR of (r+I)/2 (EIG) or
-    I - r^T r (SVD).  Sec. 4.1 asks for tol = Omega(1) and uses 0.01 as its
-    example, noting that a small tol costs accuracy and a large one costs
-    subspace size.  By Theorem 1 the containment error is about
-    ||V0^T B|| / tol, and with tol = 0.01 rounding in B alone leaves
-    residuals near 1e-13; the default here is 0.05 (ell a few % larger,
-    residuals near 1e-14).  tol is a parameter of every entry point;
-    ind is 1-based, ell = n - ind + 1, no entry below tol means ell = 0;
+    I - r^T r (SVD), with the paper's default tol = 0.01 (Sec. 4.1 after
+    Theorem 1, Algorithms 1 and 2).  Sec. 4.1 notes that a small tol costs
+    accuracy and a large one costs subspace size: by Theorem 1 the
+    containment error is about ||V0^T B|| / sigma_min(R11), and with
+    sigma_min(R11) near 0.01 rounding in B alone can leave residuals just
+    above 1e-13 (kappa = 1e16 SVD inputs); tol is a parameter of every
+    entry point.  ind is 1-based, ell = n - ind + 1, no entry below tol
+    means ell = 0;
   * Rayleigh-Ritz uses the original A (no rescaling), keeps the k largest
     Ritz values (EIG) / singular values (SVD);
   * the small SVD of A Q2 is QR followed by the SVD of the ell x ell R factor;
@@ -40,7 +41,7 @@ from .polar import qr_step, chol_step
 from .estimator import lanczos_slq, choose_tau, choose_svd_threshold
 
 S_EIG = 0.2
-TOL = 0.05
+TOL = 0.01          # Sec. 4.1 / Algorithms 1 and 2
 
 
 class NoSubspace(RuntimeError):
@@ -190,7 +191,7 @@ def _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds=None):
 
 
 def svd_partial(A, k=None, seed=0, replay=None, s=None, tol=TOL, kappa_max=100.0,
-                qr_first=True, nv=None, m=None):
+                qr_first=None, nv=None, m=None):
     """Dominant singular triplets of A (m x n) by QDWHpartial-SVD (Algorithm 2).
 
     k mode: the k largest triplets.  Threshold mode (``s`` given, no k): every

@@ -16,7 +16,7 @@ extern "C" void qdwhp_opts_default(qdwhp_opts* o) {
   o->s_eig = 0.2;
   o->eig_iters = 3;
   o->kappa_max = 100.0;
-  o->svd_qr_first = 1;
+  o->svd_qr_first = 0;
   o->precision = QDWHP_FP64;
   o->polish_steps = 1;
   o->seed = 0;

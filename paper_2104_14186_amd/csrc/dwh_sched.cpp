@@ -8,6 +8,8 @@
 namespace qdwhp {
 
 static const double kUnitRoundoff = 1.1102230246251565e-16;   // 2^-53
+// Sec. 4.2: for s << 1 ("say s < 1e-3") the first step should be QR-based.
+static const double kQrFirstBelow = 1e-3;
 
 void dwh_weights(double l, double* a, double* b, double* c) {
   if (l > 1.0) l = 1.0;
@@ -43,6 +45,7 @@ std::vector<DwhStep> eig_schedule(double s, double rho, int iters, double kappa_
 
 std::vector<DwhStep> svd_schedule(double s, double kappa_max, bool qr_first) {
   std::vector<DwhStep> out;
+  if (s < kQrFirstBelow) qr_first = true;
   double l = s;
   while (std::fabs(l - 1.0) >= 5.0 * kUnitRoundoff && out.size() < 12) {
     DwhStep st;

@@ -21,7 +21,9 @@ double dwh_map(double x, double a, double b, double c);
 // 1 + c_k x_k^2 on cond(Z_k) against kappa_max.
 std::vector<DwhStep> eig_schedule(double s, double rho, int iters, double kappa_max);
 // Algorithm 2: steps from l_0 = s until |l_k - 1| < 5u; step 0 QR-based when
-// qr_first, later steps QR-based while 1 + c_k > kappa_max.
+// qr_first or s < 1e-3 (Sec. 4.2), any step QR-based while 1 + c_k > kappa_max
+// (1 + c_k bounds cond(I + c_k X^T X) since the singular values of X_k lie in
+// [0, 1]).
 std::vector<DwhStep> svd_schedule(double s, double kappa_max, bool qr_first);
 
 // Threshold below the pooled Lanczos quadrature node at which the estimated

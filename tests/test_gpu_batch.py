@@ -149,6 +149,29 @@ def test_server_alone_equals_mix_bitwise():
     assert _same(got[3][0], alone)
     for sp, g in zip(specs, got):
         assert _same(g[0], _standalone(q, sp)), (sp["type"], tuple(sp["A"].shape))
+    # and each served result is right: values against the planted spectra,
+    # residuals and orthogonality of every returned vector
+    _check_planted(specs, exact, [g[0] for g in got])
+
+
+def _check_planted(specs, exact, results):
+    import oracle
+    for sp, ex, r in zip(specs, exact, results):
+        A = sp["A"].cpu().numpy()
+        if sp["type"] == "eig":
+            w, V = (x.cpu().numpy() for x in r)
+            e = ex[:len(w)]
+            met = oracle.eig_metrics(A, w, V, e)
+            orth = met["orth"]
+        else:
+            U, S, V = (x.cpu().numpy() for x in r)
+            e = ex[:len(S)]
+            met = oracle.svd_metrics(A, U, S, V, e)
+            orth = max(met["orth_u"], met["orth_v"])
+        tag = (sp["type"], tuple(sp["A"].shape))
+        assert met["value_rel_max"] <= 1e-12, (tag, met)
+        assert met["residual"] <= 1e-13, (tag, met)
+        assert orth <= 1e-12, (tag, met)
 
 
 def test_server_admission_by_footprint():

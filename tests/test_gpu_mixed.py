@@ -39,11 +39,11 @@ def test_gemm_f32(m, n, k, ta, tb):
 def test_eig_mixed_values():
     torch, q = _gpu()
     A, lam = eig_uniform(512, 1000)
-    o = q.default_opts(precision=q.MIXED_FP32)
+    o = q.default_opts(precision=q.MIXED_FP32, tol=0.05)
     print("eig mixed n=512", flush=True)
     w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=0.1, opts=o, return_info=True)
     w, V = w.cpu().numpy(), V.cpu().numpy()
-    r = oracle.eig_partial(A, fraction=0.1)
+    r = oracle.eig_partial(A, fraction=0.1, tol=0.05)
     exact = np.sort(lam)[::-1][:len(w)]
     assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
     assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
@@ -59,11 +59,11 @@ def test_svd_mixed_values(m, n, k, kind):
         A, sig = svd_loguniform(m, n, 1003)
     else:
         A, sig = svd_geometric(m, n, 1001)
-    o = q.default_opts(precision=q.MIXED_FP32)
+    o = q.default_opts(precision=q.MIXED_FP32, tol=0.05)
     print(f"svd mixed {m}x{n}", flush=True)
     U, S, V, info = q.svd(torch.from_numpy(A).cuda(), k, opts=o, return_info=True)
     U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
-    r = oracle.svd_partial(A, k)
+    r = oracle.svd_partial(A, k, tol=0.05)
     assert np.max(np.abs(S - r["S"]) / r["S"]) < 1e-12
     assert np.max(np.abs(S - sig[:k]) / sig[:k]) < 1e-12
     met = oracle.svd_metrics(A, U, S, V)

@@ -57,6 +57,8 @@ def test_halley_at_one(golden):
 
 
 def test_iteration_counts(golden):
+    """Paper bound (Sec. 3.1) and monotonicity; the exact counts are pinned
+    against an independent high-precision derivation in test_oracle_pins."""
     kmax = golden["max_iterations_for_kappa_1e15"]
     assert iteration_count(1.0 / kmax["kappa"]) <= kmax["value"]
     assert iteration_count(1e-16) <= kmax["value"]
@@ -122,7 +124,7 @@ def test_svd_schedule_stops_at_unit_bound():
         for st in sched:
             l = dwh_map(min(l, 1.0), st["a"], st["b"], st["c"])
         assert abs(l - 1.0) < 5 * U_ROUND
-        assert sched[0]["kind"] == "qr"
+        assert (sched[0]["kind"] == "qr") == (s < 1e-3 or 1 + sched[0]["c"] > 100.0)
         assert all(st["kind"] == "chol" for st in sched[1:] if 1 + st["c"] <= 100.0)
 
 
