@@ -94,6 +94,19 @@ typedef struct {
                               records the launch sequence, later ones replay it with
                               new weights (pays off for repeated solves on one
                               workspace; results are identical either way)        */
+  int      tau_policy;     /* 1   : EIG threshold by predicted cost: of the cuts at or
+                                    below the plain one (a gap of the estimator's
+                                    quadrature), the one whose step kinds and
+                                    predicted subspace size cost the fewest flops by
+                                    Table 1's accounting (a lower threshold can turn
+                                    QR-based steps into Cholesky-based ones at the
+                                    price of a larger ell);
+                              0   : the plain cut (target count of the estimator)    */
+  int      use_omega;      /* 0   : 1 = factor B Omega instead of the projector B,
+                                    Omega an n x n Philox Gaussian (key seed + 3,
+                                    entries of variance 1/n):
+                                    the randomised rank-revealing QR of Sec. 4.1
+                                    (costs one n^3 product more)                     */
 } qdwhp_opts;
 
 /* ---- per-call report (host struct) ------------------------------------ */

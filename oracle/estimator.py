@@ -27,6 +27,7 @@ import numpy as np
 import scipy.linalg as sla
 
 from .philox import gaussian
+from .dwh import compose, eig_schedule
 
 NV_DEFAULT = 8
 M_DEFAULT = 64
@@ -130,21 +131,98 @@ def _cut_below(est, kt, nonneg=False):
     return 0.5 * (th[j] + nxt)
 
 
-def choose_tau(est, k, boost=1):
+def _band_edge(sched, s, tol):
+    """Scaled value y in (-s, 0) where the composite map of the EIG schedule
+    reaches 2 tol - 1, i.e. (r(y) + 1)/2 = tol: scaled values above it are
+    the band the projector keeps beyond the wanted part (Sec. 4.1)."""
+    ws = [(st["a"], st["b"], st["c"]) for st in sched]
+    target = 2.0 * tol - 1.0
+    lo, hi = -s, 0.0
+    if not compose(lo, ws) < target:
+        return lo
+    for _ in range(200):
+        if hi - lo <= 1e-17:
+            break
+        mid = 0.5 * (lo + hi)
+        if compose(mid, ws) < target:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def predicted_flops(sched, n, ell):
+    """Table 1 accounting of one EIG solve with the given step kinds and
+    subspace size: (8 + 2/3) n^3 per QR-based and (4 + 1/3) n^3 per
+    Cholesky-based step, the Householder QR of the projector's first
+    j = n - ell columns (2 n j^2 - 2/3 j^3), A Q2 plus forming Q2 (6 n^2 ell)
+    and the ell x ell eigenproblem (9 ell^3)."""
+    n = float(n)
+    ell = float(ell)
+    f = sum((26.0 / 3.0 if st["kind"] == "qr" else 13.0 / 3.0) * n ** 3 for st in sched)
+    j = max(0.0, n - ell)
+    return f + 2.0 * n * j * j - 2.0 / 3.0 * j ** 3 + 6.0 * n * n * ell + 9.0 * ell ** 3
+
+
+def _scale(est, tau):
+    spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
+    mu = max(est["lmax"] - tau, 1e-3 * spread)
+    rho = max(0.0, (tau - est["lmin"]) / mu)
+    return mu, rho
+
+
+def choose_tau(est, k, boost=1, policy="cost", s=0.2, iters=3, kappa_max=100.0, tol=0.01):
     """EIG threshold tau and scaling for the wanted top-k (Algorithm 1 setup).
 
     Returns (tau, mu, rho): |mu| = lambda_max_hat - tau scales the wanted part
     onto [-1, 0] (Sec. 4.1 scales by a Lanczos bound), rho = (tau - lambda_min_hat)/|mu|
     bounds the largest unwanted scaled value.
+
+    policy 'plain': tau is the cut below the target count (``_cut_below``).
+    policy 'cost' (reading; the paper leaves the threshold to the user and
+    notes the trade-off between QR- and Cholesky-based steps): every cut at
+    or below the plain one that lies in a gap between distinct quadrature
+    nodes is a candidate; for each, the step kinds follow from rho
+    (``eig_schedule``), the subspace size ell is predicted as the quadrature
+    count above the band edge, and ``predicted_flops`` scores it; the
+    cheapest wins, ties going to the higher cut.
     """
     n = est["n"]
     kt = target_count(n, k, boost)
-    cut = _cut_below(est, kt)
-    tau = est["lmin"] if cut is None else cut
+    if policy == "plain":
+        cut = _cut_below(est, kt)
+        tau = est["lmin"] if cut is None else cut
+        mu, rho = _scale(est, tau)
+        return tau, mu, rho
+    order = np.argsort(-est["nodes"], kind="stable")
+    th = est["nodes"][order]
+    cum = n / est["nv"] * np.cumsum(est["weights"][order])
+    hit = np.nonzero(cum >= kt - 1e-9)[0]
+    if len(hit) == 0 or kt >= n:
+        mu, rho = _scale(est, est["lmin"])
+        return est["lmin"], mu, rho
     spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
-    mu = max(est["lmax"] - tau, 1e-3 * spread)
-    rho = max(0.0, (tau - est["lmin"]) / mu)
-    return tau, mu, rho
+    gap = 1e-6 * spread
+    j = int(hit[0])
+    best = None
+    while True:
+        below = np.nonzero(th[j + 1:] < th[j] - gap)[0]
+        if len(below) == 0:
+            break
+        nx = j + 1 + int(below[0])
+        tau = 0.5 * (th[j] + th[nx])
+        mu, rho = _scale(est, tau)
+        sched = eig_schedule(s, rho, iters, kappa_max)
+        edge = tau - mu * (_band_edge(sched, s, tol) + s) / (1.0 - s)
+        ell = min(float(n), count_above(est, edge))
+        cost = predicted_flops(sched, n, ell)
+        if best is None or cost < best[0] * (1.0 - 1e-12):
+            best = (cost, tau, mu, rho)
+        j = nx
+    if best is None:
+        mu, rho = _scale(est, est["lmin"])
+        return est["lmin"], mu, rho
+    return best[1], best[2], best[3]
 
 
 def choose_svd_threshold(est, k, boost=1):

@@ -39,6 +39,7 @@ import scipy.linalg as sla
 from .dwh import eig_schedule, svd_schedule
 from .polar import qr_step, chol_step
 from .estimator import lanczos_slq, choose_tau, choose_svd_threshold
+from .philox import gaussian
 
 S_EIG = 0.2
 TOL = 0.01          # Sec. 4.1 / Algorithms 1 and 2
@@ -62,10 +63,26 @@ def sign_normalize(V, U=None):
     return V, U
 
 
-def projector_subspace(B, tol=TOL):
+def omega_matrix(n, seed):
+    """n x n Gaussian Omega of the randomised rank-revealing QR (Sec. 4.1),
+    Philox stream 0 under key seed + 3, filled column by column.
+
+    Reading: the entries are scaled to variance 1/n so that B Omega keeps the
+    column norms of B on average and the absolute tol on |R_ii| keeps its
+    meaning (with unit variance every diagonal entry grows by ~sqrt(n), the
+    cut moves and the subspace loses part of the wanted space)."""
+    return gaussian(seed + 3, 0, n * n).reshape((n, n), order="F") / np.sqrt(n)
+
+
+def projector_subspace(B, tol=TOL, omega=None):
     """Householder QR of the projector B (no pivoting), ind and Q2 (Sec. 4.1,
-    'Choosing the subspace size ell'; Algorithm 1 and Algorithm 2)."""
+    'Choosing the subspace size ell'; Algorithm 1 and Algorithm 2).  With
+    ``omega`` the QR is of B Omega, which Sec. 4.1 offers to make the
+    factorisation rank revealing with high probability (B Omega has the
+    range of B)."""
     n = B.shape[0]
+    if omega is not None:
+        B = B @ omega
     Q, R = np.linalg.qr(B, mode="complete")
     d = np.abs(np.diag(R))
     small = np.nonzero(d < tol)[0]
@@ -76,7 +93,7 @@ def projector_subspace(B, tol=TOL):
     return dict(diagR=np.diag(R).copy(), ind=ind, ell=ell, Q2=Q[:, ind - 1:])
 
 
-def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None):
+def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None, omega=None):
     """Steps of Algorithm 1 after the setup: iterate, project, Rayleigh-Ritz."""
     n = Aw.shape[0]
     sched = eig_schedule(s, rho, iters, kappa_max)
@@ -91,7 +108,7 @@ def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None
         if symmetrize:
             X = 0.5 * (X + X.T)
     B = 0.5 * (X + np.eye(n))
-    sub = projector_subspace(B, tol)
+    sub = projector_subspace(B, tol, omega)
     out = dict(tau=tau, mu=mu, rho=rho, sched=sched, X=X, B=B, **sub)
     if sub["ell"] == 0:
         out.update(theta=np.zeros(0), W=np.zeros((0, 0)), H=np.zeros((0, 0)), n_above=0)
@@ -107,7 +124,7 @@ def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None
 
 def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
                 tau=None, s=S_EIG, iters=3, tol=TOL, kappa_max=100.0, symmetrize=True,
-                nv=None, m=None):
+                nv=None, m=None, tau_policy="cost", use_omega=False):
     """Wanted eigenpairs of symmetric A by QDWHpartial-EIG (Algorithm 1).
 
     k mode (``fraction`` or ``k``): the k largest ('largest') or smallest
@@ -115,7 +132,9 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
     eigenpair beyond tau on the wanted side, the paper's native form (negative
     eigenvalues for tau = 0 and 'smallest').  Returns dict with w (most wanted
     first), V (n x k) and the intermediates.  Raises NoSubspace when the
-    certificate fails after one retry (k mode).
+    certificate fails after one retry (k mode).  ``tau_policy`` picks the
+    k-mode threshold ('cost' or 'plain', see estimator.choose_tau);
+    ``use_omega`` factors B Omega instead of B (Sec. 4.1).
     """
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
@@ -124,6 +143,7 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
     if m is not None:
         kw["m"] = m
     kinds = None if replay is None else replay.get("kinds")
+    omega = omega_matrix(n, seed) if use_omega else None
     est = None
     if replay is None:
         est = lanczos_slq(lambda v: Aw @ v, n, seed, **kw)
@@ -138,7 +158,7 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
             spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
             mu = max(est["lmax"] - tw, 1e-3 * spread)
             rho = max(0.0, (tw - est["lmin"]) / mu)
-        r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds)
+        r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega)
         k = r["n_above"]
     else:
         if k is None:
@@ -147,8 +167,8 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
             if replay is not None:
                 tw, mu, rho = replay["tau"], replay["mu"], replay["rho"]
             else:
-                tw, mu, rho = choose_tau(est, k, boost)
-            r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds)
+                tw, mu, rho = choose_tau(est, k, boost, tau_policy, s, iters, kappa_max, tol)
+            r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega)
             if r["ell"] > 0 and (r["n_above"] >= k or r["ell"] >= n or replay is not None):
                 break
         else:

@@ -34,7 +34,11 @@ class Opts(ctypes.Structure):
                 ("lanczos_vectors", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("s_svd", ctypes.c_double),
-                ("kinds", ctypes.c_int * 16), ("graphs", ctypes.c_int)]
+                ("kinds", ctypes.c_int * 16), ("graphs", ctypes.c_int),
+                ("tau_policy", ctypes.c_int), ("use_omega", ctypes.c_int)]
+
+
+Opts._field_names = frozenset(f for f, _ in Opts._fields_)
 
 
 class Info(ctypes.Structure):
@@ -161,8 +165,10 @@ def default_opts(**kw):
         if k == "kinds":
             for i, x in enumerate(v):
                 o.kinds[i] = {"qr": KIND_QR, "chol": KIND_CHOL, "auto": KIND_AUTO}.get(x, x)
-        else:
+        elif k in Opts._field_names:
             setattr(o, k, v)
+        else:
+            raise KeyError(f"qdwhp_opts has no field {k!r}")
     return o
 
 

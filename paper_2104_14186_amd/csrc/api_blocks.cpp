@@ -25,6 +25,8 @@ extern "C" void qdwhp_opts_default(qdwhp_opts* o) {
   o->tau = o->mu = o->rho = nan;
   o->alpha = o->s_svd = nan;
   for (int i = 0; i < 16; ++i) o->kinds[i] = QDWHP_KIND_AUTO;
+  o->tau_policy = 1;
+  o->use_omega = 0;
 }
 
 extern "C" const char* qdwhp_strerror(int st) {

@@ -91,4 +91,76 @@ bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weig
   return false;
 }
 
+double eig_band_edge(const std::vector<DwhStep>& sched, double s, double tol) {
+  auto image = [&](double y) {
+    for (const DwhStep& st : sched) y = dwh_map(y, st.a, st.b, st.c);
+    return y;
+  };
+  const double target = 2.0 * tol - 1.0;
+  double lo = -s, hi = 0.0;
+  if (!(image(lo) < target)) return lo;
+  for (int it = 0; it < 200 && hi - lo > 1e-17; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (image(mid) < target) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+double eig_cost_flops(const std::vector<DwhStep>& sched, double n, double ell) {
+  double f = 0.0;
+  for (const DwhStep& st : sched) f += (st.kind == 1 ? 26.0 / 3.0 : 13.0 / 3.0) * n * n * n;
+  const double j = std::max(0.0, n - ell);              // columns of the projector QR before ind
+  f += 2.0 * n * j * j - 2.0 / 3.0 * j * j * j;
+  f += 6.0 * n * n * ell + 9.0 * ell * ell * ell;        // A Q2, forming Q2, the small eigenproblem
+  return f;
+}
+
+bool choose_tau_cost(const std::vector<double>& nodes, const std::vector<double>& weights, int64_t n, int nv,
+                     double lmax, double lmin, int64_t kt, double s, int iters, double kappa_max, double tol,
+                     double* tau, int* candidates) {
+  if (candidates) *candidates = 0;
+  if (kt >= n || nodes.empty()) return false;
+  std::vector<size_t> order(nodes.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return nodes[x] > nodes[y]; });
+  const double scale = (double)n / nv;
+  std::vector<double> th(order.size()), cum(order.size());
+  double acc = 0.0;
+  for (size_t i = 0; i < order.size(); ++i) {
+    th[i] = nodes[order[i]];
+    acc += scale * weights[order[i]];
+    cum[i] = acc;
+  }
+  size_t j = th.size();
+  for (size_t i = 0; i < th.size(); ++i)
+    if (cum[i] >= (double)kt - 1e-9) { j = i; break; }
+  if (j == th.size()) return false;
+  const double spread = std::max({lmax - lmin, std::fabs(lmax), std::fabs(lmin), 1e-300});
+  const double gap = 1e-6 * spread;
+  auto count_above = [&](double t) {
+    double c = 0.0;
+    for (size_t i = 0; i < th.size() && th[i] >= t; ++i) c = cum[i];
+    return c;
+  };
+  bool found = false;
+  double best = 0.0;
+  const double dn = (double)n;
+  for (int cand = 0; cand < 4096; ++cand) {
+    size_t nx = j + 1;
+    while (nx < th.size() && !(th[nx] < th[j] - gap)) ++nx;
+    if (nx >= th.size()) break;
+    const double t = 0.5 * (th[j] + th[nx]);
+    const double mu = std::max(lmax - t, 1e-3 * spread);
+    const double rho = std::max(0.0, (t - lmin) / mu);
+    const std::vector<DwhStep> sched = eig_schedule(s, rho, iters, kappa_max);
+    const double edge = t - mu * (eig_band_edge(sched, s, tol) + s) / (1.0 - s);
+    const double ell = std::min(dn, count_above(edge));
+    const double cost = eig_cost_flops(sched, dn, ell);
+    if (!found || cost < best * (1.0 - 1e-12)) { best = cost; *tau = t; found = true; }
+    if (candidates) ++*candidates;
+    j = nx;
+  }
+  return found;
+}
+
 }  // namespace qdwhp

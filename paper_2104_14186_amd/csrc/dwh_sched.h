@@ -34,4 +34,23 @@ bool cut_below(const std::vector<double>& nodes, const std::vector<double>& weig
                int nv, double lmax, double lmin, int64_t kt, double* cut, bool nonneg = false);
 int64_t target_count(int64_t n, int64_t k, int boost);
 
+// Scaled value y in (-s, 0) at which the composite map of an EIG schedule
+// reaches 2 tol - 1, i.e. where (r(y) + 1)/2 = tol: eigenvalues with scaled
+// values above it form the band that the projector keeps besides the
+// wanted ones (Sec. 4.1, "Choosing s" and "Choosing the subspace size").
+double eig_band_edge(const std::vector<DwhStep>& sched, double s, double tol);
+// Flops of a solve by the Table 1 accounting: the steps, the projector QR
+// up to column n - ell, A Q2 and forming Q2 (6 n^2 ell), the ell x ell
+// eigenproblem (9 ell^3).
+double eig_cost_flops(const std::vector<DwhStep>& sched, double n, double ell);
+// Threshold policy by predicted cost: every cut at or below the plain one
+// (cut_below for kt) that falls in a gap between distinct quadrature nodes
+// is a candidate; each is scored by eig_cost_flops with its step kinds (the
+// kappa rule of eig_schedule) and its predicted subspace size (the
+// quadrature count above the band edge).  The cheapest wins, ties go to the
+// higher cut.  Returns false when the count never reaches kt.
+bool choose_tau_cost(const std::vector<double>& nodes, const std::vector<double>& weights, int64_t n, int nv,
+                     double lmax, double lmin, int64_t kt, double s, int iters, double kappa_max, double tol,
+                     double* tau, int* candidates = nullptr);
+
 }  // namespace qdwhp

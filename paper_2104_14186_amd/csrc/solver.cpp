@@ -600,8 +600,12 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
           tau = sgn * o.tau;
         } else {
           double cut;
-          tau = cut_below(lz.nodes, lz.weights, n, nv, lmax, lmin, target_count(n, k, boost), &cut)
-                    ? cut : lmin;
+          const int64_t kt = target_count(n, k, boost);
+          const bool ok = o.tau_policy == 1
+              ? choose_tau_cost(lz.nodes, lz.weights, n, nv, lmax, lmin, kt, sfix, o.eig_iters, o.kappa_max,
+                                o.tol, &cut)
+              : cut_below(lz.nodes, lz.weights, n, nv, lmax, lmin, kt, &cut);
+          tau = ok ? cut : lmin;
         }
         mu = std::max(lmax - tau, 1e-3 * spread);
         rho = std::max(0.0, (tau - lmin) / mu);
@@ -630,11 +634,23 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       }
       run_iterations(X, Xn, n, n, true, sched, mixed, polish, P, sb, o.graphs != 0, s);
       ev.mark(2, s);
-      // ---- projector (X + I)/2, QR, ind (Algorithm 1)
+      // ---- projector (X + I)/2, QR, ind (Algorithm 1); with use_omega the
+      // QR is of B Omega (the randomised rank-revealing form of Sec. 4.1)
       half_plus_identity(X, n, P.Z, n, n, s);
+      double* Bq = P.Z;
+      double* Q2buf = (X == P.X) ? P.Xn : P.X;
+      if (o.use_omega) {
+        gaussian_fill(Q2buf, n * n, o.seed + 3, 0, s);
+        Gemm go;
+        // Omega with N(0, 1/n) entries: B Omega keeps B's column norms on average
+        go.M = n; go.N = n; go.K = n; go.alpha = 1.0 / std::sqrt((double)n);
+        go.A = P.Z; go.lda = n; go.B = Q2buf; go.ldb = n; go.C = X; go.ldc = n;
+        dgemm(go, s);
+        Bq = X;
+      }
       std::vector<double> d;
-      const PanelWatch watch = diag_watch(P.Z, n, P.diag, o.tol, &d, s);
-      geqrf(P.Z, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
+      const PanelWatch watch = diag_watch(Bq, n, P.diag, o.tol, &d, s);
+      geqrf(Bq, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
       int hflags[8];
       QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipStreamSynchronize(s));
@@ -646,9 +662,10 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       ell = n - ind + 1;
       if (ell <= 0) { status = QDWHP_ERR_NO_SUBSPACE; if (replay) break; continue; }
       // ---- Q2 = H_1 ... H_{ind-1} [0; I_ell]
-      Q2 = (X == P.X) ? P.Xn : P.X;
-      double* Y = X;
-      orgqr(P.Z, n, n, P.Tall, ind - 1, ind - 1, ell, Q2, n, P.qrs, s);
+      Q2 = Q2buf;
+      double* Y = o.use_omega ? P.Z : X;          // the buffers free once Q2 is formed
+      double* Wfree = o.use_omega ? X : P.Z;
+      orgqr(Bq, n, n, P.Tall, ind - 1, ind - 1, ell, Q2, n, P.qrs, s);
       ev.mark(4, s);
       // ---- Rayleigh-Ritz on the original matrix: H = Q2^T (sgn A) Q2
       Gemm g1;
@@ -662,7 +679,7 @@ int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, in
       dgemm(g2, s);
       symmetrize(H, ell, ell, s);
       ev.mark(5, s);
-      Wv = P.Z;
+      Wv = Wfree;
       int sweeps = -1;
       // the estimator's quadrature places the split unless it already
       // over-counted once (a retried threshold)

@@ -175,3 +175,65 @@ def test_paper_tol_vs_oracle(kind, m, n, f, seed, spec):
     assert np.max(np.abs(vals - rvals) / np.abs(rvals)) < 1e-12
     assert met["value_rel_max"] < 1e-12
     assert met["residual"] <= max(1e-13, 3.0 * ref["residual"]), (met, ref)
+
+
+# ------------------------------------------- threshold policy, Omega, s = 0.875
+@pytest.mark.parametrize("n,f,seed,policy,omega", [(1024, 0.01, 1002, "cost", 0), (1024, 0.01, 1002, "plain", 0),
+                                                   (512, 0.1, 1000, "plain", 0), (600, 0.1, 31, "cost", 1),
+                                                   (1024, 0.01, 1002, "cost", 1)])
+def test_threshold_policy_and_omega_vs_oracle(n, f, seed, policy, omega):
+    """The cost-model threshold (a cut below the plain one when it turns
+    QR-based steps into Cholesky-based ones) and the QR of B Omega (Sec. 4.1)
+    give the oracle's threshold, kinds and subspace size, and the planted values."""
+    torch, q = _gpu()
+    A, lam = (eig_clustered if seed == 1002 else eig_uniform)(n, seed)
+    print(f"policy {policy} omega {omega} n={n} f={f}", flush=True)
+    o = q.default_opts(tol=TOL_LIB, tau_policy=1 if policy == "cost" else 0, use_omega=omega)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=o, return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    r = oracle.eig_partial(A, fraction=f, tol=TOL_LIB, tau_policy=policy, use_omega=bool(omega))
+    k = r["k"]
+    print(f"  tau {info['tau']:.6f} / {r['tau']:.6f} kinds {info['kinds']} ell {info['ell']} / {r['ell']}", flush=True)
+    assert abs(info["tau"] - r["tau"]) < 1e-8
+    assert info["kinds"] == [st["kind"] for st in r["sched"]]
+    assert abs(info["ell"] - r["ell"]) <= 2
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met
+
+
+def _tail_spectrum(n, seed):
+    """10% of the eigenvalues in [0.5, 1], the rest far below in [-30, -5]:
+    the unwanted side lies beyond the two-step band, where s = 0.875 pays."""
+    from synthetic import rng, haar, planted_sym
+    g = rng(seed)
+    Q = haar(g, n)
+    nt = n // 10
+    lam = np.concatenate([g.uniform(0.5, 1.0, nt), g.uniform(-30.0, -5.0, n - nt)])
+    return planted_sym(Q, lam), lam
+
+
+@pytest.mark.parametrize("n,f,seed,spec", [(512, 0.1, 1000, "uniform"), (600, 0.08, 33, "tail")])
+def test_two_step_variant_vs_oracle(n, f, seed, spec):
+    """Sec. 4.1's other shift choice: s = 0.875 with two DWH steps (type (9,8)):
+    cheaper iterations, a band reaching ~5 |mu| beyond the threshold (on a
+    uniform spectrum that is everything, ell = n; with the unwanted part far
+    below, ell stays near k)."""
+    torch, q = _gpu()
+    A, lam = eig_uniform(n, seed) if spec == "uniform" else _tail_spectrum(n, seed)
+    print(f"s=0.875 two steps n={n} f={f} {spec}", flush=True)
+    o = q.default_opts(tol=TOL_LIB, s_eig=0.875, eig_iters=2)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=o, return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    r = oracle.eig_partial(A, fraction=f, tol=TOL_LIB, s=0.875, iters=2)
+    k = r["k"]
+    print(f"  kinds {info['kinds']} ell {info['ell']} / {r['ell']}", flush=True)
+    assert info["n_iter"] == 2 and info["kinds"] == [st["kind"] for st in r["sched"]]
+    assert abs(info["ell"] - r["ell"]) <= 2
+    if spec == "tail":
+        assert info["ell"] < n // 2
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met

@@ -282,3 +282,38 @@ def test_svd_graded_kappa_1e12_keeps_ell_below_n():
     r = oracle.svd_partial(A, k=k)
     assert r["ell"] < 256
     assert np.max(np.abs(r["S"] - sig[:k]) / sig[:k]) <= 1e-12
+
+
+def test_cost_policy_turns_qr_steps_into_cholesky_steps():
+    """A clustered spectrum with 1% wanted: the plain cut lands in the top
+    clusters, rho is large and QR-based steps follow; the cost policy picks a
+    lower cut whose three Cholesky-based steps and larger subspace cost fewer
+    Table 1 flops, with the same planted values."""
+    from oracle.estimator import predicted_flops
+    A, lam = eig_clustered(1024, 1002)
+    rp = oracle.eig_partial(A, fraction=0.01, tau_policy="plain")
+    rc = oracle.eig_partial(A, fraction=0.01, tau_policy="cost")
+    assert "qr" in [st["kind"] for st in rp["sched"]]
+    assert [st["kind"] for st in rc["sched"]] == ["chol"] * 3
+    assert rc["tau"] < rp["tau"] and rc["ell"] > rp["ell"]
+    assert predicted_flops(rc["sched"], 1024, rc["ell"]) < predicted_flops(rp["sched"], 1024, rp["ell"])
+    ex = np.sort(lam)[::-1][:rc["k"]]
+    for r in (rp, rc):
+        met = oracle.eig_metrics(A, r["w"], r["V"], ex)
+        assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met
+    # the band edge predicts the subspace size (the count of planted values
+    # above it) to within the non-rank-revealing slack of the plain QR
+    from oracle.estimator import _band_edge
+    edge = rc["tau"] - rc["mu"] * (_band_edge(rc["sched"], 0.2, 0.01) + 0.2) / 0.8
+    pred = int(np.sum(lam >= edge))
+    assert abs(rc["ell"] - pred) <= max(3, 0.02 * pred)
+
+
+def test_omega_qr_gives_the_same_subspace_values():
+    """QR of B Omega (Sec. 4.1, randomised rank-revealing form): same planted
+    values, a subspace containing the wanted one."""
+    A, lam = eig_uniform(400, 61)
+    r = oracle.eig_partial(A, fraction=0.1, use_omega=True)
+    ex = np.sort(lam)[::-1][:r["k"]]
+    met = oracle.eig_metrics(A, r["w"], r["V"], ex)
+    assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met
