@@ -1,17 +1,26 @@
 """Benchmark: n = 16384 partial symmetric eigensolve (QDWHpartial-EIG, FP64) on one MI355X.
 
-Workload (default): A = Q diag(lambda) Q^T, n = 16384, Q Haar, 90% of the
+Workload (headline): A = Q diag(lambda) Q^T, n = 16384, Q Haar, 90% of the
 eigenvalues uniform on [-1, 0.5] and 10% in 8 clusters of width 1e-8 in
 [0.5, 1]; the top 20% (3277) eigenpairs are wanted.  One step = one full
 solve (estimator, three DWH steps, projector QR, Rayleigh-Ritz) with A
-already resident in HBM.
+already resident in HBM; the timed steps run without any profiling hooks.
 
 Prints one JSON line.  Besides the time to solution it reports
-  * roofline: the FP64 MFMA GEMM kernel (the dominant kernel), algorithmic
+  * roofline: the FP64 MFMA GEMM kernel (the dominant kernel): algorithmic
     flops / summed kernel time from hipEvents around each of its launches
-    during the timed steps, against the 78.6 TFLOP/s FP64 peak;
-  * cpu_baseline: the CPU oracle timed on a bounded sample of the same
-    workload (smaller n, same spectrum recipe), scaled to n = 16384 by n^3.
+    during one extra solve after the timed ones, against the 78.6 TFLOP/s
+    FP64 peak; traffic = HBM bytes per launch from the committed
+    rocprofv3 counter summary when it was taken on the current GEMM source;
+  * workloads: the other benchmark configurations (n = 16384 top 1%, the
+    4096^2 kappa = 1e16 SVD, the 16384 x 8192 SVD in FP64 and mixed
+    precision, n = 512), each with time, Table 1 flop rate, value error
+    against the planted spectrum and the residual over all returned vectors;
+  * batched / serving: a ragged request mix (batched vs one call at a time;
+    closed-loop capacity of the server, then an open-loop Poisson trace at
+    0.7x that capacity, FP64 and mixed);
+  * cpu_baseline: the CPU oracle timed on the same spectrum recipe at
+    n = 4096 and, when the budget allows, 8192, scaled to n = 16384 by n^3.
 """
 import argparse
 import json
@@ -37,7 +46,12 @@ def parse():
     p.add_argument("--n", type=int, default=16384)
     p.add_argument("--fraction", type=float, default=0.2)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work to aim for")
+    p.add_argument("--cpu-budget", type=float, default=150.0,
+                   help="the oracle also runs at n = 8192 when 8x its n = 4096 time fits this (s)")
+    p.add_argument("--no-workloads", action="store_true", help="skip the other benchmark configurations")
+    p.add_argument("--input", default="", help="load the headline matrix (and *_lam.npy) from this .npy "
+                   "instead of generating it on the device")
+    p.add_argument("--write-input", default="", help="write the generated headline matrix to this .npy and exit")
     p.add_argument("--no-serve", action="store_true", help="skip the batched and served request-mix legs")
     p.add_argument("--gemm-probe", action="store_true",
                    help="only the 1 GiB copy and the two dominant n^3 GEMM shapes of a Cholesky step "
@@ -45,7 +59,6 @@ def parse():
     p.add_argument("--copy-probe", action="store_true",
                    help="first copy 1 GiB device to device (calibrates HBM byte counters under rocprofv3 --pmc)")
     p.add_argument("--serve-requests", type=int, default=48)
-    p.add_argument("--serve-rate", type=float, default=3.0, help="Poisson arrival rate (requests/s)")
     return p.parse_args()
 
 
@@ -102,17 +115,32 @@ def batched_leg(q, torch, mix):
 
 
 def serve_leg(q, torch, mix, trace, precision):
-    """Open-loop Poisson arrivals into the request server; latency = arrival to results ready."""
-    import numpy as np
+    """The request server, first closed loop (every request submitted at
+    once, so the lanes never idle: capacity = requests / span), then the
+    trace's Poisson arrivals replayed open loop at 0.7x that capacity;
+    latency = submit to results ready.  Reports throughput, p50/p99 latency,
+    the arena high-water mark and the value error against the planted spectra."""
     opts = q.default_opts(precision=precision)
-    lat, qms, errs, done_t = [], [], [], []
+    out = {"precision": "fp64" if precision == 0 else "mixed_fp32", "requests": len(mix)}
     with q.Server(arena_bytes=64 << 30, lanes=0, opts=opts) as srv:
         warm = srv.submit(mix[0][0])
         srv.poll(warm)
+        srv.stats(reset=True)
+        t0 = time.perf_counter()
+        tickets = [srv.submit(spec) for spec, _ in mix]
+        for tk in tickets:
+            srv.poll(tk)
+        span = time.perf_counter() - t0
+        cap = len(mix) / span
+        peak, arena, peak_run = srv.stats(reset=True)
+        out["closed_loop"] = {"solves_per_s": cap, "span_s": span, "arena_peak_bytes": peak,
+                              "peak_running": peak_run}
+        rate = 0.7 * cap
+        lat, qms, errs = [], [], []
         t0 = time.perf_counter()
         tickets = []
         for (spec, exact), r in zip(mix, trace):
-            delay = r["arrival"] - (time.perf_counter() - t0)
+            delay = r["arrival"] / rate - (time.perf_counter() - t0)   # trace drawn at rate 1
             if delay > 0:
                 time.sleep(delay)
             tickets.append(srv.submit(spec))
@@ -123,20 +151,43 @@ def serve_leg(q, torch, mix, trace, precision):
             except q.QdwhpError as e:
                 failed.append((i, e.status))
                 continue
-            lat.append(l); qms.append(qm)
-            done_t.append(time.perf_counter() - t0)
+            lat.append(l)
+            qms.append(qm)
             errs.append(_relerr(spec, res, exact))
         span = time.perf_counter() - t0
+        peak, arena, peak_run = srv.stats()
     lat = np.array(lat)
-    return {"precision": "fp64" if precision == 0 else "mixed_fp32", "requests": len(lat),
-            "offered_rate_per_s": len(trace) / trace[-1]["arrival"],
-            "solves_per_s": len(lat) / span, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_queue_ms": float(np.mean(qms)),
-            "max_rel_value_err": float(max(errs)), "failed": failed}
+    out["open_loop"] = {"offered_rate_per_s": rate, "solves_per_s": len(lat) / span,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "max_ms": float(lat.max()), "mean_queue_ms": float(np.mean(qms)),
+                        "arena_peak_bytes": peak, "arena_bytes": arena, "peak_running": peak_run,
+                        "max_rel_value_err": float(max(errs)), "failed": failed}
+    out["trace"] = (f"{len(mix)} requests, Poisson arrivals at 0.7x the closed-loop capacity, 60% EIG / 40% SVD, "
+                    "n in {256..4096}, fraction U[1%,20%], SVD kappa 10^U[0,12]")
+    return out
+
+
+def _host_info():
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    return cpu, nproc
 
 
 def cpu_baseline(n_full, fraction, budget):
-    """Time the oracle on the same workload recipe at a reduced size."""
+    """Time the oracle on the same workload recipe (same tol as the library)
+    at n = 4096 and, when the n^3 extrapolation of that run fits the budget,
+    at 8192; the largest run is scaled to n_full by n^3."""
     import oracle
     from synthetic import eig_clustered
     try:
@@ -144,24 +195,155 @@ def cpu_baseline(n_full, fraction, budget):
         threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     except Exception:
         threads = os.cpu_count() or 1
-    ns = 512
-    t = 0.0
+    cpu, nproc = _host_info()
+    runs = {}
+    ns = 4096
     while True:
         A, lam = eig_clustered(ns, 1002)
         t0 = time.perf_counter()
-        r = oracle.eig_partial(A, fraction=fraction)
+        r = oracle.eig_partial(A, fraction=fraction, tol=0.05)
         t = time.perf_counter() - t0
-        # next size costs ~8x: stop when that would exceed the budget
-        if t * 8.0 > budget or 2 * ns > n_full:
+        exact = np.sort(lam)[::-1][:r["k"]]
+        runs[ns] = (t, float(np.max(np.abs(r["w"] - exact) / np.abs(exact))))
+        print(f"[bench] oracle n={ns}: {t:.1f} s", file=sys.stderr, flush=True)
+        if 2 * ns > n_full or t * 8.0 > budget:
             break
         ns *= 2
-    exact = np.sort(lam)[::-1][:r["k"]]
-    err = float(np.max(np.abs(r["w"] - exact) / np.abs(exact)))
-    scaled = t * (n_full / ns) ** 3
-    return dict(value=scaled, unit="s", cores=int(threads), kind="oracle",
-                sample=f"oracle eig_partial on the same spectrum recipe at n={ns} "
-                       f"(top {fraction:.0%}) took {t:.2f} s; scaled by (n/{ns})^3 to n={n_full}; "
+    t, err = runs[ns]
+    return dict(value=t * (n_full / ns) ** 3, unit="s", cores=int(threads), kind="oracle",
+                host_cpu=cpu, host_nproc=nproc,
+                runs_s={str(k): round(v[0], 2) for k, v in runs.items()},
+                sample=f"oracle eig_partial (NumPy/SciPy FP64, {threads} BLAS threads on {nproc} host CPUs) "
+                       f"on the same spectrum recipe at n={ns} (top {fraction:.0%}) took {t:.2f} s; "
+                       f"scaled by (n/{ns})^3 to n={n_full} (a factor {(n_full / ns) ** 3:.0f}); "
                        f"max rel value err {err:.1e}")
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "dgemm_kernel_eig16384_top20_traffic.md")
+GEMM_SOURCE = os.path.join(ROOT, "paper_2104_14186_amd", "csrc", "gemm.hip")
+
+
+def traffic_from_profile():
+    """HBM bytes per dgemm_kernel launch from the committed counter summary,
+    or None when it is missing or was taken on another version of the GEMM
+    source (sha256 recorded in the summary)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        sha = hashlib.sha256(open(GEMM_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            key, _, v = line[2:].partition(":")
+            vals[key.strip()] = v.strip().strip("`")
+    if vals.get("gemm.hip sha256") != sha:
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _time_calls(torch, fn, warmup, steps):
+    """Median and all per-call times (ms) from torch events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    stream = torch.cuda.current_stream()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts)), ts
+
+
+def eig_entry(q, torch, name, A, lam, f, opts=None, warmup=1, steps=2, extra=None):
+    out = {}
+
+    def run():
+        out["r"] = q.eig(A, fraction=f, opts=opts, return_info=True)
+
+    med, ts = _time_calls(torch, run, warmup, steps)
+    w, V, info = out["r"]
+    k = len(w)
+    exact = torch.as_tensor(np.sort(lam)[::-1][:k].copy(), device=A.device)
+    norm = float(np.max(np.abs(lam)))
+    res = float((A @ V - V * w[None, :]).norm(dim=0).max()) / norm
+    orth = float((V.t() @ V - torch.eye(k, dtype=V.dtype, device=V.device)).abs().max())
+    rel = float(((w - exact).abs() / exact.abs()).max())
+    e = {"workload": name, "ms": med, "ms_all": [round(t, 2) for t in ts], "k": k, "ell": info["ell"],
+         "kinds": info["kinds"], "rr_split": info["rr_split"], "jacobi_sweeps": info["jacobi_sweeps"],
+         "mfma_frac_table1": info["flops_table1"] / (med * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
+         "max_rel_value_err": rel, "residual_all_k": res, "orth_all_k": orth,
+         "phases_ms": dict(zip(PHASES, [round(x, 2) for x in info["ms"]]))}
+    if extra:
+        e.update(extra)
+    return e
+
+
+def svd_entry(q, torch, name, A, sig, k, opts=None, warmup=1, steps=2, ref=None, extra=None):
+    out = {}
+
+    def run():
+        out["r"] = q.svd(A, k, opts=opts, return_info=True)
+
+    med, ts = _time_calls(torch, run, warmup, steps)
+    U, S, V, info = out["r"]
+    exact = torch.as_tensor(np.asarray(sig)[:k].copy(), device=A.device)
+    r1 = (A @ V - U * S[None, :]).norm(dim=0).max()
+    r2 = (A.t() @ U - V * S[None, :]).norm(dim=0).max()
+    eye = torch.eye(k, dtype=U.dtype, device=U.device)
+    e = {"workload": name, "ms": med, "ms_all": [round(t, 2) for t in ts], "k": k, "ell": info["ell"],
+         "kinds": info["kinds"], "s": info["s"],
+         "mfma_frac_table1": info["flops_table1"] / (med * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
+         "max_rel_value_err": float(((S - exact).abs() / exact).max()),
+         "residual_all_k": float(max(r1, r2)) / float(sig[0]),
+         "orth_all_k": float(max((U.t() @ U - eye).abs().max(), (V.t() @ V - eye).abs().max())),
+         "phases_ms": dict(zip(PHASES, [round(x, 2) for x in info["ms"]]))}
+    if ref is not None:
+        U0, S0, V0 = ref
+        e["vs_fp64"] = {"max_rel_value_diff": float(((S - S0).abs() / S0).max()),
+                        "max_vector_diff": float(max((U - U0).norm(dim=0).max(), (V - V0).norm(dim=0).max()))}
+    if extra:
+        e.update(extra)
+    return e, (U, S, V)
+
+
+def workloads_leg(q, torch, dev, A16, lam16):
+    """The other benchmark configurations, each timed and checked."""
+    from synthetic import svd_geometric, svd_loguniform, eig_uniform, CONFIG_SEEDS
+    out = []
+    print("[bench] eig16384 top 1%", file=sys.stderr, flush=True)
+    out.append(eig_entry(q, torch, "eig16384_top1pct_clustered", A16, lam16, 0.01))
+    print("[bench] svd4096 kappa 1e16 top 5%", file=sys.stderr, flush=True)
+    A, sig = svd_geometric(4096, 4096, CONFIG_SEEDS["svd4096"], kappa=1e16, device=dev)
+    out.append(svd_entry(q, torch, "svd4096_kappa1e16_top5pct", A, sig, 205, steps=3)[0])
+    out.append(svd_entry(q, torch, "svd4096_kappa1e16_top5pct_qr_first", A, sig, 205, steps=3,
+                         opts=q.default_opts(svd_qr_first=1))[0])
+    del A
+    print("[bench] svd16384x8192 top 10%", file=sys.stderr, flush=True)
+    A, sig = svd_loguniform(16384, 8192, CONFIG_SEEDS["svd16384x8192"], device=dev)
+    e64, ref = svd_entry(q, torch, "svd16384x8192_top10pct_fp64", A, sig, 819, steps=3)
+    out.append(e64)
+    emx, _ = svd_entry(q, torch, "svd16384x8192_top10pct_mixed_fp32", A, sig, 819, steps=3,
+                       opts=q.default_opts(precision=q.MIXED_FP32), ref=ref)
+    emx["speedup_vs_fp64"] = e64["ms"] / emx["ms"]
+    out.append(emx)
+    del A, ref
+    print("[bench] eig512 top 10%", file=sys.stderr, flush=True)
+    A, lam = eig_uniform(512, CONFIG_SEEDS["eig512"], device=dev)
+    out.append(eig_entry(q, torch, "eig512_top10pct_uniform", A, lam, 0.1, steps=5))
+    torch.cuda.synchronize()
+    return out
+
+
+PHASES = ["estimator", "iterations", "projector_qr", "q2", "rr_products", "small_solve", "vectors", "total"]
 
 
 def gemm_probe(torch, dev, n):
@@ -227,9 +409,21 @@ def main():
         torch.cuda.synchronize()
         del x, y
     n, f = args.n, args.fraction
-    print(f"[bench] generating n={n} planted matrix", file=sys.stderr, flush=True)
-    A, lam = eig_clustered(n, 1002, device=dev)
-    A = A.contiguous()              # symmetric: row-major storage is the column-major matrix
+    if args.input:
+        print(f"[bench] loading {args.input}", file=sys.stderr, flush=True)
+        Ah = np.load(args.input, mmap_mode="r")
+        lam = np.load(args.input.replace(".npy", "_lam.npy"))
+        A = torch.from_numpy(np.ascontiguousarray(Ah)).to(dev)
+        n = A.shape[0]
+    else:
+        print(f"[bench] generating n={n} planted matrix", file=sys.stderr, flush=True)
+        A, lam = eig_clustered(n, 1002, device=dev)
+        A = A.contiguous()              # symmetric: row-major storage is the column-major matrix
+    if args.write_input:
+        np.save(args.write_input, A.cpu().numpy())
+        np.save(args.write_input.replace(".npy", "_lam.npy"), lam)
+        print(json.dumps({"written": args.write_input, "n": n}), flush=True)
+        return
     torch.cuda.synchronize()
     k = min(n, max(1, int(math.floor(f * n + 0.5))))
     opts = q.default_opts()
@@ -254,28 +448,29 @@ def main():
         print(f"[bench] warmup {i}", file=sys.stderr, flush=True)
         solve()
     torch.cuda.synchronize()
-    q.profile_begin()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
-    t0 = time.perf_counter()
     for i in range(args.steps):
         solve()
         print(f"[bench] step {i} done", file=sys.stderr, flush=True)
     e1.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gflops, gms, glaunch = q.profile_end()
     ms_step = e0.elapsed_time(e1) / args.steps
     d = info.as_dict()
+    # roofline of the GEMM kernel: one more solve with per-launch events
+    q.profile_begin()
+    solve()
+    torch.cuda.synchronize()
+    gflops, gms, glaunch = q.profile_end()
+    print("[bench] roofline pass done", file=sys.stderr, flush=True)
 
-    # accuracy of the last solve against the planted spectrum, and sampled residuals
+    # accuracy of the timed solve: planted values, every returned vector
     exact = np.sort(lam)[::-1][:k]
     wv = w.cpu().numpy()
     rel = float(np.max(np.abs(wv - exact) / np.abs(exact)))
-    cols = torch.linspace(0, k - 1, 8, device=dev).long()
-    Vs = Vb[cols].t().contiguous()               # n x 8 sampled eigenvectors
-    R = A @ Vs - Vs * w[cols][None, :]
-    resid = float((R.norm(dim=0) / float(np.max(np.abs(lam)))).max())
+    V = Vb.t()
+    resid = float((A @ V - V * w[None, :]).norm(dim=0).max()) / float(np.max(np.abs(lam)))
+    orth = float((Vb @ V - torch.eye(k, dtype=V.dtype, device=dev)).abs().max())
 
     achieved = gflops / (gms * 1e-3) / 1e12 if gms > 0 else 0.0
     out = {
@@ -296,29 +491,33 @@ def main():
                    "seed": 1002, "parallelism": "single_gpu"},
         "solves_per_s": 1e3 / ms_step,
         "mfma_frac_table1": d["flops_table1"] / (ms_step * 1e-3) / (FP64_PEAK_TFLOPS * 1e12),
-        "phases_ms": dict(zip(["estimator", "iterations", "projector_qr", "q2", "rr_products",
-                               "small_solve", "vectors", "total"], [round(x, 2) for x in d["ms"]])),
+        "phases_ms": dict(zip(PHASES, [round(x, 2) for x in d["ms"]])),
         "solver": {kk: d[kk] for kk in ["ell", "ind", "kinds", "jacobi_sweeps", "rr_split", "tau", "retries"]},
-        "accuracy": {"max_rel_value_err": rel, "sampled_residual": resid},
+        "accuracy": {"max_rel_value_err": rel, "residual_all_k": resid, "orth_all_k": orth},
         "roofline": {"bound": "mfma", "kernel": "dgemm_kernel (FP64 v_mfma_f64_16x16x4f64)",
                      "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "launches": glaunch, "kernel_ms_per_step": gms / args.steps,
-                     "algorithmic_flops_per_launch": gflops / max(glaunch, 1)},
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": traffic_from_profile(),
+                     "traffic_unit": "HBM bytes per launch",
+                     "launches": glaunch, "kernel_ms_per_solve": gms,
+                     "algorithmic_flops_per_launch": gflops / max(glaunch, 1),
+                     "measured": "hipEvents around each launch during one extra solve after the timed steps"},
     }
+    del ws
+    torch.cuda.empty_cache()
+    if not args.no_workloads:
+        out["workloads"] = workloads_leg(q, torch, dev, A, lam)
+    del A, Vb
+    torch.cuda.empty_cache()
     if not args.no_serve:
         from synthetic import request_trace, CONFIG_SEEDS
-        trace = request_trace(args.serve_requests, args.serve_rate, CONFIG_SEEDS["trace"])
+        trace = request_trace(args.serve_requests, 1.0, CONFIG_SEEDS["trace"])
         print("[bench] building request mix", file=sys.stderr, flush=True)
         mix = build_mix(torch, trace)
         print("[bench] batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(q, torch, mix[:24])
-        print("[bench] served leg fp64", file=sys.stderr, flush=True)
-        out["serving"] = serve_leg(q, torch, mix, trace, q.FP64)
-        print("[bench] served leg mixed", file=sys.stderr, flush=True)
-        out["serving_mixed"] = serve_leg(q, torch, mix, trace, q.MIXED_FP32)
-        out["serving"]["trace"] = (f"{len(trace)} requests, Poisson {args.serve_rate}/s, 60% EIG / 40% SVD, "
-                                   "n in {256..4096}, fraction U[1%,20%], SVD kappa 10^U[0,12]")
+        for prec, key in ((q.FP64, "serving"), (q.MIXED_FP32, "serving_mixed")):
+            print(f"[bench] served leg {key}", file=sys.stderr, flush=True)
+            out[key] = serve_leg(q, torch, mix, trace, prec)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(n, f, args.cpu_budget)

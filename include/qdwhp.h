@@ -340,6 +340,13 @@ int qdwhp_serve_submit(qdwhp_server* srv, const qdwhp_problem* p, int64_t* ticke
 int qdwhp_serve_poll(qdwhp_server* srv, int64_t ticket, int wait, qdwhp_info* info,
                      double* latency_ms, double* queue_ms);
 int qdwhp_serve_destroy(qdwhp_server* srv);
+/* High-water marks since creation or the last reset: the largest sum of the
+ * footprints of requests running at once (bytes of the arena in use, i.e.
+ * the server's HBM high-water mark inside its arena), the arena size, and
+ * the most requests running at once.  reset != 0 restarts both marks from
+ * the current state.  Any pointer may be NULL. */
+int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
+                      int reset);
 
 /* ---- tuning table ------------------------------------------------------ */
 /*

@@ -109,6 +109,7 @@ _SIGS = {
     "qdwhp_serve_submit": (_I, [_P, ctypes.POINTER(Problem), _PI64]),
     "qdwhp_serve_poll": (_I, [_P, _I64, _I, ctypes.POINTER(Info), _PD, _PD]),
     "qdwhp_serve_destroy": (_I, [_P]),
+    "qdwhp_serve_stats": (_I, [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_I), _I]),
     "qdwhp_tune_set": (_I, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_get": (_I64, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_clear": (None, []),
@@ -471,6 +472,13 @@ class Server:
         keep, out = self._live.pop(ticket)
         _check(st, "qdwhp_serve request")
         return _result(out), info.as_dict(), lat.value, q.value
+
+    def stats(self, reset=False):
+        """(peak bytes of the arena in use, arena bytes, most requests running at once)."""
+        pk, cap, pr = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int(0)
+        _check(lib().qdwhp_serve_stats(self._h, ctypes.byref(pk), ctypes.byref(cap), ctypes.byref(pr),
+                                       int(bool(reset))), "qdwhp_serve_stats")
+        return pk.value, cap.value, pr.value
 
     def close(self):
         if self._h:

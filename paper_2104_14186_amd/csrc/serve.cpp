@@ -91,6 +91,8 @@ struct qdwhp_server {
   int64_t next_id = 1;
   bool stop = false;
   int running = 0;
+  int peak_running = 0;
+  size_t in_use = 0, peak_bytes = 0;
   std::vector<std::thread> lanes;
 
   std::vector<hipStream_t> streams;
@@ -111,6 +113,9 @@ struct qdwhp_server {
       Request& r = reqs[id];
       r.t_start = Clock::now();
       ++running;
+      in_use += r.bytes;
+      peak_bytes = std::max(peak_bytes, in_use);
+      peak_running = std::max(peak_running, running);
       const qdwhp_problem p = r.p;
       const size_t bytes = r.bytes;
       lk.unlock();
@@ -123,6 +128,7 @@ struct qdwhp_server {
       q.status = st;
       q.info = info;
       --running;
+      in_use -= bytes;
       alloc.give(off, bytes);
       cv_done.notify_all();
       cv_work.notify_all();
@@ -201,6 +207,20 @@ extern "C" int qdwhp_serve_poll(qdwhp_server* srv, int64_t ticket, int wait, qdw
   const int st = r.status;
   srv->reqs.erase(ticket);
   return st;
+}
+
+extern "C" int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
+                                 int reset) {
+  if (!srv) return -1;
+  std::lock_guard<std::mutex> g(srv->mu);
+  if (peak_bytes) *peak_bytes = srv->peak_bytes;
+  if (arena_bytes) *arena_bytes = srv->cap;
+  if (peak_running) *peak_running = srv->peak_running;
+  if (reset) {
+    srv->peak_bytes = srv->in_use;
+    srv->peak_running = srv->running;
+  }
+  return QDWHP_OK;
 }
 
 extern "C" int qdwhp_serve_destroy(qdwhp_server* srv) {
