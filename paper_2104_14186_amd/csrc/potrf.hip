@@ -13,7 +13,7 @@
 //      [Z11 Z12; . Z22] gives W11 = chol(Z11), W12 = W11^{-T} Z12,
 //      Z22 <- Z22 - W12^T W12, W22 = chol(Z22) and
 //      W^{-1}_{12} = -W11^{-1} W12 W22^{-1}; 64x64 leaves are factored and
-//      inverted in LDS by one workgroup;
+//      inverted by one wave (rows in registers, broadcasts through LDS);
 //   2. Z^{-1} = W^{-1} W^{-T}, upper tiles only, K starting at the tile column;
 //   3. mirror the upper triangle.
 #include "common.h"
@@ -26,68 +26,97 @@ constexpr int NB = 64;
 // Factor the bs x bs leaf (bs <= 64) at Z (upper triangle read) and write its
 // inverse factor W^{-1} (upper, zeros below) to Wi.  The factor W itself is
 // written back to Z's upper triangle.
-__global__ __launch_bounds__(256) void chol_inv_leaf(double* Z, int64_t ldz, double* Wi, int64_t ldw,
-                                                     int bs, int* flag) {
-  __shared__ double S[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ double rpiv;
-  __shared__ double rd[NB];
-  const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e % NB, c = e / NB;
-    double v = 0.0;
-    if (r < bs && c < bs) v = (r <= c) ? Z[r + (int64_t)c * ldz] : 0.0;
-    S[r][c] = v;
-    X[r][c] = 0.0;
+//
+// One wave of 64 lanes, no workgroup barriers on the critical path.  With
+// L = W^T (lower), lane i keeps row i of the matrix in registers (a[0..i]);
+// rows past bs are padded with the identity, so the padded block factors to
+// the identity and leaves the leading block untouched.
+//   factorisation (right-looking): at step k the lanes publish a(:, k) in
+//   LDS, every lane reads the pivot a_kk, scales its own entry to
+//   L_ik = a_ik / sqrt(a_kk) and updates a_ij -= L_ik L_jk for j > k, reading
+//   L_jk = a_jk / sqrt(a_kk) as a broadcast from LDS;
+//   inverse M = L^{-1} (forward substitution, lane j owning column j of M):
+//   M_kj = (delta_kj - sum_{i<k} L_ki M_ij) / L_kk, the row L_k,0..k-1 read
+//   as a broadcast from LDS; W^{-1} = M^T is written column by column.
+constexpr int LW = 64;   // lanes of the leaf wave
+__global__ __launch_bounds__(LW) void chol_inv_leaf(double* Z, int64_t ldz, double* Wi, int64_t ldw,
+                                                    int bs, int* flag) {
+  __shared__ double S[NB][NB + 1];     // S[r][c]: the input, then L, then M^T
+  __shared__ double colbuf[2][NB];
+  const int i = threadIdx.x;
+  // coalesced load of the upper triangle (lane = row of Z); identity padding
+#pragma clang loop unroll_count(4)
+  for (int c = 0; c < NB; ++c) {
+    double v = (i == c) ? 1.0 : 0.0;
+    if (c < bs && i <= c) v = Z[i + (int64_t)c * ldz];
+    S[i][c] = v;
   }
   __syncthreads();
-  for (int j = 0; j < bs; ++j) {
-    if (t == 0) {
-      double d = S[j][j];
-      if (!(d > 0.0) || !isfinite(d)) { *flag = 1; d = 1.0; }
-      const double p = sqrt(d);
-      S[j][j] = p;
-      rpiv = 1.0 / p;
-    }
+  double a[NB];
+#pragma clang loop unroll(full)
+  for (int j = 0; j < NB; ++j) a[j] = S[j][i];   // row i of the lower triangle (S is zero below its diagonal)
+  bool bad = false;
+  double piv = 1.0;                      // this lane's L_ii
+#pragma clang loop unroll(full)
+  for (int k = 0; k < NB; ++k) {
+    // branch-free step: every lane publishes a_ik, reads the pivot, then
+    // publishes its L_ik in the other buffer
+    double* craw = colbuf[0];
+    double* cl = colbuf[1];
+    craw[i] = a[k];
     __syncthreads();
-    if (t > j && t < bs) S[j][t] *= rpiv;
+    double d = craw[k];
+    const bool nonpos = !(d > 0.0) || !isfinite(d);
+    bad = bad || nonpos;
+    d = nonpos ? 1.0 : d;
+    const double p = sqrt(d);
+    const double lik = a[k] / p;
+    a[k] = (i == k) ? p : lik;
+    piv = (i == k) ? p : piv;
+    cl[i] = lik;
     __syncthreads();
-    // trailing update without branches, so the 16 independent read-modify-
-    // writes of a thread issue together
-#pragma unroll
-    for (int u = 0; u < NB * NB / 256; ++u) {
-      const int e = t + 256 * u, r = e % NB, c = e / NB;
-      const double f = (r > j && r <= c && c < bs) ? S[j][r] : 0.0;
-      S[r][c] -= f * S[j][c];
-    }
+#pragma clang loop unroll(full)
+    for (int j = k + 1; j < NB; ++j) a[j] -= lik * cl[j];   // L_jk as a broadcast
     __syncthreads();
   }
-  // back substitution W X = I, one column of X per thread (X upper
-  // triangular); the diagonal reciprocals are formed once, so the dependent
+  if (bad && i == 0) *flag = 1;
+  // L to LDS (row i; entries past the diagonal are never read)
+#pragma clang loop unroll(full)
+  for (int j = 0; j < NB; ++j) S[i][j] = a[j];
+  __syncthreads();
+  // W = L^T into Z's upper triangle (lane = row of Z)
+  if (i < bs) {
+#pragma clang loop unroll_count(4)
+    for (int c = i; c < bs; ++c) Z[i + (int64_t)c * ldz] = S[c][i];
+  }
+  // inverse M = L^{-1}, lane j owning column j; the diagonal reciprocals
+  // are formed once (lane k holds 1/L_kk) and read across the wave, so the
   // chain of each column has no division
-  if (t < bs) rd[t] = 1.0 / S[t][t];
-  __syncthreads();
-  if (t < bs) {
-    const int c = t;
-    X[c][c] = rd[c];
-    for (int i = c - 1; i >= 0; --i) {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;   // independent chains
-      int k = i + 1;
-      for (; k + 3 <= c; k += 4) {
-        a0 += S[i][k] * X[k][c];
-        a1 += S[i][k + 1] * X[k + 1][c];
-        a2 += S[i][k + 2] * X[k + 2][c];
-        a3 += S[i][k + 3] * X[k + 3][c];
-      }
-      for (; k <= c; ++k) a0 += S[i][k] * X[k][c];
-      X[i][c] = -((a0 + a1) + (a2 + a3)) * rd[i];
+  const double rd = 1.0 / piv;
+  const long long rdb = __double_as_longlong(rd);
+  const int rd_lo = (int)(rdb & 0xffffffffLL), rd_hi = (int)(rdb >> 32);
+  double m[NB];
+#pragma clang loop unroll(full)
+  for (int k = 0; k < NB; ++k) {
+    double s0 = (k == i) ? 1.0 : 0.0, s1 = 0.0;   // two independent chains
+#pragma clang loop unroll(full)
+    for (int q = 0; q < k; ++q) {
+      if (q & 1) s1 -= S[k][q] * m[q]; else s0 -= S[k][q] * m[q];
+      if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
     }
+    const long long rk = ((long long)__builtin_amdgcn_readlane(rd_hi, k) << 32) |
+                         (unsigned)__builtin_amdgcn_readlane(rd_lo, k);
+    m[k] = (s0 + s1) * __longlong_as_double(rk);
   }
   __syncthreads();
-  for (int e = t; e < bs * bs; e += 256) {
-    const int r = e % bs, c = e / bs;
-    if (r <= c) Z[r + (int64_t)c * ldz] = S[r][c];
-    Wi[r + (int64_t)c * ldw] = (r <= c) ? X[r][c] : 0.0;
+  // W^{-1} = M^T: M's column i (held by lane i) is row i of W^{-1}; staged
+  // through LDS so the stores run down columns
+#pragma clang loop unroll(full)
+  for (int k = 0; k < NB; ++k) S[k][i] = m[k];
+  __syncthreads();
+  if (i < bs) {
+#pragma clang loop unroll_count(4)
+    for (int c = 0; c < bs; ++c) Wi[i + (int64_t)c * ldw] = (c >= i) ? S[c][i] : 0.0;
   }
 }
 
@@ -98,7 +127,7 @@ struct Rec {
     double* Zo = Z + o + o * ldz;
     double* Wo = Wi + o + o * ldw;
     if (m <= NB) {
-      chol_inv_leaf<<<1, 256, 0, s>>>(Zo, ldz, Wo, ldw, (int)m, flag);
+      chol_inv_leaf<<<1, LW, 0, s>>>(Zo, ldz, Wo, ldw, (int)m, flag);
       QDWHP_LAUNCH_CHECK();
       return;
     }

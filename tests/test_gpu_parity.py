@@ -130,12 +130,15 @@ def test_svd_vs_oracle(m, n, k, kind):
 
 
 # ------------------------------------------------------------------ tol = 0.01
-# The paper's threshold (Sec. 4.1, Algorithms 1 and 2) on both sides.  With
-# it the method's containment error is about ||V0^T B|| / sigma_min(R11)
-# with sigma_min(R11) near 0.01 (Theorem 1), so the residual depends on
-# which near-threshold columns each side keeps: the GPU's residual must be
-# within the stated 1e-13 or within 3x the oracle's own (the oracle itself
-# exceeds 1e-13 on some kappa = 1e16 inputs at this tol).
+# The paper's threshold (Sec. 4.1, Algorithms 1 and 2) on both sides.  The
+# guarantee the paper gives for the subspace is Theorem 1: sin angle(V0, Q2)
+# <= ||V0^T B|| / sigma_min(R11), V0 the planted wanted vectors.  With the
+# plain (non-pivoted) QR sigma_min(R11) falls well below tol (3e-4 .. 1e-3
+# on the kappa = 1e16 SVD inputs), and the residuals of both sides, about
+# sin angle x ||A||, land between 1e-14 and ~2e-13 depending on rounding (the
+# same oracle gives 7e-14 on one host's BLAS and 1.7e-13 on another's for
+# the same input).  Gate: the GPU's residual within 1e-13, or within the
+# Theorem 1 bound of the oracle's own factorisation.
 PAPER_CASES = [("eig", 512, 512, 0.1, 1000, "uniform"), ("eig", 1024, 1024, 0.01, 1002, "clustered"),
                ("eig", 2048, 2048, 0.2, 1002, "clustered"),
                ("svd", 300, 300, 15, 1001, "geo"), ("svd", 300, 300, 15, 1002, "geo"),
@@ -143,14 +146,23 @@ PAPER_CASES = [("eig", 512, 512, 0.1, 1000, "uniform"), ("eig", 1024, 1024, 0.01
                ("svd", 512, 512, 26, 1003, "geo"), ("svd", 1024, 512, 51, 1003, "log")]
 
 
+def _theorem1_bound(B, ind, V0):
+    _, R = np.linalg.qr(B)
+    smin = np.linalg.svd(R[:ind - 1, :ind - 1], compute_uv=False).min() if ind > 1 else 1.0
+    return float(np.linalg.norm(V0.T @ B, 2) / smin)
+
+
 @pytest.mark.parametrize("kind,m,n,f,seed,spec", PAPER_CASES)
 def test_paper_tol_vs_oracle(kind, m, n, f, seed, spec):
+    from synthetic import rng, haar
     torch, q = _gpu()
     tol = 0.01
     print(f"paper tol {kind} {m}x{n} f={f} seed={seed} {spec}", flush=True)
     o = q.default_opts(tol=tol)
+    g = rng(seed)
     if kind == "eig":
         A, lam = (eig_uniform if spec == "uniform" else eig_clustered)(n, seed)
+        Qp = haar(g, n)                       # the planted eigenvectors (same draws)
         w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=o, return_info=True)
         w, V = w.cpu().numpy(), V.cpu().numpy()
         r = oracle.eig_partial(A, fraction=f, tol=tol)
@@ -159,8 +171,11 @@ def test_paper_tol_vs_oracle(kind, m, n, f, seed, spec):
         met = oracle.eig_metrics(A, w, V, exact)
         ref = oracle.eig_metrics(A, r["w"], r["V"], exact)
         vals, rvals = w, r["w"]
+        V0 = Qp[:, lam >= r["tau"]]            # the approximate null space of B
     else:
         A, sig = (svd_geometric(m, n, seed, kappa=1e16) if spec == "geo" else svd_loguniform(m, n, seed))
+        haar(g, m, n)
+        Vp = haar(g, n)
         U, S, V, info = q.svd(torch.from_numpy(A).cuda(), f, opts=o, return_info=True)
         U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
         r = oracle.svd_partial(A, f, tol=tol)
@@ -168,13 +183,17 @@ def test_paper_tol_vs_oracle(kind, m, n, f, seed, spec):
         met = oracle.svd_metrics(A, U, S, V, exact)
         ref = oracle.svd_metrics(A, r["U"], r["S"], r["V"], exact)
         vals, rvals = S, r["S"]
+        V0 = Vp[:, :f]
+    bound = _theorem1_bound(r["B"], r["ind"], V0)
     print(f"  ell gpu {info['ell']} oracle {r['ell']}; residual gpu {met['residual']:.2e} "
-          f"oracle {ref['residual']:.2e}; values {met['value_rel_max']:.2e}", flush=True)
+          f"oracle {ref['residual']:.2e}; Theorem 1 bound {bound:.2e}; values {met['value_rel_max']:.2e}",
+          flush=True)
     assert info["kinds"] == [st["kind"] for st in r["sched"]]
     assert abs(info["ell"] - r["ell"]) <= 2
     assert np.max(np.abs(vals - rvals) / np.abs(rvals)) < 1e-12
     assert met["value_rel_max"] < 1e-12
-    assert met["residual"] <= max(1e-13, 3.0 * ref["residual"]), (met, ref)
+    assert ref["residual"] <= max(1e-13, bound)
+    assert met["residual"] <= max(1e-13, bound), (met, ref, bound)
 
 
 # ------------------------------------------- threshold policy, Omega, s = 0.875
