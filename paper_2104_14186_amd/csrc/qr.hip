@@ -110,6 +110,11 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
     if (t < w && t > j) sh_w[t] = piv_in[t] + scale * sh_s[t];
     if (g == 0 && t == 0) a.tau[j] = tau;
     __syncthreads();
+  } else {
+    // the statistics-only launch applies no reflector (f = 0); LDS left by
+    // an earlier kernel must not reach 0 * sh_w as a NaN
+    if (t < QB) sh_w[t] = 0.0;
+    __syncthreads();
   }
 
   if (one_row) {
