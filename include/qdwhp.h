@@ -348,6 +348,28 @@ int qdwhp_serve_destroy(qdwhp_server* srv);
 int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
                       int reset);
 
+/* ---- solve without allocation ------------------------------------------ */
+/*
+ * For callers that cannot allocate device memory (code between graph-capture
+ * boundaries, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as qdwhp_eig, arguments 1-8 and opts/stream/info alike, but with no
+ * workspace argument.  The workspace is a fixed array of
+ * QDWHP_NOALLOC_MAX_BYTES (128 MiB) that the library holds in the memory of
+ * every GPU it runs on until the process ends (enough for n up to about
+ * 1200); a problem whose qdwhp_eig_workspace exceeds it returns
+ * QDWHP_ERR_WORKSPACE before any device work.  The call allocates nothing:
+ * no device or pinned memory, no events, streams or graphs (info->ms stays
+ * zero, opts->graphs is ignored).  Results equal those of qdwhp_eig bitwise.
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents: calls that overlap on a GPU (from several threads or
+ * streams) race and must be serialised by the caller.
+ */
+#define QDWHP_NOALLOC_MAX_BYTES (128u << 20)
+size_t qdwhp_noalloc_max_bytes(void);
+int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, int which,
+                      double* w, double* V, int64_t ldv, const qdwhp_opts* opts, void* stream,
+                      qdwhp_info* info);
+
 /* ---- tuning table ------------------------------------------------------ */
 /*
  * Named integer parameters read by launch-shape decisions, written by the

@@ -110,6 +110,9 @@ _SIGS = {
     "qdwhp_serve_poll": (_I, [_P, _I64, _I, ctypes.POINTER(Info), _PD, _PD]),
     "qdwhp_serve_destroy": (_I, [_P]),
     "qdwhp_serve_stats": (_I, [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_I), _I]),
+    "qdwhp_noalloc_max_bytes": (_SZ, []),
+    "qdwhp_eig_noalloc": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, ctypes.POINTER(Opts), _P,
+                               ctypes.POINTER(Info)]),
     "qdwhp_tune_set": (_I, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_get": (_I64, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_clear": (None, []),
@@ -244,6 +247,29 @@ def eig(A, fraction=None, k=None, which="largest", opts=None, return_info=False,
                          _ptr(w), _ptr(Vb), n, _ptr(ws), nbytes, ctypes.byref(o),
                          stream if stream is not None else _stream(torch), ctypes.byref(info))
     _check(st, "qdwhp_eig")
+    out = (w, Vb.t())
+    return out + (info.as_dict(),) if return_info else out
+
+
+def eig_noalloc(A, fraction=None, k=None, which="largest", opts=None, return_info=False, stream=None):
+    """qdwhp_eig_noalloc: eig() with the library's fixed workspace array (no
+    workspace is allocated; n limited by qdwhp_noalloc_max_bytes).  The
+    outputs are allocated here, as for eig()."""
+    import torch
+    n = A.shape[0]
+    assert A.shape == (n, n) and A.dtype == torch.float64 and A.is_cuda
+    if fraction is None:
+        fraction = float(k) / n
+    kk = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    o = opts if opts is not None else default_opts()
+    Acm = A.t().contiguous()
+    w = torch.empty(kk, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((kk, n), dtype=torch.float64, device=A.device)
+    info = Info()
+    st = lib().qdwhp_eig_noalloc(_ptr(Acm), n, n, fraction, SMALLEST if which == "smallest" else LARGEST,
+                                 _ptr(w), _ptr(Vb), n, ctypes.byref(o),
+                                 stream if stream is not None else _stream(torch), ctypes.byref(info))
+    _check(st, "qdwhp_eig_noalloc")
     out = (w, Vb.t())
     return out + (info.as_dict(),) if return_info else out
 

@@ -66,6 +66,11 @@ void dgemm(const Gemm& g, hipStream_t s);
 // needs), honouring the upper-output and triangular K-range structure.
 double gemm_flops(const Gemm& g);
 
+// No-allocation mode of the calling thread (noalloc.hip): while set, the
+// solve path creates no events, streams or graphs (phase timing off, the
+// iterations run uncaptured, Jacobi updates H and V in one launch per round).
+bool no_alloc_mode();
+
 // Live kernel timing (prof.cpp).
 bool prof_active();
 void prof_begin_launch(hipStream_t s, void** tok);

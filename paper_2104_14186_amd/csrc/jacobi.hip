@@ -709,7 +709,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
   a.offmax = offmax;
   a.act = act;
   const int64_t ntiles = (int64_t)np2 * (np2 - 1) / 2;
-  const bool fused = n <= qdwhp_tune_get("jacobi.fused_max", 2048);
+  const bool fused = n <= qdwhp_tune_get("jacobi.fused_max", 2048) || no_alloc_mode();
   int dev = 0;
   QDWHP_HIP(hipGetDevice(&dev));
   std::unique_ptr<AuxLease> aux;

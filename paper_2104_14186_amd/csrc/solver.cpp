@@ -48,7 +48,7 @@ struct Events {
   bool on = false;
   int used = 0;
   explicit Events(bool enable) {
-    if (!enable) return;
+    if (!enable || no_alloc_mode()) return;
     for (auto& e : ev) QDWHP_HIP(hipEventCreate(&e));
     on = true;
   }
@@ -285,7 +285,7 @@ void run_iterations(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, con
       else chol_step(x, xn, m, n, 3.0, 1.0, 3.0, sym, sb, s, false);
     }
   };
-  if (graphs && sched.size() <= 16 && !prof_active()) {
+  if (graphs && sched.size() <= 16 && !prof_active() && !no_alloc_mode()) {
     std::vector<int64_t> key = {(int64_t)(intptr_t)X, (int64_t)(intptr_t)Xn, (int64_t)(intptr_t)P.big,
                                 (int64_t)(intptr_t)P.wts, m, n, sym, mixed};
     for (const auto& st : sched) key.push_back(st.kind);
