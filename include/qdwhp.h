@@ -74,10 +74,11 @@ typedef struct {
                               1   : step 0 always QR-based (Table 1 counts one)     */
   int      precision;      /* QDWHP_FP64, or QDWHP_MIXED_FP32: the Gram matrix and
                               the two triangular products of every Cholesky-based
-                              step on FP32 matrix cores; QR-based steps, the
-                              Cholesky-inversion, projector QR and Rayleigh-Ritz
-                              stay FP64                                             */
-  int      polish_steps;   /* 1   : FP64 polish steps after mixed iterations
+                              step except the last on FP32 matrix cores (the last
+                              step, FP64, maps the wanted values back to FP64
+                              accuracy); QR-based steps, the Cholesky-inversion,
+                              projector QR and Rayleigh-Ritz stay FP64             */
+  int      polish_steps;   /* 0   : extra FP64 polish steps after the iterations
                               (Newton-Schulz X(3I - X^T X)/2; EIG uses Halley's
                               (3,1,3) step when the unwanted side exceeds sqrt(3)) */
   uint64_t seed;           /* Philox key of the Lanczos start vectors               */

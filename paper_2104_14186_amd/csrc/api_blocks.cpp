@@ -18,7 +18,7 @@ extern "C" void qdwhp_opts_default(qdwhp_opts* o) {
   o->kappa_max = 100.0;
   o->svd_qr_first = 0;
   o->precision = QDWHP_FP64;
-  o->polish_steps = 1;
+  o->polish_steps = 0;
   o->seed = 0;
   o->lanczos_vectors = 8;
   o->lanczos_steps = 64;

@@ -57,6 +57,9 @@ struct Gemm {
   double* ws = nullptr; int64_t ws_doubles = 0;
   int splitk = 1;        // set by dgemm(); callers leave it at 1
   bool f32 = false;      // FP32 matrix cores (operands rounded to FP32, FP64 epilogue)
+  // with f32: A and B are stored as FP32 (the pointers hold floats, leading
+  // dimensions in floats), read at half the bytes; C stays FP64
+  bool in32 = false;
   // alpha = dscal[ia] and beta = dscal[ib] (device memory) when set, so a
   // captured launch sequence can be replayed with new scalars
   const double* dscal = nullptr; int ia = -1, ib = -1;

@@ -12,6 +12,8 @@ void scale_copy(const double* A, int64_t lda, double* X, int64_t ldx, int64_t ro
 void stacked(const double* X, int64_t ldx, double* W, int64_t ldw, int64_t m, int64_t n, double sc,
              hipStream_t st, const double* dsc = nullptr);
 void symmetrize(double* X, int64_t n, int64_t ld, hipStream_t st);
+// Y (m x n, FP32) = X rounded to nearest
+void to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st);
 void half_plus_identity(const double* X, int64_t ldx, double* B, int64_t ldb, int64_t n, hipStream_t st);
 void diagonal(const double* A, int64_t lda, int64_t n, double* d, hipStream_t st);
 void upper_copy(const double* A, int64_t lda, double* R, int64_t ldr, int64_t n, hipStream_t st);

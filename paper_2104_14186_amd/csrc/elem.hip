@@ -88,6 +88,12 @@ __global__ void half_plus_i_kernel(const double* X, int64_t ldx, double* B, int6
     if (i < n) B[i + j * ldb] = 0.5 * (X[i + j * ldx] + (i == j ? 1.0 : 0.0));
 }
 
+__global__ void to_f32_kernel(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y)
+    if (i < m) Y[i + j * ldy] = (float)X[i + j * ldx];
+}
+
 __global__ void diag_kernel(const double* A, int64_t lda, int64_t n, double* d) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) d[i] = A[i + i * lda];
@@ -169,6 +175,11 @@ void stacked(const double* X, int64_t ldx, double* W, int64_t ldw, int64_t m, in
 void symmetrize(double* X, int64_t n, int64_t ld, hipStream_t st) {
   const unsigned t = (unsigned)cdiv(n, TT);
   symmetrize_kernel<<<dim3(t, t), 256, 0, st>>>(X, n, ld);
+  QDWHP_LAUNCH_CHECK();
+}
+void to_f32(const double* X, int64_t ldx, float* Y, int64_t ldy, int64_t m, int64_t n, hipStream_t st) {
+  if (m <= 0 || n <= 0) return;
+  to_f32_kernel<<<grid2(m, n), 256, 0, st>>>(X, ldx, Y, ldy, m, n);
   QDWHP_LAUNCH_CHECK();
 }
 void half_plus_identity(const double* X, int64_t ldx, double* B, int64_t ldb, int64_t n, hipStream_t st) {

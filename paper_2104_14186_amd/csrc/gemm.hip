@@ -5,9 +5,10 @@
 // v_mfma_f32_16x16x4f32 (the mixed-precision variant) takes the same operand
 // layout but holds D[4(l/16) + r][l%16].
 //
-// Mixed precision (Gemm::f32): operands stay FP64 in HBM and are rounded to
-// FP32 when staged into LDS; products accumulate in FP32 on the FP32 matrix
-// cores (twice the FP64 rate); alpha, beta, the C term and the diagonal shift
+// Mixed precision (Gemm::f32): operands are rounded to FP32 when staged into
+// LDS, or (Gemm::in32) are FP32 copies in HBM read at half the bytes;
+// products accumulate in FP32 on the FP32 matrix cores (twice the FP64 rate),
+// folded into FP64 every 32 k; alpha, beta, the C term and the diagonal shift
 // are applied in FP64.
 //
 // Column-major operands.  One 256-thread workgroup (4 wave64s in a 2x2
@@ -93,7 +94,7 @@ __device__ inline void tile_of(int64_t w, int64_t gx, int64_t gy, bool upper, in
 
 // One BT x BT output tile (tm, tn) of problem g (BT = 128 or 64); zi is the batch index, or
 // the K share when g.splitk > 1.  As / Bs are the workgroup's LDS buffers.
-template <bool TA, bool TB, bool F32, int BT>
+template <bool TA, bool TB, bool F32, int BT, bool IN32 = false>
 __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn, int64_t zi,
                                           typename MfmaT<F32>::elem (*As)[BK * (BT + PAD)],
                                           typename MfmaT<F32>::elem (*Bs)[BK * (BT + PAD)]) {
@@ -110,8 +111,9 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   const int64_t col0 = tn * TN;
   const bool split = g.splitk > 1;
   const int64_t bz = split ? 0 : zi;
-  const double* __restrict__ A = g.A + bz * g.sA;
-  const double* __restrict__ B = g.B + bz * g.sB;
+  constexpr int ES = IN32 ? 4 : 8;      // bytes per stored operand element
+  const char* __restrict__ A = (const char*)g.A + bz * g.sA * ES;
+  const char* __restrict__ B = (const char*)g.B + bz * g.sB * ES;
   double* C = g.C + bz * g.sC;
   const double* Cin = g.Cin ? g.Cin + bz * g.sCin : C;
   const int64_t ldcin = g.Cin ? g.ldcin : g.ldc;
@@ -164,21 +166,24 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
   uint32_t aoff[TNLD], boff[TNLD];
 #pragma unroll
   for (int r = 0; r < TNLD; ++r) {
-    aoff[r] = TA ? (uint32_t)((ak + (int64_t)(am + 16 * r) * lda) * 8)
-                 : (uint32_t)((am + (int64_t)(ak + KS * r) * lda) * 8);
-    boff[r] = TB ? (uint32_t)((bn + (int64_t)(bk + KS * r) * ldb) * 8)
-                 : (uint32_t)((bk + (int64_t)(bn + 16 * r) * ldb) * 8);
+    aoff[r] = TA ? (uint32_t)((ak + (int64_t)(am + 16 * r) * lda) * ES)
+                 : (uint32_t)((am + (int64_t)(ak + KS * r) * lda) * ES);
+    boff[r] = TB ? (uint32_t)((bn + (int64_t)(bk + KS * r) * ldb) * ES)
+                 : (uint32_t)((bk + (int64_t)(bn + 16 * r) * ldb) * ES);
   }
   auto slice_a = [&](int64_t k0) {
-    const double* p = TA ? A + row0 * lda + k0 : A + k0 * lda + row0;
+    const char* p = A + (TA ? row0 * lda + k0 : k0 * lda + row0) * ES;
     return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)RECORDS, 0x00020000);
   };
   auto slice_b = [&](int64_t k0) {
-    const double* p = TB ? B + k0 * ldb + col0 : B + col0 * ldb + k0;
+    const char* p = B + (TB ? k0 * ldb + col0 : col0 * ldb + k0) * ES;
     return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)RECORDS, 0x00020000);
   };
-  auto ld = [](__amdgpu_buffer_rsrc_t rs, uint32_t off) -> double {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+  auto ld = [](__amdgpu_buffer_rsrc_t rs, uint32_t off) -> E {
+    if constexpr (IN32)
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+    else
+      return (E)__builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
   };
 
   ACC acc[WT][WT];
@@ -202,9 +207,9 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
     const __amdgpu_buffer_rsrc_t rsa = slice_a(k0), rsb = slice_b(k0);
     if (interior && k0 + BK <= khi && mask_free(k0)) {
 #pragma unroll
-      for (int r = 0; r < TNLD; ++r) ra[r] = (E)ld(rsa, aoff[r]);
+      for (int r = 0; r < TNLD; ++r) ra[r] = ld(rsa, aoff[r]);
 #pragma unroll
-      for (int r = 0; r < TNLD; ++r) rb[r] = (E)ld(rsb, boff[r]);
+      for (int r = 0; r < TNLD; ++r) rb[r] = ld(rsb, boff[r]);
       return;
     }
 #pragma unroll
@@ -213,9 +218,9 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       const int64_t sr = TA ? k : m, sc = TA ? m : k;   // stored (row, col)
       const bool in = m < M && k >= klo && k < khi;
       const bool take = in && (!aul || sr > sc);
-      double v = ld(rsa, take ? aoff[r] : OOB);
-      if (aul && in && sr == sc) v = 1.0;
-      ra[r] = (E)v;
+      E v = ld(rsa, take ? aoff[r] : OOB);
+      if (aul && in && sr == sc) v = (E)1.0;
+      ra[r] = v;
     }
 #pragma unroll
     for (int r = 0; r < TNLD; ++r) {
@@ -223,9 +228,9 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       const int64_t sr = TB ? n : k, sc = TB ? k : n;
       const bool in = n < N && k >= klo && k < khi;
       const bool take = in && (!bul || sr > sc);
-      double v = ld(rsb, take ? boff[r] : OOB);
-      if (bul && in && sr == sc) v = 1.0;
-      rb[r] = (E)v;
+      E v = ld(rsb, take ? boff[r] : OOB);
+      if (bul && in && sr == sc) v = (E)1.0;
+      rb[r] = v;
     }
   };
   auto store = [&](int buf) {
@@ -316,7 +321,7 @@ __device__ __forceinline__ void gemm_tile(const Gemm& g, int64_t tm, int64_t tn,
       }
 }
 
-template <bool TA, bool TB, bool F32, int BT>
+template <bool TA, bool TB, bool F32, int BT, bool IN32 = false>
 __global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(Gemm g, int64_t gx, int64_t gy) {
   __shared__ typename MfmaT<F32>::elem As[2][BK * (BT + PAD)];
   __shared__ typename MfmaT<F32>::elem Bs[2][BK * (BT + PAD)];
@@ -329,7 +334,7 @@ __global__ __launch_bounds__(256, (F32 && BT == 128) ? 1 : 2) void dgemm_kernel(
                         ? ((g.klo == KLO_COL) ? 1 : (g.khi == KHI_COL ? -1 : 0))
                         : ((g.klo == KLO_ROW) ? 1 : ((g.khi == KHI_ROW || g.khi == KHI_COL) ? -1 : 0));
   tile_of(blockIdx.x, gx, gy, g.tiles == TILES_UPPER, order, &tm, &tn);
-  gemm_tile<TA, TB, F32, BT>(g, tm, tn, blockIdx.z, As, Bs);
+  gemm_tile<TA, TB, F32, BT, IN32>(g, tm, tn, blockIdx.z, As, Bs);
 }
 
 // Persistent launch over a ragged list of FP64 problems (same transposes):
@@ -457,11 +462,16 @@ static void launch_tiles(const Gemm& g, int64_t tm, int64_t tn, hipStream_t s) {
     else if (!g.ta && g.tb) dgemm_kernel<false, true, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
     else if (g.ta && !g.tb) dgemm_kernel<true, false, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
     else dgemm_kernel<true, true, false, BT><<<grid, block, 0, s>>>(g, tm, tn);
-  } else {
+  } else if (!g.in32) {
     if (!g.ta && !g.tb) dgemm_kernel<false, false, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
     else if (!g.ta && g.tb) dgemm_kernel<false, true, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
     else if (g.ta && !g.tb) dgemm_kernel<true, false, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
     else dgemm_kernel<true, true, true, BT><<<grid, block, 0, s>>>(g, tm, tn);
+  } else {
+    if (!g.ta && !g.tb) dgemm_kernel<false, false, true, BT, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (!g.ta && g.tb) dgemm_kernel<false, true, true, BT, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else if (g.ta && !g.tb) dgemm_kernel<true, false, true, BT, true><<<grid, block, 0, s>>>(g, tm, tn);
+    else dgemm_kernel<true, true, true, BT, true><<<grid, block, 0, s>>>(g, tm, tn);
   }
 }
 

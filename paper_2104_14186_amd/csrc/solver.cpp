@@ -86,7 +86,8 @@ int lz_vectors(const qdwhp_opts& o) { return o.lanczos_vectors > 0 ? std::min(o.
 // DWH steps on X (m x n, ld m).  X and Xn are exchanged by the Cholesky step.
 struct StepBufs {
   double* Z;        // n x n
-  double* spd;      // spd_inverse_doubles(n)
+  double* spd;      // spd_inverse_doubles(n), then the step's product and FP32 staging
+  int64_t spd_doubles = 0;   // size of that region (0: unknown, no FP32 staging)
   double* W;        // (m + n) x n stacked matrix
   double* Q;        // (m + n) x n thin Q
   double* tau;      // m + n
@@ -114,27 +115,41 @@ void step_params(double a, double b, double c, double* out) {
   out[5] = out[6] = out[7] = 0.0;
 }
 
+// f32 with room for it: the operands are first rounded into FP32 copies
+// (X, W^{-1}, then the product X W^{-1}), so the FP32 products read half the
+// bytes of FP64 operands; the products' results stay FP64.
 void chol_step(double*& X, double*& Xn, int64_t m, int64_t n, double a, double b, double c, bool sym,
                const StepBufs& B, hipStream_t s, bool f32 = false, const double* dw = nullptr) {
+  const double* Wi = B.spd;
+  double* T = B.spd + spd_inverse_doubles(n);
+  // FP32 staging after T: X32 (m x n), T32 (m x n), W32 (n x n) floats
+  float* X32 = (float*)(T + m * n);
+  float* T32 = X32 + m * n;
+  float* W32 = T32 + m * n;
+  const bool staged = f32 && B.spd_doubles > 0 &&
+                      spd_inverse_doubles(n) + m * n + (2 * m * n + n * n + 1) / 2 <= B.spd_doubles;
+  if (staged) to_f32(X, m, X32, m, m, n, s);
   Gemm g;
-  g.f32 = f32;
+  g.f32 = f32; g.in32 = staged;
   g.M = n; g.N = n; g.K = m; g.alpha = c; g.beta = 0.0; g.diag = 1.0;
   if (dw) { g.dscal = dw; g.ia = 0; }
-  g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.Z; g.ldc = n;
+  g.A = staged ? (const double*)X32 : X; g.lda = m; g.ta = true; g.B = g.A; g.ldb = m; g.C = B.Z; g.ldc = n;
   g.tiles = TILES_UPPER;
   dgemm(g, s);
   chol_inverse_factor(B.Z, n, n, B.spd, B.flag, s);
-  const double* Wi = B.spd;
-  double* T = B.spd + spd_inverse_doubles(n);
+  if (staged) to_f32(Wi, n, W32, n, n, n, s);
   Gemm t;
-  t.f32 = f32;
-  t.M = m; t.N = n; t.K = n; t.A = X; t.lda = m; t.B = Wi; t.ldb = n; t.C = T; t.ldc = m;
+  t.f32 = f32; t.in32 = staged;
+  t.M = m; t.N = n; t.K = n; t.A = staged ? (const double*)X32 : X; t.lda = m;
+  t.B = staged ? (const double*)W32 : Wi; t.ldb = n; t.C = T; t.ldc = m;
   t.khi = KHI_COL;
   dgemm(t, s);
+  if (staged) to_f32(T, m, T32, m, m, n, s);
   Gemm u;
-  u.f32 = f32;
+  u.f32 = f32; u.in32 = staged;
   u.M = m; u.N = n; u.K = n; u.alpha = a - b / c; u.beta = b / c;
-  u.A = T; u.lda = m; u.B = Wi; u.ldb = n; u.tb = true; u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
+  u.A = staged ? (const double*)T32 : T; u.lda = m; u.B = staged ? (const double*)W32 : Wi; u.ldb = n;
+  u.tb = true; u.C = Xn; u.ldc = m; u.Cin = X; u.ldcin = m;
   u.klo = KLO_COL;
   if (dw) { u.dscal = dw; u.ia = 1; u.ib = 2; }
   if (sym) u.tiles = TILES_UPPER;
@@ -211,7 +226,7 @@ Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd) 
 
 StepBufs step_bufs(const Plan& p, int64_t m, int64_t n) {
   StepBufs b;
-  b.Z = p.Z; b.spd = p.big; b.W = p.big; b.Q = p.big + (m + n) * n;
+  b.Z = p.Z; b.spd = p.big; b.spd_doubles = p.big_doubles; b.W = p.big; b.Q = p.big + (m + n) * n;
   b.tau = p.tau; b.Tall = p.Tall; b.qrs = p.qrs; b.flag = p.flags;
   return b;
 }
@@ -266,6 +281,12 @@ PanelWatch diag_watch(double* B, int64_t ldb, double* dbuf, double tol, std::vec
 
 // The DWH steps of a solve, then the FP64 polish plan (0 = Newton-Schulz,
 // 1 = Halley (3,1,3) in Cholesky form) of the mixed-precision variant.
+// Mixed precision runs every Cholesky-based step but the last on the FP32
+// matrix cores; the last step of the schedule stays FP64: its map is flat at
+// 1 (|1 - r(1 + e)| = O(e^3) for l_k near 1), so the O(u_32) errors the
+// low-precision steps leave on the wanted values vanish, while the unwanted
+// values get the same map as in FP64 (the band, hence ell, stays as in FP64;
+// a Newton-Schulz polish would push the band towards 1 and enlarge ell).
 // With opts.graphs the sequence is captured once per (buffers, sizes, step
 // kinds, plan) and replayed with this solve's weights.
 void run_iterations(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, const std::vector<DwhStep>& sched,
@@ -278,7 +299,7 @@ void run_iterations(double*& X, double*& Xn, int64_t m, int64_t n, bool sym, con
       const DwhStep& st = sched[i];
       const double* d = dw ? dw + kStepParams * i : nullptr;
       if (st.kind == 1) qr_step(x, m, n, st.a, st.b, st.c, sym, sb, s, d);
-      else chol_step(x, xn, m, n, st.a, st.b, st.c, sym, sb, s, mixed, d);
+      else chol_step(x, xn, m, n, st.a, st.b, st.c, sym, sb, s, mixed && i + 1 < sched.size(), d);
     }
     for (int p : polish) {
       if (p == 0) ns_step(x, xn, m, n, sym, sb, s);
