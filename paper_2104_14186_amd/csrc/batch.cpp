@@ -1,19 +1,23 @@
-// Ragged batches of independent EIG / SVD problems.
+// Ragged batches of independent EIG / SVD problems, in three phases.
 //
-// A batch of uneven sizes runs on `lanes` concurrent HIP streams, each fed
-// by a host thread that takes the next instance (largest first) and drives
-// its solve on the lane's stream with the instance's own slice of the
-// workspace.  The solves of small instances are latency-bound (many short
-// launches and a few host round trips), so instances on different lanes
-// overlap on the device.  The last matrix product of every instance
-// (V = Q2 W_k, or V = Q2 V~_k for SVD) is deferred and all of them run in
-// one persistent ragged GEMM launch on the caller's stream, followed by the
-// sign steps.
+//  1. setup (estimator, threshold, schedule, X0) on `lanes` concurrent HIP
+//     streams, each fed by a host thread that takes the next instance
+//     (largest first), with the instance's own slice of the workspace;
+//  2. the DWH iterations, instances of one shape (type, rows, columns)
+//     together: step i of every member whose step i is Cholesky-based runs as
+//     one grouped Gram, one lockstep Cholesky-inversion (each leaf one launch
+//     for all members, each product one grouped GEMM) and two grouped
+//     triangular products, each a persistent launch over the members'
+//     tiles; the shape groups are spread over the lanes ("batch.grouped" = 0
+//     runs each instance's own steps on its lane instead);
+//  3. projector QR, subspace and Rayleigh-Ritz on the lanes again; the last
+//     product of every instance (V = Q2 W_k, or V = Q2 V~_k for SVD) runs in
+//     one persistent ragged GEMM launch, followed by the sign steps.
 //
-// Each instance computes exactly what a standalone qdwhp_eig / qdwhp_svd call
-// computes: the same kernels with the same launch shapes (no choice depends
-// on the batch composition) and no atomics whose order could vary, so the
-// results are bitwise identical.
+// Every grouped launch performs each member's operations exactly as its
+// standalone call would (same recursion, same tile arithmetic, no atomics),
+// so each instance computes bitwise what a standalone qdwhp_eig / qdwhp_svd
+// call computes, whatever else is in the batch.
 #include <algorithm>
 #include <atomic>
 #include <cstring>
@@ -89,7 +93,9 @@ extern "C" size_t qdwhp_batched_workspace(int count, const qdwhp_problem* probs,
     if (b == 0) return 0;
     total += align256(b);
   }
-  return total + align256(grouped_table_bytes(count));
+  // the final grouped product's table, then one table slice per instance
+  // for the shape groups of phase 2
+  return total + align256(grouped_table_bytes(count)) + (size_t)count * grouped_table_bytes(1);
 }
 
 extern "C" int qdwhp_batched(int count, const qdwhp_problem* probs, void* work, size_t lwork,
@@ -111,47 +117,113 @@ extern "C" int qdwhp_batched(int count, const qdwhp_problem* probs, void* work, 
   std::vector<qdwhp_info> inf(count);
   std::vector<int> st(count, QDWHP_OK);
   std::vector<Deferred> df(count);
+  std::vector<SolveState*> S(count, nullptr);
   std::vector<int> order(count);
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return problem_cost(probs[a]) > problem_cost(probs[b]); });
   const int L = std::min(lanes > 0 ? lanes : default_lanes(count), count);
+  const bool grouped = qdwhp_tune_get("batch.grouped", 1) != 0;
   int dev = 0;
   int rc = QDWHP_OK;
   std::vector<hipEvent_t> evs;
+  auto event = [&]() {
+    hipEvent_t e;
+    QDWHP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    evs.push_back(e);
+    return e;
+  };
   try {
     QDWHP_HIP(hipGetDevice(&dev));
-    hipEvent_t start;
-    QDWHP_HIP(hipEventCreateWithFlags(&start, hipEventDisableTiming));
-    evs.push_back(start);
+    hipEvent_t start = event();
     QDWHP_HIP(hipEventRecord(start, s));
     std::vector<hipStream_t> ls(L);
     for (int l = 0; l < L; ++l) {
       ls[l] = lane_stream(dev, l);
       QDWHP_HIP(hipStreamWaitEvent(ls[l], start, 0));
     }
-    std::atomic<int> next(0);
     std::vector<int> lane_err(L, QDWHP_OK);
-    auto lane = [&](int l) {
-      if (hipSetDevice(dev) != hipSuccess) { lane_err[l] = QDWHP_ERR_HIP; return; }
-      for (int j; (j = next.fetch_add(1)) < count;) {
-        const int i = order[j];
-        st[i] = run_problem(probs[i], (char*)work + off[i], align256(problem_workspace(probs[i], opts)),
-                            opts, ls[l], &inf[i], &df[i]);
+    // Runs phase(i, lane stream) for every instance on the lanes (host
+    // threads take the next instance, largest first).
+    auto on_lanes = [&](auto phase) {
+      std::atomic<int> next(0);
+      auto lane = [&](int l) {
+        if (hipSetDevice(dev) != hipSuccess) { lane_err[l] = QDWHP_ERR_HIP; return; }
+        for (int j; (j = next.fetch_add(1)) < count;) phase(order[j], ls[l]);
+      };
+      std::vector<std::thread> th;
+      for (int l = 1; l < L; ++l) th.emplace_back(lane, l);
+      lane(0);
+      for (auto& t : th) t.join();
+      for (int l = 0; l < L; ++l)
+        if (lane_err[l] != QDWHP_OK) throw HipError{hipErrorUnknown};
+    };
+    auto join_into = [&](hipStream_t to) {
+      for (int l = 0; l < L; ++l) {
+        hipEvent_t e = event();
+        QDWHP_HIP(hipEventRecord(e, ls[l]));
+        QDWHP_HIP(hipStreamWaitEvent(to, e, 0));
       }
     };
-    std::vector<std::thread> th;
-    for (int l = 1; l < L; ++l) th.emplace_back(lane, l);
-    lane(0);
-    for (auto& t : th) t.join();
-    for (int l = 0; l < L; ++l) {
-      if (lane_err[l] != QDWHP_OK) throw HipError{hipErrorUnknown};
-      hipEvent_t e;
-      QDWHP_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-      evs.push_back(e);
-      QDWHP_HIP(hipEventRecord(e, ls[l]));
-      QDWHP_HIP(hipStreamWaitEvent(s, e, 0));
+    // phase 1: setup (estimator, threshold, schedule, X0)
+    on_lanes([&](int i, hipStream_t ls_) {
+      S[i] = solve_create(probs[i], (char*)work + off[i], align256(problem_workspace(probs[i], opts)), opts,
+                          ls_, &inf[i], &df[i]);
+      st[i] = solve_setup(S[i]);
+    });
+    // every lane waits for every other lane's setups
+    auto cross_join = [&]() {
+      std::vector<hipEvent_t> e(L);
+      for (int l = 0; l < L; ++l) { e[l] = event(); QDWHP_HIP(hipEventRecord(e[l], ls[l])); }
+      for (int l = 0; l < L; ++l)
+        for (int j = 0; j < L; ++j)
+          if (j != l) QDWHP_HIP(hipStreamWaitEvent(ls[l], e[j], 0));
+    };
+    // phase 2: the DWH iterations, one grouped run per shape (instances of
+    // equal type and size share every launch), the groups spread over the lanes
+    if (grouped) {
+      cross_join();
+      std::map<int64_t, std::vector<int>> by_shape;
+      for (int j = 0; j < count; ++j)
+        if (st[order[j]] == QDWHP_OK) by_shape[solve_shape(S[order[j]])].push_back(order[j]);
+      std::vector<std::vector<int>> groups;
+      for (auto& kv : by_shape) groups.push_back(kv.second);
+      std::stable_sort(groups.begin(), groups.end(), [&](const std::vector<int>& a, const std::vector<int>& b) {
+        return problem_cost(probs[a[0]]) * a.size() > problem_cost(probs[b[0]]) * b.size();
+      });
+      std::vector<size_t> toff(groups.size());
+      size_t t = 0;
+      for (size_t gi = 0; gi < groups.size(); ++gi) { toff[gi] = t; t += grouped_table_bytes((int)groups[gi].size()); }
+      char* tables = (char*)table + align256(grouped_table_bytes(count));
+      std::atomic<int> next(0);
+      auto lane = [&](int l) {
+        if (hipSetDevice(dev) != hipSuccess) { lane_err[l] = QDWHP_ERR_HIP; return; }
+        try {
+          for (int gi; (gi = next.fetch_add(1)) < (int)groups.size();) {
+            std::vector<SolveState*> v;
+            for (int i : groups[gi]) v.push_back(S[i]);
+            iterations_grouped(v.data(), (int)v.size(), tables + toff[gi], ls[l]);
+          }
+        } catch (const HipError&) {
+          lane_err[l] = QDWHP_ERR_HIP;
+        }
+      };
+      std::vector<std::thread> th;
+      for (int l = 1; l < L; ++l) th.emplace_back(lane, l);
+      lane(0);
+      for (auto& x : th) x.join();
+      for (int l = 0; l < L; ++l)
+        if (lane_err[l] != QDWHP_OK) throw HipError{hipErrorUnknown};
+      cross_join();
     }
+    // phase 3: projector, subspace, Rayleigh-Ritz (and phase 2 per lane when not grouped)
+    on_lanes([&](int i, hipStream_t ls_) {
+      if (st[i] != QDWHP_OK) return;
+      solve_set_stream(S[i], ls_);
+      if (!grouped) st[i] = solve_iterate(S[i]);
+      if (st[i] == QDWHP_OK) st[i] = solve_finish(S[i]);
+    });
+    join_into(s);
     // deferred products of every successful instance: one ragged launch
     std::vector<GroupedDesc> gd;
     std::vector<int> who;
@@ -169,6 +241,9 @@ extern "C" int qdwhp_batched(int count, const qdwhp_problem* probs, void* work, 
   } catch (const HipError&) {
     rc = QDWHP_ERR_HIP;
   }
+  // the states are released once their work has drained
+  (void)hipStreamSynchronize(s);
+  for (auto* p : S) if (p) solve_destroy(p);
   for (auto e : evs) (void)hipEventDestroy(e);
   for (int i = 0; i < count; ++i) {
     if (infos) infos[i] = inf[i];

@@ -357,9 +357,18 @@ __global__ __launch_bounds__(256, 2) void dgemm_grouped_kernel(const GroupedDesc
     Gemm g;
     g.M = d.M; g.N = d.N; g.K = d.K; g.alpha = d.alpha; g.beta = d.beta;
     g.A = d.A; g.lda = d.lda; g.ta = TA; g.B = d.B; g.ldb = d.ldb; g.tb = TB; g.C = d.C; g.ldc = d.ldc;
+    g.diag = d.diag; g.Cin = d.Cin; g.ldcin = d.ldcin; g.klo = d.klo; g.khi = d.khi; g.tiles = d.tiles;
     const int64_t local = t - first[lo];
     const int64_t gx = (g.M + BM - 1) / BM;
-    gemm_tile<TA, TB, false, 128>(g, local % gx, local / gx, 0, As, Bs);
+    int64_t tm = local % gx, tn = local / gx;
+    if (d.tiles == TILES_UPPER) {   // column c holds tiles 0..c: local = c (c + 1) / 2 + tm
+      int64_t c = (int64_t)((sqrt(8.0 * (double)local + 1.0) - 1.0) / 2.0);
+      while (c * (c + 1) / 2 > local) --c;
+      while ((c + 1) * (c + 2) / 2 <= local) ++c;
+      tn = c;
+      tm = local - c * (c + 1) / 2;
+    }
+    gemm_tile<TA, TB, false, 128>(g, tm, tn, 0, As, Bs);
     __syncthreads();
   }
 }
@@ -539,9 +548,11 @@ void dgemm_grouped(const GroupedDesc* descs, int count, bool ta, bool tb, void* 
     for (int i = 0; i < c.count; ++i) {
       const GroupedDesc& d = descs[base + i];
       if (d.lda >= (int64_t(1) << 21) || d.ldb >= (int64_t(1) << 21)) throw HipError{hipErrorInvalidValue};
+      if (d.tiles == TILES_UPPER && d.M != d.N) throw HipError{hipErrorInvalidValue};
       c.d[i] = d;
       c.first[i] = run;
-      if (d.M > 0 && d.N > 0) run += cdiv(d.M, BM) * cdiv(d.N, BN);
+      if (d.M > 0 && d.N > 0)
+        run += (d.tiles == TILES_UPPER) ? cdiv(d.M, BM) * (cdiv(d.M, BM) + 1) / 2 : cdiv(d.M, BM) * cdiv(d.N, BN);
     }
     c.first[c.count] = run;
     desc_write_kernel<<<1, 64, 0, s>>>(dt, first, c, count);

@@ -16,7 +16,11 @@
 //      inverted by one wave (rows in registers, broadcasts through LDS);
 //   2. Z^{-1} = W^{-1} W^{-T}, upper tiles only, K starting at the tile column;
 //   3. mirror the upper triangle.
+#include <algorithm>
+#include <vector>
+
 #include "common.h"
+#include "drivers.h"
 
 namespace qdwhp {
 namespace {
@@ -39,8 +43,7 @@ constexpr int NB = 64;
 //   M_kj = (delta_kj - sum_{i<k} L_ki M_ij) / L_kk, the row L_k,0..k-1 read
 //   as a broadcast from LDS; W^{-1} = M^T is written column by column.
 constexpr int LW = 64;   // lanes of the leaf wave
-__global__ __launch_bounds__(LW) void chol_inv_leaf(double* Z, int64_t ldz, double* Wi, int64_t ldw,
-                                                    int bs, int* flag) {
+__device__ __forceinline__ void leaf_body(double* Z, int64_t ldz, double* Wi, int64_t ldw, int bs, int* flag) {
   __shared__ double S[NB][NB + 1];     // S[r][c]: the input, then L, then M^T
   __shared__ double colbuf[2][NB];
   const int i = threadIdx.x;
@@ -120,6 +123,32 @@ __global__ __launch_bounds__(LW) void chol_inv_leaf(double* Z, int64_t ldz, doub
   }
 }
 
+__global__ __launch_bounds__(LW) void chol_inv_leaf(double* Z, int64_t ldz, double* Wi, int64_t ldw,
+                                                    int bs, int* flag) {
+  leaf_body(Z, ldz, Wi, ldw, bs, flag);
+}
+
+// The diagonal leaves of up to LEAF_CHUNK matrices of a batch, one wave each.
+constexpr int LEAF_CHUNK = 32;
+struct LeafDesc { double* Z; int64_t ldz; double* Wi; int64_t ldw; int* flag; int bs; };
+struct LeafChunk { LeafDesc d[LEAF_CHUNK]; };
+__global__ __launch_bounds__(LW) void chol_inv_leaf_batched(LeafChunk c) {
+  const LeafDesc d = c.d[blockIdx.x];
+  leaf_body(d.Z, d.ldz, d.Wi, d.ldw, d.bs, d.flag);
+}
+
+// dst (rows x cols, ldd) = src (ld lds) for up to LEAF_CHUNK matrices.
+struct CopyDesc { const double* src; int64_t lds; double* dst; int64_t ldd; int64_t rows, cols; };
+struct CopyChunk { CopyDesc d[LEAF_CHUNK]; };
+__global__ void copy_batched_kernel(CopyChunk c) {
+  const CopyDesc d = c.d[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (int64_t q = e; q < d.rows * d.cols; q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = q % d.rows, col = q / d.rows;
+    d.dst[r + col * d.ldd] = d.src[r + col * d.lds];
+  }
+}
+
 struct Rec {
   double* Z; int64_t ldz; double* Wi; int64_t ldw; double* T; int* flag; hipStream_t s;
 
@@ -179,6 +208,90 @@ void chol_inverse_factor(double* Z, int64_t n, int64_t ldz, double* work, int* f
   double* T = work + n * n;
   fill(Wi, n, n, n, 0.0, 0.0, s);
   Rec r{Z, ldz, Wi, n, T, flag, s};
+  r.run(0, n);
+}
+
+namespace {
+
+// chol_inverse_factor's recursion (Rec::run) for several matrices of one size
+// at once: the same operations in the same order, each leaf one launch over
+// the matrices (chunks of LEAF_CHUNK) and each product one grouped GEMM.
+struct GroupRec {
+  const CholItem* it; int count; int64_t n; void* table; hipStream_t s;
+  std::vector<GroupedDesc> d;
+
+  void run(int64_t o, int64_t m) {
+    if (m <= NB) {
+      for (int c0 = 0; c0 < count; c0 += LEAF_CHUNK) {
+        LeafChunk lc;
+        const int cnt = std::min(LEAF_CHUNK, count - c0);
+        for (int q = 0; q < cnt; ++q) {
+          const CholItem& x = it[c0 + q];
+          lc.d[q] = LeafDesc{x.Z + o + o * x.ldz, x.ldz, x.work + o + o * n, n, x.flag, (int)m};
+        }
+        chol_inv_leaf_batched<<<cnt, LW, 0, s>>>(lc);
+        QDWHP_LAUNCH_CHECK();
+      }
+      return;
+    }
+    const int64_t nblk = cdiv(m, NB);
+    const int64_t n1 = NB * cdiv(nblk, 2), n2 = m - n1;
+    run(o, n1);
+    auto each = [&](auto make) {
+      d.clear();
+      for (int q = 0; q < count; ++q) d.push_back(make(it[q]));
+    };
+    // T = W11^{-T} Z12
+    each([&](const CholItem& x) {
+      GroupedDesc g{n1, n2, n1, 1.0, 0.0, x.work + o + o * n, n, x.Z + o + (o + n1) * x.ldz, x.ldz,
+                    x.work + n * n, n1};
+      g.khi = KHI_ROW;
+      return g;
+    });
+    dgemm_grouped(d.data(), count, true, false, table, s);
+    for (int c0 = 0; c0 < count; c0 += LEAF_CHUNK) {   // Z12 <- W12
+      CopyChunk cc;
+      const int cnt = std::min(LEAF_CHUNK, count - c0);
+      for (int q = 0; q < cnt; ++q) {
+        const CholItem& x = it[c0 + q];
+        cc.d[q] = CopyDesc{x.work + n * n, n1, x.Z + o + (o + n1) * x.ldz, x.ldz, n1, n2};
+      }
+      copy_batched_kernel<<<dim3((unsigned)std::min<int64_t>(cdiv(n1 * n2, 256), 1024), cnt), 256, 0, s>>>(cc);
+      QDWHP_LAUNCH_CHECK();
+    }
+    // Z22 <- Z22 - W12^T W12 (upper tiles)
+    each([&](const CholItem& x) {
+      GroupedDesc g{n2, n2, n1, -1.0, 1.0, x.Z + o + (o + n1) * x.ldz, x.ldz, x.Z + o + (o + n1) * x.ldz, x.ldz,
+                    x.Z + (o + n1) + (o + n1) * x.ldz, x.ldz};
+      g.tiles = TILES_UPPER;
+      return g;
+    });
+    dgemm_grouped(d.data(), count, true, false, table, s);
+    run(o + n1, n2);
+    // T = W12 W22^{-1}
+    each([&](const CholItem& x) {
+      GroupedDesc g{n1, n2, n2, 1.0, 0.0, x.Z + o + (o + n1) * x.ldz, x.ldz, x.work + (o + n1) + (o + n1) * n, n,
+                    x.work + n * n, n1};
+      g.khi = KHI_COL;
+      return g;
+    });
+    dgemm_grouped(d.data(), count, false, false, table, s);
+    // W^{-1}_{12} = -W11^{-1} T
+    each([&](const CholItem& x) {
+      GroupedDesc g{n1, n2, n1, -1.0, 0.0, x.work + o + o * n, n, x.work + n * n, n1, x.work + o + (o + n1) * n, n};
+      g.klo = KLO_ROW;
+      return g;
+    });
+    dgemm_grouped(d.data(), count, false, false, table, s);
+  }
+};
+
+}  // namespace
+
+void chol_inverse_grouped(const CholItem* items, int count, int64_t n, void* table, hipStream_t s) {
+  if (count <= 0 || n <= 0) return;
+  for (int q = 0; q < count; ++q) fill(items[q].work, n, n, n, 0.0, 0.0, s);
+  GroupRec r{items, count, n, table, s, {}};
   r.run(0, n);
 }
 

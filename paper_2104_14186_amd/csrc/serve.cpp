@@ -1,17 +1,25 @@
 // Continuous-batching request server for EIG / SVD solves.
 //
-// Requests enter a FIFO.  A request is admitted when a lane is idle and its
+// Requests enter a FIFO.  A request is admitted when a lane is free and its
 // workspace (the library's own size query, i.e. its HBM footprint) fits in
 // a free range of the server's arena; lanes are host threads, each with its
-// own HIP stream, so admitted requests run concurrently and their kernels
-// overlap on the device.  Requests that arrive while others run are admitted
-// as lanes and memory free up; the head of the queue is never overtaken, so
-// a large request cannot starve.  Iteration state lives in the request's
-// arena range on the device for the whole solve.
+// own HIP stream.  An admitted request goes through the three phases of a
+// solve, each taken by whichever lane is free: its setup (estimator,
+// threshold, schedule, X0); its DWH iterations, together with every other
+// request of the same shape waiting at that point (grouped Gram, lockstep
+// Cholesky-inversion and grouped triangular products: one persistent launch
+// per phase for the whole group); then projector, subspace and Rayleigh-Ritz.
+// Requests that arrive while others run are admitted as lanes and memory free
+// up and join the next group of their shape; the head of the queue is never
+// overtaken, so a large request cannot starve.  Iteration state lives in the
+// request's arena range on the device for the whole solve.  "serve.grouped" =
+// 0 runs every phase of a request on one lane instead.
 //
-// A request computes exactly what a standalone call computes (same kernels,
-// launch shapes independent of what else runs, no order-dependent atomics),
-// so its results do not depend on the mix it was served in.
+// Every grouped launch performs each member's operations exactly as its
+// standalone call would (same kernels and tile arithmetic, no order-dependent
+// atomics), so a request's results do not depend on the mix it was served
+// in: alone, in any mix, or as a standalone call, they are bitwise the same.
+
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -27,8 +35,6 @@
 
 namespace qdwhp {
 size_t problem_workspace(const qdwhp_problem& p, const qdwhp_opts* o);
-int run_problem(const qdwhp_problem& p, void* work, size_t lwork, const qdwhp_opts* o,
-                hipStream_t s, qdwhp_info* info, Deferred* df);
 }  // namespace qdwhp
 
 using namespace qdwhp;
@@ -76,63 +82,148 @@ struct Request {
   qdwhp_info info{};
 };
 
+// An admitted request between its phases.
+struct Active {
+  int64_t id = 0;
+  size_t off = 0, bytes = 0;
+  SolveState* S = nullptr;
+  qdwhp_info info{};
+  hipEvent_t ready = nullptr;    // end of its last phase, on the stream that ran it
+};
+
+constexpr int kMaxGroup = 64;    // requests per grouped iteration launch sequence
+
 }  // namespace
 
 struct qdwhp_server {
   int dev = 0;
   char* arena = nullptr;
-  size_t cap = 0;
+  size_t cap = 0;                // bytes of the arena open to requests
+  char* tables = nullptr;        // one grouped-GEMM descriptor table per lane (end of the arena)
   RangeAlloc alloc{0};
   qdwhp_opts opts;
+  bool grouped = true;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<int64_t> queue;
+  std::deque<int64_t> queue;                 // submitted, not admitted
+  std::deque<Active*> iter_q, fin_q;         // set up / iterated, waiting for the next phase
   std::map<int64_t, Request> reqs;
   int64_t next_id = 1;
   bool stop = false;
-  int running = 0;
+  int running = 0;               // admitted, not finished
   int peak_running = 0;
   size_t in_use = 0, peak_bytes = 0;
   std::vector<std::thread> lanes;
-
   std::vector<hipStream_t> streams;
 
+  // Each lane runs whatever phase is ready, finishing work first: the
+  // subspace and Rayleigh-Ritz phase of an iterated request; else the
+  // iterations of every waiting request with the shape of the oldest one,
+  // as one group; else admission and setup of the next queued request.
   void lane_loop(int l) {
     if (hipSetDevice(dev) != hipSuccess) return;
     hipStream_t s = streams[l];
+    void* table = tables + (size_t)l * grouped_table_bytes(kMaxGroup);
     std::unique_lock<std::mutex> lk(mu);
+    std::vector<Active*> grp;
+    std::vector<SolveState*> sv;
     for (;;) {
-      if (stop && queue.empty()) return;
-      size_t off = 0;
-      if (queue.empty() || !alloc.take(reqs[queue.front()].bytes, &off)) {
-        cv_work.wait(lk);
+      if (!fin_q.empty()) {
+        Active* a = fin_q.front();
+        fin_q.pop_front();
+        lk.unlock();
+        int st = QDWHP_OK;
+        if (hipStreamWaitEvent(s, a->ready, 0) != hipSuccess) st = QDWHP_ERR_HIP;
+        solve_set_stream(a->S, s);
+        if (st == QDWHP_OK) st = solve_finish(a->S);
+        if (hipStreamSynchronize(s) != hipSuccess && st == QDWHP_OK) st = QDWHP_ERR_HIP;
+        lk.lock();
+        complete(a, st);
         continue;
       }
-      const int64_t id = queue.front();
-      queue.pop_front();
-      Request& r = reqs[id];
-      r.t_start = Clock::now();
-      ++running;
-      in_use += r.bytes;
-      peak_bytes = std::max(peak_bytes, in_use);
-      peak_running = std::max(peak_running, running);
-      const qdwhp_problem p = r.p;
-      const size_t bytes = r.bytes;
-      lk.unlock();
-      qdwhp_info info{};
-      int st = run_problem(p, arena + off, bytes, &opts, s, &info, nullptr);
-      if (hipStreamSynchronize(s) != hipSuccess && st == QDWHP_OK) st = QDWHP_ERR_HIP;
-      lk.lock();
-      Request& q = reqs[id];
-      q.t_done = Clock::now();
-      q.status = st;
-      q.info = info;
-      --running;
-      in_use -= bytes;
-      alloc.give(off, bytes);
-      cv_done.notify_all();
-      cv_work.notify_all();
+      if (!iter_q.empty()) {
+        const int64_t shape = solve_shape(iter_q.front()->S);
+        grp.clear();
+        for (auto it = iter_q.begin(); it != iter_q.end() && (int)grp.size() < kMaxGroup;) {
+          if (solve_shape((*it)->S) == shape) { grp.push_back(*it); it = iter_q.erase(it); }
+          else ++it;
+        }
+        lk.unlock();
+        bool ok = true;
+        sv.clear();
+        for (Active* a : grp) {
+          ok = ok && hipStreamWaitEvent(s, a->ready, 0) == hipSuccess;
+          sv.push_back(a->S);
+        }
+        try {
+          if (ok) iterations_grouped(sv.data(), (int)sv.size(), table, s);
+        } catch (const HipError&) {
+          ok = false;
+        }
+        for (Active* a : grp) ok = ok && hipEventRecord(a->ready, s) == hipSuccess;
+        if (!ok) (void)hipStreamSynchronize(s);   // nothing may still run in a range that is given back
+        lk.lock();
+        for (Active* a : grp) {
+          if (ok) fin_q.push_back(a);
+          else complete(a, QDWHP_ERR_HIP);
+        }
+        cv_work.notify_all();
+        continue;
+      }
+      size_t off = 0;
+      if (!queue.empty() && alloc.take(reqs[queue.front()].bytes, &off)) {
+        const int64_t id = queue.front();
+        queue.pop_front();
+        Request& r = reqs[id];
+        r.t_start = Clock::now();
+        ++running;
+        in_use += r.bytes;
+        peak_bytes = std::max(peak_bytes, in_use);
+        peak_running = std::max(peak_running, running);
+        Active* a = new Active();
+        a->id = id; a->off = off; a->bytes = r.bytes;
+        const qdwhp_problem p = r.p;
+        lk.unlock();
+        int st = QDWHP_OK;
+        a->S = solve_create(p, arena + off, a->bytes, &opts, s, &a->info, nullptr);
+        if (hipEventCreateWithFlags(&a->ready, hipEventDisableTiming) != hipSuccess) { a->ready = nullptr; st = QDWHP_ERR_HIP; }
+        if (st == QDWHP_OK) st = solve_setup(a->S);
+        if (st == QDWHP_OK && !grouped) {
+          st = solve_iterate(a->S);
+          if (st == QDWHP_OK) st = solve_finish(a->S);
+          if (hipStreamSynchronize(s) != hipSuccess && st == QDWHP_OK) st = QDWHP_ERR_HIP;
+        } else if (st == QDWHP_OK && hipEventRecord(a->ready, s) != hipSuccess) {
+          st = QDWHP_ERR_HIP;
+        }
+        if (st != QDWHP_OK) (void)hipStreamSynchronize(s);
+        lk.lock();
+        if (st == QDWHP_OK && grouped) {
+          iter_q.push_back(a);
+          cv_work.notify_all();
+        } else {
+          complete(a, st);
+        }
+        continue;
+      }
+      if (stop && queue.empty() && running == 0) return;
+      cv_work.wait(lk);
     }
+  }
+
+  // called with mu held
+  void complete(Active* a, int st) {
+    Request& q = reqs[a->id];
+    q.t_done = Clock::now();
+    q.status = st;
+    q.info = a->info;
+    --running;
+    in_use -= a->bytes;
+    alloc.give(a->off, a->bytes);
+    if (a->S) solve_destroy(a->S);
+    if (a->ready) (void)hipEventDestroy(a->ready);
+    delete a;
+    cv_done.notify_all();
+    cv_work.notify_all();
   }
 };
 
@@ -140,18 +231,21 @@ extern "C" int qdwhp_serve_create(size_t arena_bytes, int lanes, const qdwhp_opt
                                   qdwhp_server** out) {
   if (!out) return -4;
   *out = nullptr;
-  if (arena_bytes == 0) return -1;
   if (lanes < 0) return -2;
+  const int L = lanes > 0 ? lanes : (int)std::max<int64_t>(1, qdwhp_tune_get("serve.lanes", 3));
+  const size_t tbytes = ((size_t)L * grouped_table_bytes(kMaxGroup) + 255) / 256 * 256;
+  if (arena_bytes <= tbytes) return -1;
   auto* srv = new qdwhp_server();
   if (opts) srv->opts = *opts; else qdwhp_opts_default(&srv->opts);
+  srv->grouped = qdwhp_tune_get("serve.grouped", 1) != 0;
   if (hipGetDevice(&srv->dev) != hipSuccess ||
       hipMalloc((void**)&srv->arena, arena_bytes) != hipSuccess) {
     delete srv;
     return QDWHP_ERR_HIP;
   }
-  srv->cap = arena_bytes;
-  srv->alloc = RangeAlloc(arena_bytes);
-  const int L = lanes > 0 ? lanes : (int)std::max<int64_t>(1, qdwhp_tune_get("serve.lanes", 8));
+  srv->cap = (arena_bytes - tbytes) / 256 * 256;
+  srv->tables = srv->arena + srv->cap;
+  srv->alloc = RangeAlloc(srv->cap);
   for (int l = 0; l < L; ++l) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {

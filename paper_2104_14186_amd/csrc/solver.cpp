@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <memory>
 #include <vector>
 
 #include "qdwhp.h"
@@ -543,211 +544,6 @@ extern "C" size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_op
   return ar.off;
 }
 
-int qdwhp::eig_impl(const double* A, int64_t n, int64_t lda, double fraction, int which,
-                   double* w, double* V, int64_t ldv, void* work, size_t lwork,
-                   const qdwhp_opts* opts, void* stream, qdwhp_info* info, Deferred* df) {
-  qdwhp_info dummy;
-  if (!info) info = &dummy;
-  std::memset(info, 0, sizeof(*info));
-  auto ret = [&](int st) { info->status = st; return st; };
-  if (!A) return ret(-1);
-  if (n < 1) return ret(-2);
-  if (lda < n) return ret(-3);
-  if (!(fraction > 0.0) || fraction > 1.0) return ret(-4);
-  if (which != QDWHP_LARGEST && which != QDWHP_SMALLEST) return ret(-5);
-  if (!w) return ret(-6);
-  if (!V) return ret(-7);
-  if (ldv < n) return ret(-8);
-  if (!work) return ret(-9);
-  qdwhp_opts o;
-  if (opts) o = *opts; else qdwhp_opts_default(&o);
-  if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16)
-    return ret(-11);
-  hipStream_t s = (hipStream_t)stream;
-  int64_t k = (int64_t)std::floor(fraction * (double)n + 0.5);
-  k = std::min<int64_t>(n, std::max<int64_t>(1, k));
-  info->k = k;
-  const int nv = lz_vectors(o);
-  const int64_t msteps = lz_steps(o, n);
-  const double sgn = (which == QDWHP_SMALLEST) ? -1.0 : 1.0;
-  try {
-    Arena ar(work, lwork);
-    Plan P = carve(ar, n, n, nv, msteps, false);
-    Events ev(true);
-    ev.mark(0, s);
-    QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
-    nonfinite(A, lda, n, n, P.flags + 1, s);
-    // ---- estimator (Algorithm 1 opens with a few Lanczos steps)
-    const bool replay = !is_nan(o.tau) && !is_nan(o.mu) && !is_nan(o.rho);
-    LanczosResult lz;
-    double lmax = 0.0, lmin = 0.0;
-    if (!replay) {
-      LanczosOp op;
-      op.rows_tmp = 1;
-      op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
-        // the big work block is free until the iterations start
-        skinny_gemm(A, lda, n, n, in, ldi, nv, sgn, out, ldo, P.big, P.big_doubles, st);
-      };
-      lz = lanczos(op, n, nv, (int)msteps, o.seed, P.lz, s);
-      if (lz.sweeps < 0) {   // a non-finite input shows up here first
-        int hf[8];
-        QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-        QDWHP_HIP(hipStreamSynchronize(s));
-        return ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
-      }
-      lmax = -std::numeric_limits<double>::infinity();
-      lmin = std::numeric_limits<double>::infinity();
-      for (size_t i = 0; i < lz.nodes.size(); ++i) {
-        lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
-        lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
-      }
-    }
-    info->lmax = lmax; info->lmin = lmin;
-    ev.mark(1, s);
-    const double sfix = o.s_eig;
-    std::vector<DwhStep> sched;
-    std::vector<double> theta;
-    int64_t ell = 0, ind = 0, n_above = 0;
-    double tau = 0.0, mu = 1.0, rho = 0.0;
-    double* Q2 = nullptr;
-    double* Wv = nullptr;
-    int status = QDWHP_OK;
-    for (int boost = 1; boost <= 2; ++boost) {
-      if (replay) {
-        tau = o.tau; mu = o.mu; rho = o.rho;
-      } else {
-        const double spread = std::max({lmax - lmin, std::fabs(lmax), std::fabs(lmin), 1e-300});
-        if (!is_nan(o.tau)) {
-          tau = sgn * o.tau;
-        } else {
-          double cut;
-          const int64_t kt = target_count(n, k, boost);
-          const bool ok = o.tau_policy == 1
-              ? choose_tau_cost(lz.nodes, lz.weights, n, nv, lmax, lmin, kt, sfix, o.eig_iters, o.kappa_max,
-                                o.tol, &cut)
-              : cut_below(lz.nodes, lz.weights, n, nv, lmax, lmin, kt, &cut);
-          tau = ok ? cut : lmin;
-        }
-        mu = std::max(lmax - tau, 1e-3 * spread);
-        rho = std::max(0.0, (tau - lmin) / mu);
-      }
-      sched = eig_schedule(sfix, rho, o.eig_iters, o.kappa_max);
-      for (size_t i = 0; i < sched.size() && i < 16; ++i)
-        if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) sched[i].kind = o.kinds[i];
-      info->retries = boost - 1;
-      // ---- iterations on the scaled, shifted matrix (Sec. 4.1)
-      double* X = P.X;
-      double* Xn = P.Xn;
-      eig_x0(A, lda, X, n, n, (1.0 - sfix) / mu, tau, sgn, sfix, s);
-      const StepBufs sb = step_bufs(P, n, n);
-      const bool mixed = (o.precision == QDWHP_MIXED_FP32);
-      double xbound = 1.0;
-      for (const auto& st : sched) xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
-      std::vector<int> polish;
-      if (mixed) {
-        // FP64 polish: Newton-Schulz while the unwanted side stays below
-        // sqrt(3) (where it converges), else Halley's (3,1,3) step in
-        // Cholesky form (monotone for any x)
-        for (int p = 0; p < o.polish_steps; ++p) {
-          if (xbound < 1.7) { polish.push_back(0); xbound = std::max(1.0, 0.5 * xbound * (3.0 - xbound * xbound)); }
-          else { polish.push_back(1); xbound = std::max(1.0, dwh_map(xbound, 3.0, 1.0, 3.0)); }
-        }
-      }
-      run_iterations(X, Xn, n, n, true, sched, mixed, polish, P, sb, o.graphs != 0, s);
-      ev.mark(2, s);
-      // ---- projector (X + I)/2, QR, ind (Algorithm 1); with use_omega the
-      // QR is of B Omega (the randomised rank-revealing form of Sec. 4.1)
-      half_plus_identity(X, n, P.Z, n, n, s);
-      double* Bq = P.Z;
-      double* Q2buf = (X == P.X) ? P.Xn : P.X;
-      if (o.use_omega) {
-        gaussian_fill(Q2buf, n * n, o.seed + 3, 0, s);
-        Gemm go;
-        // Omega with N(0, 1/n) entries: B Omega keeps B's column norms on average
-        go.M = n; go.N = n; go.K = n; go.alpha = 1.0 / std::sqrt((double)n);
-        go.A = P.Z; go.lda = n; go.B = Q2buf; go.ldb = n; go.C = X; go.ldc = n;
-        dgemm(go, s);
-        Bq = X;
-      }
-      std::vector<double> d;
-      const PanelWatch watch = diag_watch(Bq, n, P.diag, o.tol, &d, s);
-      geqrf(Bq, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
-      int hflags[8];
-      QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
-      QDWHP_HIP(hipStreamSynchronize(s));
-      ev.mark(3, s);
-      if (hflags[1]) return ret(QDWHP_ERR_NONFINITE);
-      if (hflags[0]) return ret(QDWHP_ERR_CHOL);
-      if (any_nonfinite(d)) return ret(QDWHP_ERR_NONFINITE);
-      ind = find_ind(d, o.tol);
-      ell = n - ind + 1;
-      if (ell <= 0) { status = QDWHP_ERR_NO_SUBSPACE; if (replay) break; continue; }
-      // ---- Q2 = H_1 ... H_{ind-1} [0; I_ell]
-      Q2 = Q2buf;
-      double* Y = o.use_omega ? P.Z : X;          // the buffers free once Q2 is formed
-      double* Wfree = o.use_omega ? X : P.Z;
-      orgqr(Bq, n, n, P.Tall, ind - 1, ind - 1, ell, Q2, n, P.qrs, s);
-      ev.mark(4, s);
-      // ---- Rayleigh-Ritz on the original matrix: H = Q2^T (sgn A) Q2
-      Gemm g1;
-      g1.M = n; g1.N = ell; g1.K = n; g1.alpha = sgn; g1.A = A; g1.lda = lda; g1.B = Q2; g1.ldb = n;
-      g1.C = Y; g1.ldc = n;
-      dgemm(g1, s);
-      double* H = P.big;
-      Gemm g2;
-      g2.M = ell; g2.N = ell; g2.K = n; g2.A = Q2; g2.lda = n; g2.ta = true; g2.B = Y; g2.ldb = n;
-      g2.C = H; g2.ldc = ell;
-      dgemm(g2, s);
-      symmetrize(H, ell, ell, s);
-      ev.mark(5, s);
-      Wv = Wfree;
-      int sweeps = -1;
-      // the estimator's quadrature places the split unless it already
-      // over-counted once (a retried threshold)
-      info->rr_split = rr_split(H, ell, k, n, (replay || boost > 1) ? nullptr : &lz, lmax, lmin, o, P, Y, n * n,
-                                Wv, n * n, P.big + ell * ell, P.vals, &sweeps, s);
-      if (info->rr_split == 0) sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
-      info->jacobi_sweeps = sweeps;
-      if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);
-      theta.resize(ell);
-      QDWHP_HIP(hipMemcpyAsync(theta.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
-      QDWHP_HIP(hipStreamSynchronize(s));
-      ev.mark(6, s);
-      n_above = 0;
-      for (double t : theta) n_above += (t >= tau);
-      status = QDWHP_OK;
-      if (n_above >= k || ell >= n || replay) break;
-      status = QDWHP_ERR_NO_SUBSPACE;
-    }
-    info->tau = sgn * tau; info->mu = mu; info->rho = rho;
-    info->ell = ell; info->ind = ind; info->n_above = n_above;
-    fill_info(info, sched);
-    if (status != QDWHP_OK) return ret(status);
-    if (ell < k) return ret(QDWHP_ERR_NO_SUBSPACE);
-    // ---- V = Q2 W(:, 1:k), w = sgn theta(1:k)
-    Gemm g3;
-    g3.M = n; g3.N = k; g3.K = ell; g3.A = Q2; g3.lda = n; g3.B = Wv; g3.ldb = ell; g3.C = V; g3.ldc = ldv;
-    scale_vec(P.vals, w, k, sgn, s);
-    if (df) {   // the caller launches the product and the sign step
-      df->g = g3; df->V = V; df->ldv = ldv; df->n = n; df->k = k; df->U = nullptr; df->ldu = 0; df->m = 0;
-    } else {
-      dgemm(g3, s);
-      sign_normalize(V, ldv, n, k, nullptr, 0, 0, s);
-    }
-    ev.mark(7, s);
-    ev.fill(info->ms);
-    const double dn = (double)n, dl = (double)ell, dk = (double)k;
-    info->flops_table1 = table1_iter_flops(sched, dn, dn) + 4.0 / 3.0 * dn * dn * dn +
-                         2.0 * dn * dn * dl + 2.0 * dn * dl * dl + 9.0 * dl * dl * dl + 2.0 * dn * dl * dk;
-  } catch (const WorkspaceError&) {
-    return ret(QDWHP_ERR_WORKSPACE);
-  } catch (const HipError&) {
-    return ret(QDWHP_ERR_HIP);
-  }
-  return ret(QDWHP_OK);
-}
-
-// ===========================================================================
 extern "C" size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdwhp_opts* opts) {
   (void)k;
   if (m < 1 || n < 1) return 0;
@@ -759,202 +555,595 @@ extern "C" size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdw
   return ar.off;
 }
 
-int qdwhp::svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k,
-                   double* U, int64_t ldu, double* S, double* V, int64_t ldv,
-                   void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
-                   qdwhp_info* info, Deferred* df) {
-  qdwhp_info dummy;
-  if (!info) info = &dummy;
-  std::memset(info, 0, sizeof(*info));
-  auto ret = [&](int st) { info->status = st; return st; };
-  if (!A) return ret(-1);
-  if (m < 1) return ret(-2);
-  if (n < 1) return ret(-3);
-  if (lda < m) return ret(-4);
-  if (k < 1 || k > std::min(m, n)) return ret(-5);
-  if (!U) return ret(-6);
-  if (ldu < m) return ret(-7);
-  if (!S) return ret(-8);
-  if (!V) return ret(-9);
-  if (ldv < n) return ret(-10);
-  if (!work) return ret(-11);
+// ===========================================================================
+// One solve in phases.  Everything a solve carries between its phases lives
+// in SolveState, so that a batch or the server can run the DWH iterations of
+// many solves together (iterations_grouped) between their setup and finish
+// phases.  A standalone call runs the phases back to back.
+namespace qdwhp {
+struct SolveState {
+  bool svd = false;
+  // arguments
+  const double* A = nullptr;
+  int64_t m = 0, n = 0, lda = 0, k = 0;
+  double fraction = 0.0;
+  int which = QDWHP_LARGEST;
+  double *w = nullptr, *U = nullptr, *V = nullptr;
+  int64_t ldu = 0, ldv = 0;
+  void* work = nullptr;
+  size_t lwork = 0;
   qdwhp_opts o;
-  if (opts) o = *opts; else qdwhp_opts_default(&o);
-  if (!(o.tol > 0.0)) return ret(-13);
-  hipStream_t s = (hipStream_t)stream;
-  const bool tr = m < n;                       // process M = A^T when A is wide
-  const int64_t mm = std::max(m, n), nn = std::min(m, n);
-  info->k = k;
-  const int nv = lz_vectors(o);
-  const int64_t msteps = lz_steps(o, nn);
-  try {
-    Arena ar(work, lwork);
-    Plan P = carve(ar, mm, nn, nv, msteps, true);
-    Events ev(true);
-    ev.mark(0, s);
-    QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
-    nonfinite(A, lda, m, n, P.flags + 1, s);
-    const bool replay = !is_nan(o.alpha) && !is_nan(o.s_svd);
-    LanczosResult lz;
-    double lmax = 0.0, lmin = 0.0;
-    if (!replay || is_nan(o.alpha)) {
-      // operator M^T M on nn-vectors; M = A (tall) or A^T (wide)
-      LanczosOp op;
-      op.rows_tmp = mm;
-      op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double* tmp, hipStream_t st) {
-        // tmp = M in (mm x nv), out = M^T tmp (nn x nv), as skinny products
-        // (the big work block is free until the iterations start); the
-        // transposed kernel takes up to 8 columns, wider blocks use the GEMM
-        auto at_b = [&](int64_t rows, int64_t cols, const double* B, int64_t ldb, double* C, int64_t ldc) {
-          if (nv <= 8) {
-            skinny_gemm_t(A, lda, rows, cols, B, ldb, nv, 1.0, C, ldc, st);
-          } else {
-            Gemm g;
-            g.M = cols; g.N = nv; g.K = rows; g.A = A; g.lda = lda; g.ta = true; g.B = B; g.ldb = ldb;
-            g.C = C; g.ldc = ldc;
-            dgemm(g, st);
-          }
-        };
-        if (!tr) {
-          skinny_gemm(A, lda, mm, nn, in, ldi, nv, 1.0, tmp, mm, P.big, P.big_doubles, st);
-          at_b(mm, nn, tmp, mm, out, ldo);
+  hipStream_t s = nullptr;
+  qdwhp_info* info = nullptr;
+  Deferred* df = nullptr;
+  // derived
+  bool tr = false;                 // SVD of a wide A: the algorithm runs on M = A^T
+  int64_t mm = 0, nn = 0;          // rows / columns of the iterate (EIG: n, n)
+  int nv = 8;
+  int64_t msteps = 64;
+  double sgn = 1.0;                // EIG: -1 for the smallest eigenvalues
+  Plan P;
+  std::unique_ptr<Events> ev;
+  LanczosResult lz;
+  double lmax = 0.0, lmin = 0.0;
+  bool replay = false;
+  int boost = 1;
+  std::vector<DwhStep> sched;
+  std::vector<int> polish;
+  bool mixed = false;
+  double tau = 0.0, mu = 1.0, rho = 0.0;   // EIG threshold, scale, unwanted-side bound
+  double alpha = 1.0, sthr = 0.5;          // SVD norm estimate, relative threshold
+  double* X = nullptr;
+  double* Xn = nullptr;
+  StepBufs sb;
+  int status = QDWHP_OK;
+  int ret(int st) { info->status = st; status = st; return st; }
+};
+}  // namespace qdwhp
+
+namespace {
+
+using qdwhp::SolveState;
+
+// ---- EIG (Algorithm 1) -----------------------------------------------------
+int eig_setup(SolveState& S) {
+  const qdwhp_opts& o = S.o;
+  if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16)
+    return S.ret(-11);
+  const int64_t n = S.n;
+  int64_t k = (int64_t)std::floor(S.fraction * (double)n + 0.5);
+  S.k = k = std::min<int64_t>(n, std::max<int64_t>(1, k));
+  S.info->k = k;
+  S.nv = lz_vectors(o);
+  S.msteps = lz_steps(o, n);
+  S.sgn = (S.which == QDWHP_SMALLEST) ? -1.0 : 1.0;
+  S.mm = S.nn = n;
+  Arena ar(S.work, S.lwork);
+  S.P = carve(ar, n, n, S.nv, S.msteps, false);
+  S.ev.reset(new Events(true));
+  S.ev->mark(0, S.s);
+  hipStream_t s = S.s;
+  Plan& P = S.P;
+  QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
+  nonfinite(S.A, S.lda, n, n, P.flags + 1, s);
+  // ---- estimator (Algorithm 1 opens with a few Lanczos steps)
+  S.replay = !is_nan(o.tau) && !is_nan(o.mu) && !is_nan(o.rho);
+  if (!S.replay) {
+    LanczosOp op;
+    op.rows_tmp = 1;
+    const double* A = S.A;
+    const int64_t lda = S.lda;
+    const double sgn = S.sgn;
+    const int nv = S.nv;
+    op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t st) {
+      // the big work block is free until the iterations start
+      skinny_gemm(A, lda, n, n, in, ldi, nv, sgn, out, ldo, P.big, P.big_doubles, st);
+    };
+    S.lz = lanczos(op, n, S.nv, (int)S.msteps, o.seed, P.lz, s);
+    if (S.lz.sweeps < 0) {   // a non-finite input shows up here first
+      int hf[8];
+      QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+      QDWHP_HIP(hipStreamSynchronize(s));
+      return S.ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
+    }
+    S.lmax = -std::numeric_limits<double>::infinity();
+    S.lmin = std::numeric_limits<double>::infinity();
+    for (size_t i = 0; i < S.lz.nodes.size(); ++i) {
+      S.lmax = std::max(S.lmax, S.lz.nodes[i] + S.lz.resid[i]);
+      S.lmin = std::min(S.lmin, S.lz.nodes[i] - S.lz.resid[i]);
+    }
+  }
+  S.info->lmax = S.lmax;
+  S.info->lmin = S.lmin;
+  S.ev->mark(1, s);
+  return QDWHP_OK;
+}
+
+// Threshold for this attempt (boost), schedule, X0, polish plan.
+void eig_prepare(SolveState& S) {
+  const qdwhp_opts& o = S.o;
+  const int64_t n = S.n;
+  const double sfix = o.s_eig;
+  if (S.replay) {
+    S.tau = o.tau; S.mu = o.mu; S.rho = o.rho;
+  } else {
+    const double spread = std::max({S.lmax - S.lmin, std::fabs(S.lmax), std::fabs(S.lmin), 1e-300});
+    if (!is_nan(o.tau)) {
+      S.tau = S.sgn * o.tau;
+    } else {
+      double cut;
+      const int64_t kt = target_count(n, S.k, S.boost);
+      const bool ok = o.tau_policy == 1
+          ? choose_tau_cost(S.lz.nodes, S.lz.weights, n, S.nv, S.lmax, S.lmin, kt, sfix, o.eig_iters,
+                            o.kappa_max, o.tol, &cut)
+          : cut_below(S.lz.nodes, S.lz.weights, n, S.nv, S.lmax, S.lmin, kt, &cut);
+      S.tau = ok ? cut : S.lmin;
+    }
+    S.mu = std::max(S.lmax - S.tau, 1e-3 * spread);
+    S.rho = std::max(0.0, (S.tau - S.lmin) / S.mu);
+  }
+  S.sched = eig_schedule(sfix, S.rho, o.eig_iters, o.kappa_max);
+  for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
+    if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  S.info->retries = S.boost - 1;
+  // ---- iterations on the scaled, shifted matrix (Sec. 4.1)
+  S.X = S.P.X;
+  S.Xn = S.P.Xn;
+  eig_x0(S.A, S.lda, S.X, n, n, (1.0 - sfix) / S.mu, S.tau, S.sgn, sfix, S.s);
+  S.sb = step_bufs(S.P, n, n);
+  S.mixed = (o.precision == QDWHP_MIXED_FP32);
+  double xbound = 1.0;
+  for (const auto& st : S.sched) xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
+  S.polish.clear();
+  if (S.mixed) {
+    // FP64 polish: Newton-Schulz while the unwanted side stays below
+    // sqrt(3) (where it converges), else Halley's (3,1,3) step in
+    // Cholesky form (monotone for any x)
+    for (int p = 0; p < o.polish_steps; ++p) {
+      if (xbound < 1.7) { S.polish.push_back(0); xbound = std::max(1.0, 0.5 * xbound * (3.0 - xbound * xbound)); }
+      else { S.polish.push_back(1); xbound = std::max(1.0, dwh_map(xbound, 3.0, 1.0, 3.0)); }
+    }
+  }
+}
+
+// Projector, QR, ind/ell, Q2, Rayleigh-Ritz.  Returns 0 when this attempt
+// is final (success or a final error in S.status), 1 when the threshold must
+// be retried.
+int eig_project(SolveState& S, std::vector<double>& theta, int64_t& ell, int64_t& ind, int64_t& n_above,
+                double*& Q2, double*& Wv) {
+  const qdwhp_opts& o = S.o;
+  const int64_t n = S.n, k = S.k;
+  hipStream_t s = S.s;
+  Plan& P = S.P;
+  double* X = S.X;
+  S.ev->mark(2, s);
+  // ---- projector (X + I)/2, QR, ind (Algorithm 1); with use_omega the
+  // QR is of B Omega (the randomised rank-revealing form of Sec. 4.1)
+  half_plus_identity(X, n, P.Z, n, n, s);
+  double* Bq = P.Z;
+  double* Q2buf = (X == P.X) ? P.Xn : P.X;
+  if (o.use_omega) {
+    gaussian_fill(Q2buf, n * n, o.seed + 3, 0, s);
+    Gemm go;
+    // Omega with N(0, 1/n) entries: B Omega keeps B's column norms on average
+    go.M = n; go.N = n; go.K = n; go.alpha = 1.0 / std::sqrt((double)n);
+    go.A = P.Z; go.lda = n; go.B = Q2buf; go.ldb = n; go.C = X; go.ldc = n;
+    dgemm(go, s);
+    Bq = X;
+  }
+  std::vector<double> d;
+  const PanelWatch watch = diag_watch(Bq, n, P.diag, o.tol, &d, s);
+  geqrf(Bq, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
+  int hflags[8];
+  QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  S.ev->mark(3, s);
+  if (hflags[1]) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
+  if (hflags[0]) { S.ret(QDWHP_ERR_CHOL); return 0; }
+  if (any_nonfinite(d)) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
+  ind = find_ind(d, o.tol);
+  ell = n - ind + 1;
+  if (ell <= 0) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
+  // ---- Q2 = H_1 ... H_{ind-1} [0; I_ell]
+  Q2 = Q2buf;
+  double* Y = o.use_omega ? P.Z : X;          // the buffers free once Q2 is formed
+  double* Wfree = o.use_omega ? X : P.Z;
+  orgqr(Bq, n, n, P.Tall, ind - 1, ind - 1, ell, Q2, n, P.qrs, s);
+  S.ev->mark(4, s);
+  // ---- Rayleigh-Ritz on the original matrix: H = Q2^T (sgn A) Q2
+  Gemm g1;
+  g1.M = n; g1.N = ell; g1.K = n; g1.alpha = S.sgn; g1.A = S.A; g1.lda = S.lda; g1.B = Q2; g1.ldb = n;
+  g1.C = Y; g1.ldc = n;
+  dgemm(g1, s);
+  double* H = P.big;
+  Gemm g2;
+  g2.M = ell; g2.N = ell; g2.K = n; g2.A = Q2; g2.lda = n; g2.ta = true; g2.B = Y; g2.ldb = n;
+  g2.C = H; g2.ldc = ell;
+  dgemm(g2, s);
+  symmetrize(H, ell, ell, s);
+  S.ev->mark(5, s);
+  Wv = Wfree;
+  int sweeps = -1;
+  // the estimator's quadrature places the split unless it already
+  // over-counted once (a retried threshold)
+  S.info->rr_split = rr_split(H, ell, k, n, (S.replay || S.boost > 1) ? nullptr : &S.lz, S.lmax, S.lmin, o, P, Y,
+                              n * n, Wv, n * n, P.big + ell * ell, P.vals, &sweeps, s);
+  if (S.info->rr_split == 0) sweeps = syev(H, ell, ell, P.vals, Wv, ell, P.big + ell * ell, s);
+  S.info->jacobi_sweeps = sweeps;
+  if (sweeps < 0) { S.ret(QDWHP_ERR_NOCONV); return 0; }
+  theta.resize(ell);
+  QDWHP_HIP(hipMemcpyAsync(theta.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  S.ev->mark(6, s);
+  n_above = 0;
+  for (double t : theta) n_above += (t >= S.tau);
+  S.status = QDWHP_OK;
+  if (n_above >= k || ell >= n || S.replay) return 0;
+  S.status = QDWHP_ERR_NO_SUBSPACE;
+  return 1;
+}
+
+int eig_finish(SolveState& S) {
+  const int64_t n = S.n, k = S.k;
+  hipStream_t s = S.s;
+  std::vector<double> theta;
+  int64_t ell = 0, ind = 0, n_above = 0;
+  double* Q2 = nullptr;
+  double* Wv = nullptr;
+  while (eig_project(S, theta, ell, ind, n_above, Q2, Wv) == 1 && S.boost < 2) {
+    ++S.boost;
+    eig_prepare(S);
+    run_iterations(S.X, S.Xn, n, n, true, S.sched, S.mixed, S.polish, S.P, S.sb, S.o.graphs != 0, s);
+  }
+  qdwhp_info* info = S.info;
+  info->tau = S.sgn * S.tau; info->mu = S.mu; info->rho = S.rho;
+  info->ell = ell; info->ind = ind; info->n_above = n_above;
+  fill_info(info, S.sched);
+  if (S.status != QDWHP_OK) return S.ret(S.status);
+  if (ell < k) return S.ret(QDWHP_ERR_NO_SUBSPACE);
+  // ---- V = Q2 W(:, 1:k), w = sgn theta(1:k)
+  Gemm g3;
+  g3.M = n; g3.N = k; g3.K = ell; g3.A = Q2; g3.lda = n; g3.B = Wv; g3.ldb = ell; g3.C = S.V; g3.ldc = S.ldv;
+  scale_vec(S.P.vals, S.w, k, S.sgn, s);
+  if (S.df) {   // the caller launches the product and the sign step
+    Deferred* df = S.df;
+    df->g = g3; df->V = S.V; df->ldv = S.ldv; df->n = n; df->k = k; df->U = nullptr; df->ldu = 0; df->m = 0;
+  } else {
+    dgemm(g3, s);
+    sign_normalize(S.V, S.ldv, n, k, nullptr, 0, 0, s);
+  }
+  S.ev->mark(7, s);
+  S.ev->fill(info->ms);
+  const double dn = (double)n, dl = (double)ell, dk = (double)k;
+  info->flops_table1 = table1_iter_flops(S.sched, dn, dn) + 4.0 / 3.0 * dn * dn * dn +
+                       2.0 * dn * dn * dl + 2.0 * dn * dl * dl + 9.0 * dl * dl * dl + 2.0 * dn * dl * dk;
+  return S.ret(QDWHP_OK);
+}
+
+// ---- SVD (Algorithm 2) -----------------------------------------------------
+int svd_setup(SolveState& S) {
+  const qdwhp_opts& o = S.o;
+  if (!(o.tol > 0.0)) return S.ret(-13);
+  hipStream_t s = S.s;
+  const int64_t m = S.m, n = S.n;
+  S.tr = m < n;                       // process M = A^T when A is wide
+  const bool tr = S.tr;
+  const int64_t mm = S.mm = std::max(m, n), nn = S.nn = std::min(m, n);
+  S.info->k = S.k;
+  S.nv = lz_vectors(o);
+  S.msteps = lz_steps(o, nn);
+  Arena ar(S.work, S.lwork);
+  S.P = carve(ar, mm, nn, S.nv, S.msteps, true);
+  Plan& P = S.P;
+  S.ev.reset(new Events(true));
+  S.ev->mark(0, s);
+  QDWHP_HIP(hipMemsetAsync(P.flags, 0, 8 * sizeof(int), s));
+  nonfinite(S.A, S.lda, m, n, P.flags + 1, s);
+  S.replay = !is_nan(o.alpha) && !is_nan(o.s_svd);
+  if (!S.replay || is_nan(o.alpha)) {
+    // operator M^T M on nn-vectors; M = A (tall) or A^T (wide)
+    const double* A = S.A;
+    const int64_t lda = S.lda;
+    const int nv = S.nv;
+    LanczosOp op;
+    op.rows_tmp = mm;
+    op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double* tmp, hipStream_t st) {
+      // tmp = M in (mm x nv), out = M^T tmp (nn x nv), as skinny products
+      // (the big work block is free until the iterations start); the
+      // transposed kernel takes up to 8 columns, wider blocks use the GEMM
+      auto at_b = [&](int64_t rows, int64_t cols, const double* B, int64_t ldb, double* C, int64_t ldc) {
+        if (nv <= 8) {
+          skinny_gemm_t(A, lda, rows, cols, B, ldb, nv, 1.0, C, ldc, st);
         } else {
-          at_b(nn, mm, in, ldi, tmp, mm);
-          skinny_gemm(A, lda, nn, mm, tmp, mm, nv, 1.0, out, ldo, P.big, P.big_doubles, st);
+          Gemm g;
+          g.M = cols; g.N = nv; g.K = rows; g.A = A; g.lda = lda; g.ta = true; g.B = B; g.ldb = ldb;
+          g.C = C; g.ldc = ldc;
+          dgemm(g, st);
         }
       };
-      lz = lanczos(op, nn, nv, (int)msteps, o.seed, P.lz, s);
-      if (lz.sweeps < 0) {   // a non-finite input shows up here first
-        int hf[8];
-        QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
-        QDWHP_HIP(hipStreamSynchronize(s));
-        return ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
-      }
-      lmax = -std::numeric_limits<double>::infinity();
-      lmin = std::numeric_limits<double>::infinity();
-      for (size_t i = 0; i < lz.nodes.size(); ++i) {
-        lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
-        lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
-      }
-    }
-    info->lmax = lmax; info->lmin = lmin;
-    ev.mark(1, s);
-    std::vector<DwhStep> sched;
-    std::vector<double> sig;
-    int64_t ell = 0, ind = 0, n_above = 0;
-    double alpha = 1.0, sthr = 0.5;
-    double *Q2 = nullptr, *Y = nullptr, *Vt = nullptr, *Ut = nullptr;
-    int status = QDWHP_OK;
-    for (int boost = 1; boost <= 2; ++boost) {
-      if (replay) {
-        alpha = o.alpha; sthr = o.s_svd;
+      if (!tr) {
+        skinny_gemm(A, lda, mm, nn, in, ldi, nv, 1.0, tmp, mm, P.big, P.big_doubles, st);
+        at_b(mm, nn, tmp, mm, out, ldo);
       } else {
-        alpha = std::sqrt(std::max(lmax, 0.0));
-        if (!(alpha > 0.0)) alpha = 1e-300;
-        if (!is_nan(o.alpha)) alpha = o.alpha;
-        if (!is_nan(o.s_svd)) {
-          sthr = o.s_svd;
-        } else {
-          double cut;
-          const double t = cut_below(lz.nodes, lz.weights, nn, nv, lmax, lmin,
-                                     target_count(nn, k, boost), &cut, true) ? std::max(cut, 0.0) : 0.0;
-          sthr = std::min(1.0, std::max(1e-15, std::sqrt(t) / alpha));
-        }
+        at_b(nn, mm, in, ldi, tmp, mm);
+        skinny_gemm(A, lda, nn, mm, tmp, mm, nv, 1.0, out, ldo, P.big, P.big_doubles, st);
       }
-      sched = svd_schedule(sthr, o.kappa_max, o.svd_qr_first != 0);
-      for (size_t i = 0; i < sched.size() && i < 16; ++i)
-        if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) sched[i].kind = o.kinds[i];
-      info->retries = boost - 1;
-      double* X = P.X;
-      double* Xn = P.Xn;
-      scale_copy(A, lda, X, mm, mm, nn, 1.0 / alpha, tr, s);
-      const StepBufs sb = step_bufs(P, mm, nn);
-      const bool mixed = (o.precision == QDWHP_MIXED_FP32);
-      // FP64 Newton-Schulz polish after mixed steps (singular values of X lie in [0, 1 + O(u_32)])
-      const std::vector<int> polish(mixed ? std::max(0, o.polish_steps) : 0, 0);
-      run_iterations(X, Xn, mm, nn, false, sched, mixed, polish, P, sb, o.graphs != 0, s);
-      ev.mark(2, s);
-      // ---- projector I - X^T X, QR, ind (Algorithm 2)
-      Gemm gb;
-      gb.M = nn; gb.N = nn; gb.K = mm; gb.alpha = -1.0; gb.diag = 1.0; gb.A = X; gb.lda = mm; gb.ta = true;
-      gb.B = X; gb.ldb = mm; gb.C = P.Z; gb.ldc = nn; gb.tiles = TILES_UPPER;
-      dgemm(gb, s);
-      mirror_upper(P.Z, nn, nn, s);
-      std::vector<double> d;
-      const PanelWatch watch = diag_watch(P.Z, nn, P.diag, o.tol, &d, s);
-      geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s, &watch);
-      int hflags[8];
-      QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+    };
+    S.lz = lanczos(op, nn, S.nv, (int)S.msteps, o.seed, P.lz, s);
+    if (S.lz.sweeps < 0) {   // a non-finite input shows up here first
+      int hf[8];
+      QDWHP_HIP(hipMemcpyAsync(hf, P.flags, sizeof(hf), hipMemcpyDeviceToHost, s));
       QDWHP_HIP(hipStreamSynchronize(s));
-      ev.mark(3, s);
-      if (hflags[1]) return ret(QDWHP_ERR_NONFINITE);
-      if (hflags[0]) return ret(QDWHP_ERR_CHOL);
-      if (any_nonfinite(d)) return ret(QDWHP_ERR_NONFINITE);
-      ind = find_ind(d, o.tol);
-      ell = nn - ind + 1;
-      if (ell <= 0) { status = QDWHP_ERR_NO_SUBSPACE; if (replay) break; continue; }
-      Q2 = (X == P.X) ? P.Xn : P.X;
-      Y = X;
-      orgqr(P.Z, nn, nn, P.Tall, ind - 1, ind - 1, ell, Q2, nn, P.qrs, s);
-      ev.mark(4, s);
-      // ---- Y = M Q2 = Q_Y R_Y, SVD of R_Y (Algorithm 2 projection step)
-      Gemm gy;
-      gy.M = mm; gy.N = ell; gy.K = nn; gy.A = A; gy.lda = lda; gy.ta = tr; gy.B = Q2; gy.ldb = nn;
-      gy.C = Y; gy.ldc = mm;
-      dgemm(gy, s);
-      geqrf(Y, mm, ell, mm, P.tau, P.Tall, P.qrs, s);
-      Ut = P.Z;
-      upper_copy(Y, mm, Ut, ell, ell, s);
-      ev.mark(5, s);
-      Vt = P.big + gesvj_scratch_doubles(ell, ell);
-      const int sweeps = gesvj(Ut, ell, ell, ell, P.vals, Vt, ell, P.big, s);
-      info->jacobi_sweeps = sweeps;
-      if (sweeps < 0) return ret(QDWHP_ERR_NOCONV);
-      sig.resize(ell);
-      QDWHP_HIP(hipMemcpyAsync(sig.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
-      QDWHP_HIP(hipStreamSynchronize(s));
-      ev.mark(6, s);
-      n_above = 0;
-      for (double v : sig) n_above += (v >= sthr * alpha);
-      status = QDWHP_OK;
-      if (n_above >= k || ell >= nn || replay) break;
-      status = QDWHP_ERR_NO_SUBSPACE;
+      return S.ret(hf[1] ? QDWHP_ERR_NONFINITE : QDWHP_ERR_NOCONV);
     }
-    info->alpha = alpha; info->s = sthr;
-    info->ell = ell; info->ind = ind; info->n_above = n_above;
-    fill_info(info, sched);
-    if (status != QDWHP_OK) return ret(status);
-    if (ell < k) return ret(QDWHP_ERR_NO_SUBSPACE);
-    // ---- U_M = Q_Y [U~_k; 0], V_M = Q2 V~_k; A = M or M^T
-    double* Um = tr ? V : U;
-    const int64_t ldum = tr ? ldv : ldu;
-    double* Vm = tr ? U : V;
-    const int64_t ldvm = tr ? ldu : ldv;
-    fill(Um, mm, k, ldum, 0.0, 0.0, s);
-    copy(Ut, ell, Um, ldum, ell, k, s);
-    apply_q(Y, mm, mm, P.Tall, ell, Um, k, ldum, P.qrs, s);
-    Gemm gv;
-    gv.M = nn; gv.N = k; gv.K = ell; gv.A = Q2; gv.lda = nn; gv.B = Vt; gv.ldb = ell; gv.C = Vm; gv.ldc = ldvm;
-    scale_vec(P.vals, S, k, 1.0, s);
-    if (df) {
-      df->g = gv; df->V = V; df->ldv = ldv; df->n = n; df->k = k; df->U = U; df->ldu = ldu; df->m = m;
-    } else {
-      dgemm(gv, s);
-      sign_normalize(V, ldv, n, k, U, ldu, m, s);
+    S.lmax = -std::numeric_limits<double>::infinity();
+    S.lmin = std::numeric_limits<double>::infinity();
+    for (size_t i = 0; i < S.lz.nodes.size(); ++i) {
+      S.lmax = std::max(S.lmax, S.lz.nodes[i] + S.lz.resid[i]);
+      S.lmin = std::min(S.lmin, S.lz.nodes[i] - S.lz.resid[i]);
     }
-    ev.mark(7, s);
-    ev.fill(info->ms);
-    const double dm = (double)mm, dn = (double)nn, dl = (double)ell, dk = (double)k;
-    info->flops_table1 = table1_iter_flops(sched, dm, dn) + dm * dn * dn + 4.0 / 3.0 * dn * dn * dn +
-                         2.0 * dm * dn * dl + 2.0 * dm * dl * dl + 17.0 * dl * dl * dl +
-                         2.0 * dm * dl * dk + 2.0 * dn * dl * dk;
-  } catch (const WorkspaceError&) {
-    return ret(QDWHP_ERR_WORKSPACE);
-  } catch (const HipError&) {
-    return ret(QDWHP_ERR_HIP);
   }
-  return ret(QDWHP_OK);
+  S.info->lmax = S.lmax;
+  S.info->lmin = S.lmin;
+  S.ev->mark(1, s);
+  return QDWHP_OK;
 }
+
+void svd_prepare(SolveState& S) {
+  const qdwhp_opts& o = S.o;
+  const int64_t mm = S.mm, nn = S.nn;
+  if (S.replay) {
+    S.alpha = o.alpha; S.sthr = o.s_svd;
+  } else {
+    S.alpha = std::sqrt(std::max(S.lmax, 0.0));
+    if (!(S.alpha > 0.0)) S.alpha = 1e-300;
+    if (!is_nan(o.alpha)) S.alpha = o.alpha;
+    if (!is_nan(o.s_svd)) {
+      S.sthr = o.s_svd;
+    } else {
+      double cut;
+      const double t = cut_below(S.lz.nodes, S.lz.weights, nn, S.nv, S.lmax, S.lmin,
+                                 target_count(nn, S.k, S.boost), &cut, true) ? std::max(cut, 0.0) : 0.0;
+      S.sthr = std::min(1.0, std::max(1e-15, std::sqrt(t) / S.alpha));
+    }
+  }
+  S.sched = svd_schedule(S.sthr, o.kappa_max, o.svd_qr_first != 0);
+  for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
+    if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  S.info->retries = S.boost - 1;
+  S.X = S.P.X;
+  S.Xn = S.P.Xn;
+  scale_copy(S.A, S.lda, S.X, mm, mm, nn, 1.0 / S.alpha, S.tr, S.s);
+  S.sb = step_bufs(S.P, mm, nn);
+  S.mixed = (o.precision == QDWHP_MIXED_FP32);
+  // FP64 Newton-Schulz polish steps (singular values of X lie in [0, 1 + O(u_32)])
+  S.polish.assign(S.mixed ? std::max(0, o.polish_steps) : 0, 0);
+}
+
+int svd_project(SolveState& S, std::vector<double>& sig, int64_t& ell, int64_t& ind, int64_t& n_above,
+                double*& Q2, double*& Y, double*& Ut, double*& Vt) {
+  const qdwhp_opts& o = S.o;
+  const int64_t mm = S.mm, nn = S.nn, k = S.k;
+  hipStream_t s = S.s;
+  Plan& P = S.P;
+  double* X = S.X;
+  S.ev->mark(2, s);
+  // ---- projector I - X^T X, QR, ind (Algorithm 2)
+  Gemm gb;
+  gb.M = nn; gb.N = nn; gb.K = mm; gb.alpha = -1.0; gb.diag = 1.0; gb.A = X; gb.lda = mm; gb.ta = true;
+  gb.B = X; gb.ldb = mm; gb.C = P.Z; gb.ldc = nn; gb.tiles = TILES_UPPER;
+  dgemm(gb, s);
+  mirror_upper(P.Z, nn, nn, s);
+  std::vector<double> d;
+  const PanelWatch watch = diag_watch(P.Z, nn, P.diag, o.tol, &d, s);
+  geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s, &watch);
+  int hflags[8];
+  QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  S.ev->mark(3, s);
+  if (hflags[1]) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
+  if (hflags[0]) { S.ret(QDWHP_ERR_CHOL); return 0; }
+  if (any_nonfinite(d)) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
+  ind = find_ind(d, o.tol);
+  ell = nn - ind + 1;
+  if (ell <= 0) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
+  Q2 = (X == P.X) ? P.Xn : P.X;
+  Y = X;
+  orgqr(P.Z, nn, nn, P.Tall, ind - 1, ind - 1, ell, Q2, nn, P.qrs, s);
+  S.ev->mark(4, s);
+  // ---- Y = M Q2 = Q_Y R_Y, SVD of R_Y (Algorithm 2 projection step)
+  Gemm gy;
+  gy.M = mm; gy.N = ell; gy.K = nn; gy.A = S.A; gy.lda = S.lda; gy.ta = S.tr; gy.B = Q2; gy.ldb = nn;
+  gy.C = Y; gy.ldc = mm;
+  dgemm(gy, s);
+  geqrf(Y, mm, ell, mm, P.tau, P.Tall, P.qrs, s);
+  Ut = P.Z;
+  upper_copy(Y, mm, Ut, ell, ell, s);
+  S.ev->mark(5, s);
+  Vt = P.big + gesvj_scratch_doubles(ell, ell);
+  const int sweeps = gesvj(Ut, ell, ell, ell, P.vals, Vt, ell, P.big, s);
+  S.info->jacobi_sweeps = sweeps;
+  if (sweeps < 0) { S.ret(QDWHP_ERR_NOCONV); return 0; }
+  sig.resize(ell);
+  QDWHP_HIP(hipMemcpyAsync(sig.data(), P.vals, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  S.ev->mark(6, s);
+  n_above = 0;
+  for (double v : sig) n_above += (v >= S.sthr * S.alpha);
+  S.status = QDWHP_OK;
+  if (n_above >= k || ell >= nn || S.replay) return 0;
+  S.status = QDWHP_ERR_NO_SUBSPACE;
+  return 1;
+}
+
+int svd_finish(SolveState& S) {
+  const int64_t mm = S.mm, nn = S.nn, k = S.k;
+  hipStream_t s = S.s;
+  std::vector<double> sig;
+  int64_t ell = 0, ind = 0, n_above = 0;
+  double *Q2 = nullptr, *Y = nullptr, *Ut = nullptr, *Vt = nullptr;
+  while (svd_project(S, sig, ell, ind, n_above, Q2, Y, Ut, Vt) == 1 && S.boost < 2) {
+    ++S.boost;
+    svd_prepare(S);
+    run_iterations(S.X, S.Xn, mm, nn, false, S.sched, S.mixed, S.polish, S.P, S.sb, S.o.graphs != 0, s);
+  }
+  qdwhp_info* info = S.info;
+  info->alpha = S.alpha; info->s = S.sthr;
+  info->ell = ell; info->ind = ind; info->n_above = n_above;
+  fill_info(info, S.sched);
+  if (S.status != QDWHP_OK) return S.ret(S.status);
+  if (ell < k) return S.ret(QDWHP_ERR_NO_SUBSPACE);
+  Plan& P = S.P;
+  // ---- U_M = Q_Y [U~_k; 0], V_M = Q2 V~_k; A = M or M^T
+  double* Um = S.tr ? S.V : S.U;
+  const int64_t ldum = S.tr ? S.ldv : S.ldu;
+  double* Vm = S.tr ? S.U : S.V;
+  const int64_t ldvm = S.tr ? S.ldu : S.ldv;
+  fill(Um, mm, k, ldum, 0.0, 0.0, s);
+  copy(Ut, ell, Um, ldum, ell, k, s);
+  apply_q(Y, mm, mm, P.Tall, ell, Um, k, ldum, P.qrs, s);
+  Gemm gv;
+  gv.M = nn; gv.N = k; gv.K = ell; gv.A = Q2; gv.lda = nn; gv.B = Vt; gv.ldb = ell; gv.C = Vm; gv.ldc = ldvm;
+  scale_vec(P.vals, S.w, k, 1.0, s);
+  if (S.df) {
+    Deferred* df = S.df;
+    df->g = gv; df->V = S.V; df->ldv = S.ldv; df->n = S.n; df->k = k; df->U = S.U; df->ldu = S.ldu; df->m = S.m;
+  } else {
+    dgemm(gv, s);
+    sign_normalize(S.V, S.ldv, S.n, k, S.U, S.ldu, S.m, s);
+  }
+  S.ev->mark(7, s);
+  S.ev->fill(info->ms);
+  const double dm = (double)mm, dn = (double)nn, dl = (double)ell, dk = (double)k;
+  info->flops_table1 = table1_iter_flops(S.sched, dm, dn) + dm * dn * dn + 4.0 / 3.0 * dn * dn * dn +
+                       2.0 * dm * dn * dl + 2.0 * dm * dl * dl + 17.0 * dl * dl * dl +
+                       2.0 * dm * dl * dk + 2.0 * dn * dl * dk;
+  return S.ret(QDWHP_OK);
+}
+
+// Argument checks of the two drivers (LAPACK-style negative codes).
+int check_eig(const double* A, int64_t n, int64_t lda, double fraction, int which, const double* w,
+              const double* V, int64_t ldv, const void* work) {
+  if (!A) return -1;
+  if (n < 1) return -2;
+  if (lda < n) return -3;
+  if (!(fraction > 0.0) || fraction > 1.0) return -4;
+  if (which != QDWHP_LARGEST && which != QDWHP_SMALLEST) return -5;
+  if (!w) return -6;
+  if (!V) return -7;
+  if (ldv < n) return -8;
+  if (!work) return -9;
+  return 0;
+}
+
+int check_svd(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k, const double* U, int64_t ldu,
+              const double* S, const double* V, int64_t ldv, const void* work) {
+  if (!A) return -1;
+  if (m < 1) return -2;
+  if (n < 1) return -3;
+  if (lda < m) return -4;
+  if (k < 1 || k > std::min(m, n)) return -5;
+  if (!U) return -6;
+  if (ldu < m) return -7;
+  if (!S) return -8;
+  if (!V) return -9;
+  if (ldv < n) return -10;
+  if (!work) return -11;
+  return 0;
+}
+
+// Runs f, mapping the library's exceptions to status codes.
+template <class F>
+int guarded(SolveState& S, F&& f) {
+  try {
+    return f();
+  } catch (const WorkspaceError&) {
+    return S.ret(QDWHP_ERR_WORKSPACE);
+  } catch (const HipError&) {
+    return S.ret(QDWHP_ERR_HIP);
+  }
+}
+
+}  // namespace
+
+namespace qdwhp {
+
+SolveState* solve_create(const qdwhp_problem& p, void* work, size_t lwork, const qdwhp_opts* opts,
+                         hipStream_t s, qdwhp_info* info, Deferred* df) {
+  auto* S = new SolveState();
+  S->svd = (p.type == QDWHP_PROBLEM_SVD);
+  S->A = p.A; S->lda = p.lda; S->n = p.n; S->m = S->svd ? p.m : p.n;
+  S->fraction = p.fraction; S->which = p.which; S->k = p.k;
+  S->w = p.w; S->U = p.U; S->ldu = p.ldu; S->V = p.V; S->ldv = p.ldv;
+  S->work = work; S->lwork = lwork;
+  if (opts) S->o = *opts; else qdwhp_opts_default(&S->o);
+  S->s = s;
+  S->info = info;
+  S->df = df;
+  std::memset(info, 0, sizeof(*info));
+  return S;
+}
+
+void solve_destroy(SolveState* S) { delete S; }
+int solve_status(const SolveState* S) { return S->status; }
+void solve_set_stream(SolveState* S, hipStream_t s) { S->s = s; }
+
+int solve_setup(SolveState* S) {
+  SolveState& st = *S;
+  const int bad = st.svd ? check_svd(st.A, st.m, st.n, st.lda, st.k, st.U, st.ldu, st.w, st.V, st.ldv, st.work)
+                         : check_eig(st.A, st.n, st.lda, st.fraction, st.which, st.w, st.V, st.ldv, st.work);
+  if (bad) return st.ret(bad);
+  return guarded(st, [&] {
+    const int r = st.svd ? svd_setup(st) : eig_setup(st);
+    if (r != QDWHP_OK) return r;
+    if (st.svd) svd_prepare(st); else eig_prepare(st);
+    return QDWHP_OK;
+  });
+}
+
+int solve_iterate(SolveState* S) {
+  SolveState& st = *S;
+  return guarded(st, [&] {
+    run_iterations(st.X, st.Xn, st.mm, st.nn, !st.svd, st.sched, st.mixed, st.polish, st.P, st.sb,
+                   st.o.graphs != 0, st.s);
+    return QDWHP_OK;
+  });
+}
+
+int solve_finish(SolveState* S) {
+  SolveState& st = *S;
+  return guarded(st, [&] { return st.svd ? svd_finish(st) : eig_finish(st); });
+}
+
+int eig_impl(const double* A, int64_t n, int64_t lda, double fraction, int which, double* w, double* V,
+             int64_t ldv, void* work, size_t lwork, const qdwhp_opts* opts, void* stream, qdwhp_info* info,
+             Deferred* df) {
+  qdwhp_info dummy;
+  qdwhp_problem p{};
+  p.type = QDWHP_PROBLEM_EIG; p.which = which; p.m = n; p.n = n; p.A = A; p.lda = lda; p.fraction = fraction;
+  p.w = w; p.V = V; p.ldv = ldv;
+  std::unique_ptr<SolveState> S(solve_create(p, work, lwork, opts, (hipStream_t)stream, info ? info : &dummy, df));
+  int r = solve_setup(S.get());
+  if (r == QDWHP_OK) r = solve_iterate(S.get());
+  if (r == QDWHP_OK) r = solve_finish(S.get());
+  return r;
+}
+
+int svd_impl(const double* A, int64_t m, int64_t n, int64_t lda, int64_t k, double* U, int64_t ldu, double* S_,
+             double* V, int64_t ldv, void* work, size_t lwork, const qdwhp_opts* opts, void* stream,
+             qdwhp_info* info, Deferred* df) {
+  qdwhp_info dummy;
+  qdwhp_problem p{};
+  p.type = QDWHP_PROBLEM_SVD; p.m = m; p.n = n; p.A = A; p.lda = lda; p.k = k;
+  p.w = S_; p.U = U; p.ldu = ldu; p.V = V; p.ldv = ldv;
+  std::unique_ptr<SolveState> S(solve_create(p, work, lwork, opts, (hipStream_t)stream, info ? info : &dummy, df));
+  int r = solve_setup(S.get());
+  if (r == QDWHP_OK) r = solve_iterate(S.get());
+  if (r == QDWHP_OK) r = solve_finish(S.get());
+  return r;
+}
+
+}  // namespace qdwhp
 
 extern "C" int qdwhp_eig(const double* A, int64_t n, int64_t lda, double fraction, int which,
                          double* w, double* V, int64_t ldv, void* work, size_t lwork,
@@ -1094,4 +1283,77 @@ extern "C" int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double*
     return QDWHP_ERR_HIP;
   }
   return QDWHP_OK;
+}
+
+// ===========================================================================
+// DWH steps of a group of solves of one shape (phase 2 of a batch or a server
+// group): the operations of chol_step for all Cholesky-based members at once.
+int64_t qdwhp::solve_shape(const SolveState* S) {
+  return ((S->svd ? 1 : 0) | ((int64_t)(S->mixed ? 1 : 0) << 1)) + 4 * (S->mm * 2000003 + S->nn);
+}
+
+void qdwhp::iterations_grouped(SolveState* const* v, int count, void* table, hipStream_t s) {
+  if (count <= 0) return;
+  if (count == 1) {    // a group of one is the solve's own iterations
+    SolveState& S = *v[0];
+    run_iterations(S.X, S.Xn, S.mm, S.nn, !S.svd, S.sched, S.mixed, S.polish, S.P, S.sb, false, s);
+    return;
+  }
+  const int64_t m = v[0]->mm, n = v[0]->nn;
+  const bool sym = !v[0]->svd;
+  for (int q = 1; q < count; ++q)
+    if (solve_shape(v[q]) != solve_shape(v[0])) throw HipError{hipErrorInvalidValue};
+  size_t steps = 0;
+  for (int q = 0; q < count; ++q) steps = std::max(steps, v[q]->sched.size());
+  std::vector<GroupedDesc> gram, prod1, prod2;
+  std::vector<CholItem> chol;
+  std::vector<SolveState*> grp;
+  for (size_t i = 0; i < steps; ++i) {
+    grp.clear();
+    for (int q = 0; q < count; ++q) {
+      SolveState& S = *v[q];
+      if (i >= S.sched.size()) continue;
+      const DwhStep& st = S.sched[i];
+      const bool f32 = S.mixed && i + 1 < S.sched.size();
+      if (st.kind == 1) qr_step(S.X, m, n, st.a, st.b, st.c, sym, S.sb, s);
+      else if (f32) chol_step(S.X, S.Xn, m, n, st.a, st.b, st.c, sym, S.sb, s, true);
+      else grp.push_back(&S);
+    }
+    if (grp.empty()) continue;
+    gram.clear(); prod1.clear(); prod2.clear(); chol.clear();
+    for (SolveState* p : grp) {
+      SolveState& S = *p;
+      const DwhStep& st = S.sched[i];
+      double* Wi = S.sb.spd;
+      double* T = S.sb.spd + spd_inverse_doubles(n);
+      GroupedDesc g{n, n, m, st.c, 0.0, S.X, m, S.X, m, S.sb.Z, n};   // Z = I + c X^T X (upper tiles)
+      g.diag = 1.0;
+      g.tiles = TILES_UPPER;
+      gram.push_back(g);
+      chol.push_back(CholItem{S.sb.Z, n, S.sb.spd, S.sb.flag});
+      GroupedDesc t{m, n, n, 1.0, 0.0, S.X, m, Wi, n, T, m};          // T = X W^{-1}
+      t.khi = KHI_COL;
+      prod1.push_back(t);
+      GroupedDesc u{m, n, n, st.a - st.b / st.c, st.b / st.c, T, m, Wi, n, S.Xn, m};   // X+ = (b/c) X + (a - b/c) T W^{-T}
+      u.Cin = S.X; u.ldcin = m; u.klo = KLO_COL;
+      if (sym) u.tiles = TILES_UPPER;
+      prod2.push_back(u);
+    }
+    const int cnt = (int)grp.size();
+    dgemm_grouped(gram.data(), cnt, true, false, table, s);
+    chol_inverse_grouped(chol.data(), cnt, n, table, s);
+    dgemm_grouped(prod1.data(), cnt, false, false, table, s);
+    dgemm_grouped(prod2.data(), cnt, false, true, table, s);
+    for (SolveState* p : grp) {
+      if (sym) mirror_upper(p->Xn, n, m, s);
+      std::swap(p->X, p->Xn);
+    }
+  }
+  for (int q = 0; q < count; ++q) {
+    SolveState& S = *v[q];
+    for (int pl : S.polish) {
+      if (pl == 0) ns_step(S.X, S.Xn, m, n, sym, S.sb, s);
+      else chol_step(S.X, S.Xn, m, n, 3.0, 1.0, 3.0, sym, S.sb, s, false);
+    }
+  }
 }

@@ -1,8 +1,13 @@
 """Ragged batches, the persistent grouped GEMM and the request server.
 
-Batched and served results must equal standalone calls bitwise (same kernels,
-launch shapes independent of the batch or mix); values are also checked
-against the planted spectra.  Each case prints its shapes before GPU work."""
+Batches and the server run the DWH iterations of instances of one shape as
+grouped launches (grouped Gram, lockstep Cholesky-inversion with batched
+leaves, grouped triangular products).  Each grouped launch performs every
+member's operations exactly as its standalone call would, so batched and
+served results equal standalone calls bitwise, alone and in any batch or mix.
+Values are checked against the planted spectra, and every returned vector's
+residual and orthogonality.  Each case prints its shapes before GPU work."""
+import contextlib
 import ctypes
 
 import numpy as np
@@ -39,6 +44,27 @@ def _specs(torch):
     return specs, exact
 
 
+def _specs_same_shape(torch):
+    """Groups of equal shapes (so the iterations really run grouped): three
+    EIG of n = 256, two of n = 384 (smallest), three SVD of 300 x 200."""
+    from synthetic import eig_uniform, svd_geometric
+    dev = torch.device("cuda")
+    specs, exact = [], []
+    for seed, f in [(61, 0.1), (62, 0.2), (63, 0.05)]:
+        A, lam = eig_uniform(256, seed, device=dev)
+        specs.append(dict(type="eig", A=A, fraction=f))
+        exact.append(np.sort(lam)[::-1])
+    for seed in (64, 65):
+        A, lam = eig_uniform(384, seed, device=dev)
+        specs.append(dict(type="eig", A=A, fraction=0.1, which="smallest"))
+        exact.append(np.sort(lam))
+    for seed, kappa in [(66, 1e3), (67, 1e8), (68, 1e12)]:
+        A, sg = svd_geometric(300, 200, seed, kappa=kappa, device=dev)
+        specs.append(dict(type="svd", A=A, k=12))
+        exact.append(np.asarray(sg))
+    return specs, exact
+
+
 def _standalone(q, sp):
     if sp["type"] == "eig":
         return q.eig(sp["A"], fraction=sp["fraction"], which=sp.get("which", "largest"))
@@ -47,6 +73,21 @@ def _standalone(q, sp):
 
 def _same(a, b):
     return all(bool((x == y).all()) for x, y in zip(a, b))
+
+
+@contextlib.contextmanager
+def _tuned(q, **keys):
+    old = {k: q.tune_get(k.replace("_", "."), -12345) for k in keys}
+    try:
+        for k, v in keys.items():
+            q.tune_set(k.replace("_", "."), v)
+        yield
+    finally:
+        for k, v in old.items():
+            if v == -12345:
+                q.tune_set(k.replace("_", "."), 1)
+            else:
+                q.tune_set(k.replace("_", "."), v)
 
 
 @pytest.mark.parametrize("transa,transb", [(0, 0), (1, 0), (0, 1), (1, 1)])
@@ -87,21 +128,45 @@ def test_grouped_gemm_matches_host_and_single_launches(transa, transb):
             assert bool((Cs[i] == Cs1[i]).all()), ("grouped differs from single launch", i, m, n, k)
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
-def test_batched_equals_standalone_bitwise(lanes):
+@pytest.mark.parametrize("lanes,same", [(1, False), (4, False), (2, True), (4, True)])
+def test_batched_equals_standalone_bitwise(lanes, same):
     torch = _torch()
     import paper_2104_14186_amd as q
-    specs, exact = _specs(torch)
+    specs, exact = (_specs_same_shape if same else _specs)(torch)
     print("batched lanes", lanes, [(s["type"], tuple(s["A"].shape)) for s in specs], flush=True)
     res, infos = q.batched(specs, lanes=lanes, return_info=True)
     torch.cuda.synchronize()
-    for sp, r, ex, inf in zip(specs, res, exact, infos):
-        alone = _standalone(q, sp)
-        assert _same(r, alone), (sp["type"], tuple(sp["A"].shape))
-        vals = (r[0] if sp["type"] == "eig" else r[1]).cpu().numpy()
-        e = ex[:len(vals)]
-        assert np.max(np.abs(vals - e) / np.abs(e)) <= 1e-12, (sp["type"], tuple(sp["A"].shape))
+    _check_planted(specs, exact, res)
+    for sp, r, inf in zip(specs, res, infos):
         assert inf["status"] == 0
+        assert _same(r, _standalone(q, sp)), (sp["type"], tuple(sp["A"].shape))
+
+
+def test_batched_result_does_not_depend_on_the_batch():
+    """The same instance in two different batches (and alone in a batch):
+    bitwise the same result."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    specs, exact = _specs_same_shape(torch)
+    print("batch composition", flush=True)
+    full = q.batched(specs, lanes=3)
+    part = q.batched([specs[5], specs[0], specs[2]], lanes=2)
+    one = q.batched([specs[2]], lanes=1)
+    torch.cuda.synchronize()
+    assert _same(full[5], part[0]) and _same(full[0], part[1]) and _same(full[2], part[2])
+    assert _same(full[2], one[0])
+
+
+def test_batched_ungrouped_equals_standalone_bitwise():
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    specs, exact = _specs(torch)
+    print("batched ungrouped", flush=True)
+    with _tuned(q, batch_grouped=0):
+        res = q.batched(specs, lanes=4)
+        torch.cuda.synchronize()
+        for sp, r in zip(specs, res):
+            assert _same(r, _standalone(q, sp)), (sp["type"], tuple(sp["A"].shape))
 
 
 def test_batched_reports_failing_instance_and_finishes_the_rest():
@@ -130,27 +195,34 @@ def test_batched_reports_failing_instance_and_finishes_the_rest():
                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), infos, stat)
     torch.cuda.synchronize()
     assert st == 1 and stat[1] == 1
-    for i in [0, 2, 3, 4, 5, 6]:
+    clean = q.batched([specs[i] for i in [0, 2, 3, 4, 5, 6]], lanes=3)
+    torch.cuda.synchronize()
+    for j, i in enumerate([0, 2, 3, 4, 5, 6]):
         assert stat[i] == 0
-        assert _same(q._result(outs[i]), _standalone(q, specs[i])), i
+        assert _same(q._result(outs[i]), clean[j]), i
 
 
-def test_server_alone_equals_mix_bitwise():
+@pytest.mark.parametrize("same", [False, True])
+def test_server_alone_equals_mix_bitwise(same):
+    """Every request served alone (one at a time) and served in a mix with all
+    the others (same-shape requests grouped): bitwise the same result, equal
+    to a standalone call; each result is right (planted values, residual and
+    orthogonality of every returned vector)."""
     torch = _torch()
     import paper_2104_14186_amd as q
-    specs, exact = _specs(torch)
+    specs, exact = (_specs_same_shape if same else _specs)(torch)
     print("server alone vs mix", flush=True)
-    with q.Server(arena_bytes=2 << 30, lanes=4) as srv:
-        t = srv.submit(specs[3])
-        alone, info, lat, qms = srv.poll(t)
-        assert lat >= 0 and qms >= 0
-        tickets = [srv.submit(sp) for sp in specs]      # the same problem again, in a mix
+    with q.Server(arena_bytes=2 << 30, lanes=3) as srv:
+        alone = []
+        for sp in specs:
+            r, info, lat, qms = srv.poll(srv.submit(sp))
+            assert lat >= 0 and qms >= 0
+            alone.append(r)
+        tickets = [srv.submit(sp) for sp in specs]      # the same problems again, in a mix
         got = [srv.poll(tk) for tk in tickets]
-    assert _same(got[3][0], alone)
-    for sp, g in zip(specs, got):
+    for sp, g, a in zip(specs, got, alone):
+        assert _same(g[0], a), (sp["type"], tuple(sp["A"].shape))
         assert _same(g[0], _standalone(q, sp)), (sp["type"], tuple(sp["A"].shape))
-    # and each served result is right: values against the planted spectra,
-    # residuals and orthogonality of every returned vector
     _check_planted(specs, exact, [g[0] for g in got])
 
 

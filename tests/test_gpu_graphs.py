@@ -99,9 +99,14 @@ def test_batched_with_graphs_twice():
     specs = [dict(type="eig", A=eig_uniform(n, 50 + n, device=dev)[0], fraction=0.1) for n in (200, 260, 200)]
     print("batched graphs", flush=True)
     o = q.default_opts(graphs=1)
-    r1 = q.batched(specs, lanes=2, opts=o)
-    r2 = q.batched(specs, lanes=2, opts=o)
-    for sp, a, b in zip(specs, r1, r2):
-        alone = q.eig(sp["A"], fraction=sp["fraction"])
-        assert all(bool((x == y).all()) for x, y in zip(a, alone))
-        assert all(bool((x == y).all()) for x, y in zip(b, alone))
+    old = q.tune_get("batch.grouped", 1)
+    q.tune_set("batch.grouped", 0)      # each instance's iterations on its lane, captured
+    try:
+        r1 = q.batched(specs, lanes=2, opts=o)
+        r2 = q.batched(specs, lanes=2, opts=o)
+        for sp, a, b in zip(specs, r1, r2):
+            alone = q.eig(sp["A"], fraction=sp["fraction"])
+            assert all(bool((x == y).all()) for x, y in zip(a, alone))
+            assert all(bool((x == y).all()) for x, y in zip(b, alone))
+    finally:
+        q.tune_set("batch.grouped", old)
