@@ -114,6 +114,36 @@ def batched_leg(q, torch, mix):
             "bitwise_equal_to_standalone": same, "max_rel_value_err": err}
 
 
+def same_shape_leg(q, torch, n=1024, count=16):
+    """count EIG problems of one size n (top 10%, uniform planted spectra):
+    one call at a time, batched with grouped iterations, and batched with
+    every instance on its own lane (batch.grouped = 0)."""
+    from synthetic import eig_uniform
+    dev = torch.device("cuda")
+    specs = [dict(type="eig", A=eig_uniform(n, 42000 + i, device=dev)[0], fraction=0.1) for i in range(count)]
+    q.batched(specs[:2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [q.eig(sp["A"], fraction=sp["fraction"]) for sp in specs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    out = {"problems": count, "n": n, "sequential_s": t_seq}
+    for grouped in (1, 0):
+        q.tune_set("batch.grouped", grouped)
+        q.batched(specs[:2])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = q.batched(specs)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        same = all(all(bool((x == y).all()) for x, y in zip(a, b)) for a, b in zip(seq, res))
+        key = "grouped" if grouped else "per_lane"
+        out[key] = {"s": t, "solves_per_s": count / t, "speedup_vs_sequential": t_seq / t,
+                    "bitwise_equal_to_standalone": same}
+    q.tune_set("batch.grouped", 1)
+    return out
+
+
 def serve_leg(q, torch, mix, trace, precision):
     """The request server, first closed loop (every request submitted at
     once, so the lanes never idle: capacity = requests / span), then the
@@ -132,9 +162,10 @@ def serve_leg(q, torch, mix, trace, precision):
             srv.poll(tk)
         span = time.perf_counter() - t0
         cap = len(mix) / span
-        peak, arena, peak_run = srv.stats(reset=True)
-        out["closed_loop"] = {"solves_per_s": cap, "span_s": span, "arena_peak_bytes": peak,
-                              "peak_running": peak_run}
+        st = srv.stats(reset=True)
+        out["closed_loop"] = {"solves_per_s": cap, "span_s": span, "arena_peak_bytes": st["arena_peak_bytes"],
+                              "peak_running": st["peak_running"], "iteration_groups": st["groups"],
+                              "grouped_requests": st["grouped_requests"]}
         rate = 0.7 * cap
         lat, qms, errs = [], [], []
         t0 = time.perf_counter()
@@ -155,12 +186,14 @@ def serve_leg(q, torch, mix, trace, precision):
             qms.append(qm)
             errs.append(_relerr(spec, res, exact))
         span = time.perf_counter() - t0
-        peak, arena, peak_run = srv.stats()
+        st = srv.stats()
     lat = np.array(lat)
     out["open_loop"] = {"offered_rate_per_s": rate, "solves_per_s": len(lat) / span,
                         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                         "max_ms": float(lat.max()), "mean_queue_ms": float(np.mean(qms)),
-                        "arena_peak_bytes": peak, "arena_bytes": arena, "peak_running": peak_run,
+                        "arena_peak_bytes": st["arena_peak_bytes"], "arena_bytes": st["arena_bytes"],
+                        "peak_running": st["peak_running"], "iteration_groups": st["groups"],
+                        "grouped_requests": st["grouped_requests"],
                         "max_rel_value_err": float(max(errs)), "failed": failed}
     out["trace"] = (f"{len(mix)} requests, Poisson arrivals at 0.7x the closed-loop capacity, 60% EIG / 40% SVD, "
                     "n in {256..4096}, fraction U[1%,20%], SVD kappa 10^U[0,12]")
@@ -515,6 +548,8 @@ def main():
         mix = build_mix(torch, trace)
         print("[bench] batched leg", file=sys.stderr, flush=True)
         out["batched"] = batched_leg(q, torch, mix[:24])
+        print("[bench] same-shape batch leg", file=sys.stderr, flush=True)
+        out["batched_same_shape"] = same_shape_leg(q, torch)
         for prec, key in ((q.FP64, "serving"), (q.MIXED_FP32, "serving_mixed")):
             print(f"[bench] served leg {key}", file=sys.stderr, flush=True)
             out[key] = serve_leg(q, torch, mix, trace, prec)

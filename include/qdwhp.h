@@ -325,15 +325,19 @@ int qdwhp_dgemm_grouped(int count, int transa, int transb, const int64_t* m, con
  * here) and `lanes` worker threads with their own streams (0: the tuned
  * default, "serve.lanes").  submit() queues a problem (the descriptor is
  * copied; its buffers must stay valid until the request finishes) and
- * returns a ticket.  Requests are admitted in FIFO order when a lane is idle
- * and the request's workspace fits in a free range of the arena; admitted
- * requests run concurrently.  A request larger than the arena finishes at
- * once with QDWHP_ERR_WORKSPACE.  poll() returns QDWHP_PENDING while the
- * request runs (wait = 0) or blocks until it finishes (wait != 0); a
- * finished request returns its status, fills info, the latency from submit
- * to results ready and the time it queued (ms, host clock), and its ticket
- * is released.  destroy() finishes every queued request, then frees the
- * arena.  Results equal those of a standalone call bitwise.
+ * returns a ticket.  Requests are admitted in FIFO order when a lane is free
+ * and the request's workspace fits in a free range of the arena.  An
+ * admitted request's phases (setup, DWH iterations, subspace and
+ * Rayleigh-Ritz) are taken by whichever lane is free; the iterations of all
+ * requests of one shape (type, rows, columns) waiting at the same time run
+ * as one group of grouped launches.  A request larger than the arena
+ * finishes at once with QDWHP_ERR_WORKSPACE.  poll() returns QDWHP_PENDING
+ * while the request runs (wait = 0) or blocks until it finishes (wait != 0);
+ * a finished request returns its status, fills info, the latency from
+ * submit to results ready and the time it queued (ms, host clock), and its
+ * ticket is released.  destroy() finishes every queued request, then frees
+ * the arena.  Results equal those of a standalone call bitwise, alone or in
+ * any mix ("serve.grouped" = 0 runs every phase of a request on one lane).
  */
 typedef struct qdwhp_server qdwhp_server;
 int qdwhp_serve_create(size_t arena_bytes, int lanes, const qdwhp_opts* opts, qdwhp_server** srv);
@@ -341,13 +345,16 @@ int qdwhp_serve_submit(qdwhp_server* srv, const qdwhp_problem* p, int64_t* ticke
 int qdwhp_serve_poll(qdwhp_server* srv, int64_t ticket, int wait, qdwhp_info* info,
                      double* latency_ms, double* queue_ms);
 int qdwhp_serve_destroy(qdwhp_server* srv);
-/* High-water marks since creation or the last reset: the largest sum of the
+/* Counters since creation or the last reset: the largest sum of the
  * footprints of requests running at once (bytes of the arena in use, i.e.
- * the server's HBM high-water mark inside its arena), the arena size, and
- * the most requests running at once.  reset != 0 restarts both marks from
- * the current state.  Any pointer may be NULL. */
+ * the server's HBM high-water mark inside its arena), the arena size (open
+ * to requests), the most requests running at once, and the number of
+ * iteration groups run with the number of requests they held (same-shape
+ * requests waiting together share one group).  reset != 0 restarts the
+ * marks from the current state and the group counts from zero.  Any pointer
+ * may be NULL. */
 int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
-                      int reset);
+                      int64_t* groups, int64_t* grouped_requests, int reset);
 
 /* ---- solve without allocation ------------------------------------------ */
 /*

@@ -109,7 +109,7 @@ _SIGS = {
     "qdwhp_serve_submit": (_I, [_P, ctypes.POINTER(Problem), _PI64]),
     "qdwhp_serve_poll": (_I, [_P, _I64, _I, ctypes.POINTER(Info), _PD, _PD]),
     "qdwhp_serve_destroy": (_I, [_P]),
-    "qdwhp_serve_stats": (_I, [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_I), _I]),
+    "qdwhp_serve_stats": (_I, [_P, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_I), _PI64, _PI64, _I]),
     "qdwhp_noalloc_max_bytes": (_SZ, []),
     "qdwhp_eig_noalloc": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, ctypes.POINTER(Opts), _P,
                                ctypes.POINTER(Info)]),
@@ -500,11 +500,14 @@ class Server:
         return _result(out), info.as_dict(), lat.value, q.value
 
     def stats(self, reset=False):
-        """(peak bytes of the arena in use, arena bytes, most requests running at once)."""
+        """dict: peak bytes of the arena in use, arena bytes, most requests
+        running at once, iteration groups run and the requests they held."""
         pk, cap, pr = ctypes.c_size_t(0), ctypes.c_size_t(0), ctypes.c_int(0)
+        gr, gq = ctypes.c_int64(0), ctypes.c_int64(0)
         _check(lib().qdwhp_serve_stats(self._h, ctypes.byref(pk), ctypes.byref(cap), ctypes.byref(pr),
-                                       int(bool(reset))), "qdwhp_serve_stats")
-        return pk.value, cap.value, pr.value
+                                       ctypes.byref(gr), ctypes.byref(gq), int(bool(reset))), "qdwhp_serve_stats")
+        return dict(arena_peak_bytes=pk.value, arena_bytes=cap.value, peak_running=pr.value,
+                    groups=gr.value, grouped_requests=gq.value)
 
     def close(self):
         if self._h:

@@ -113,13 +113,16 @@ struct qdwhp_server {
   int running = 0;               // admitted, not finished
   int peak_running = 0;
   size_t in_use = 0, peak_bytes = 0;
+  int64_t groups = 0, grouped_reqs = 0;   // iteration groups run and their members
+  int nlanes = 0;
   std::vector<std::thread> lanes;
   std::vector<hipStream_t> streams;
 
   // Each lane runs whatever phase is ready, finishing work first: the
-  // subspace and Rayleigh-Ritz phase of an iterated request; else the
-  // iterations of every waiting request with the shape of the oldest one,
-  // as one group; else admission and setup of the next queued request.
+  // subspace and Rayleigh-Ritz phase of an iterated request; else, while
+  // fewer requests than lanes wait for their iterations, admission and setup
+  // of the next queued request; else the iterations of every waiting request
+  // with the shape of the oldest one, as one group.
   void lane_loop(int l) {
     if (hipSetDevice(dev) != hipSuccess) return;
     hipStream_t s = streams[l];
@@ -141,37 +144,11 @@ struct qdwhp_server {
         complete(a, st);
         continue;
       }
-      if (!iter_q.empty()) {
-        const int64_t shape = solve_shape(iter_q.front()->S);
-        grp.clear();
-        for (auto it = iter_q.begin(); it != iter_q.end() && (int)grp.size() < kMaxGroup;) {
-          if (solve_shape((*it)->S) == shape) { grp.push_back(*it); it = iter_q.erase(it); }
-          else ++it;
-        }
-        lk.unlock();
-        bool ok = true;
-        sv.clear();
-        for (Active* a : grp) {
-          ok = ok && hipStreamWaitEvent(s, a->ready, 0) == hipSuccess;
-          sv.push_back(a->S);
-        }
-        try {
-          if (ok) iterations_grouped(sv.data(), (int)sv.size(), table, s);
-        } catch (const HipError&) {
-          ok = false;
-        }
-        for (Active* a : grp) ok = ok && hipEventRecord(a->ready, s) == hipSuccess;
-        if (!ok) (void)hipStreamSynchronize(s);   // nothing may still run in a range that is given back
-        lk.lock();
-        for (Active* a : grp) {
-          if (ok) fin_q.push_back(a);
-          else complete(a, QDWHP_ERR_HIP);
-        }
-        cv_work.notify_all();
-        continue;
-      }
       size_t off = 0;
-      if (!queue.empty() && alloc.take(reqs[queue.front()].bytes, &off)) {
+      // admission runs ahead of the iterations while fewer requests than
+      // lanes wait for them, so that same-shape requests can meet in a group
+      const bool admit_first = (int)iter_q.size() < nlanes;
+      if ((admit_first || iter_q.empty()) && !queue.empty() && alloc.take(reqs[queue.front()].bytes, &off)) {
         const int64_t id = queue.front();
         queue.pop_front();
         Request& r = reqs[id];
@@ -203,6 +180,37 @@ struct qdwhp_server {
         } else {
           complete(a, st);
         }
+        continue;
+      }
+      if (!iter_q.empty()) {
+        const int64_t shape = solve_shape(iter_q.front()->S);
+        grp.clear();
+        for (auto it = iter_q.begin(); it != iter_q.end() && (int)grp.size() < kMaxGroup;) {
+          if (solve_shape((*it)->S) == shape) { grp.push_back(*it); it = iter_q.erase(it); }
+          else ++it;
+        }
+        ++groups;
+        grouped_reqs += (int64_t)grp.size();
+        lk.unlock();
+        bool ok = true;
+        sv.clear();
+        for (Active* a : grp) {
+          ok = ok && hipStreamWaitEvent(s, a->ready, 0) == hipSuccess;
+          sv.push_back(a->S);
+        }
+        try {
+          if (ok) iterations_grouped(sv.data(), (int)sv.size(), table, s);
+        } catch (const HipError&) {
+          ok = false;
+        }
+        for (Active* a : grp) ok = ok && hipEventRecord(a->ready, s) == hipSuccess;
+        if (!ok) (void)hipStreamSynchronize(s);   // nothing may still run in a range that is given back
+        lk.lock();
+        for (Active* a : grp) {
+          if (ok) fin_q.push_back(a);
+          else complete(a, QDWHP_ERR_HIP);
+        }
+        cv_work.notify_all();
         continue;
       }
       if (stop && queue.empty() && running == 0) return;
@@ -256,6 +264,7 @@ extern "C" int qdwhp_serve_create(size_t arena_bytes, int lanes, const qdwhp_opt
     }
     srv->streams.push_back(st);
   }
+  srv->nlanes = L;
   for (int l = 0; l < L; ++l) srv->lanes.emplace_back(&qdwhp_server::lane_loop, srv, l);
   *out = srv;
   return QDWHP_OK;
@@ -304,15 +313,18 @@ extern "C" int qdwhp_serve_poll(qdwhp_server* srv, int64_t ticket, int wait, qdw
 }
 
 extern "C" int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
-                                 int reset) {
+                                 int64_t* groups, int64_t* grouped_requests, int reset) {
   if (!srv) return -1;
   std::lock_guard<std::mutex> g(srv->mu);
   if (peak_bytes) *peak_bytes = srv->peak_bytes;
   if (arena_bytes) *arena_bytes = srv->cap;
   if (peak_running) *peak_running = srv->peak_running;
+  if (groups) *groups = srv->groups;
+  if (grouped_requests) *grouped_requests = srv->grouped_reqs;
   if (reset) {
     srv->peak_bytes = srv->in_use;
     srv->peak_running = srv->running;
+    srv->groups = srv->grouped_reqs = 0;
   }
   return QDWHP_OK;
 }
