@@ -391,7 +391,12 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
  * wanted part, with a margin of max(16, k/32), is at most split_pct percent
  * of them (default 85) are first split exactly at a Lanczos-placed shift by
  * a converged QDWH polar decomposition, and only the wanted block goes to
- * Jacobi).  Unset keys keep
+ * Jacobi), "rr.svd_polar" (SVD Rayleigh-Ritz factors of at least this many
+ * rows, default 256, are decomposed the QDWH-SVD way, Sec. 3.2: a converged
+ * polar decomposition, then the symmetric eigenproblem of its Hermitian
+ * factor; smaller ones, or 0, by one-sided Jacobi), "batch.grouped" and
+ * "serve.grouped" (1, default: the iterations of same-shape instances run
+ * as grouped launches; 0: each on its own lane).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.
  */
 int qdwhp_tune_set(const char* key, int64_t value);

@@ -354,7 +354,7 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
 // Q1 Q2^T as in Eq. (2).  W and Q: 2n x n each; G: n x n; spd:
 // spd_inverse_doubles(n).  ||X||_2 <= 1 is assumed for the shift.
 void cholqr_step(double* X, int64_t n, double a, double b, double c, double* W, double* Q, double* G,
-                 double* spd, int* flag, hipStream_t s) {
+                 double* spd, int* flag, hipStream_t s, bool sym = true) {
   const int64_t n2 = 2 * n;
   stacked(X, n, W, n2, n, n, std::sqrt(c), s);
   double* src = W;
@@ -376,7 +376,60 @@ void cholqr_step(double* X, int64_t n, double a, double b, double c, double* W, 
   f.M = n; f.N = n; f.K = n; f.alpha = (a - b / c) / std::sqrt(c); f.beta = b / c;
   f.A = src; f.lda = n2; f.B = src + n; f.ldb = n2; f.tb = true; f.C = X; f.ldc = n;
   dgemm(f, s);
-  symmetrize(X, n, n, s);
+  if (sym) symmetrize(X, n, n, s);
+}
+
+// The SVD of the Rayleigh-Ritz factor R (ell x ell, ld ell) the QDWH-SVD
+// way (Sec. 3.2): the polar factor U_p of R / alpha (||R|| <= alpha) by the
+// scalar schedule of Sec. 3.1 run to convergence from l0 = 1e-12 (its
+// QR-form steps by the shifted Cholesky QR of cholqr_step, the rest
+// Cholesky-based), H = U_p^T R (symmetric positive semidefinite), the
+// symmetric eigen decomposition H = W diag(sigma) W^T by block Jacobi, and
+// U = U_p W.  Singular values below 1e-12 alpha are left unconverged (their
+// vectors are not asked for).  On success R <- U (ell x ell), vals[0..ell)
+// the singular values (descending), V (ell x ell, ld ell) the right vectors,
+// and it returns the Jacobi sweeps; returns -1 (R untouched) when buf is too
+// small or a pivot fails.  buf: buf_doubles of free device memory.
+int polar_svd(double* R, int64_t ell, double alpha, double* vals, double*& V, double* buf, int64_t buf_doubles,
+              const qdwhp_opts& o, int* flag, hipStream_t s) {
+  const int64_t e2 = ell * ell;
+  const int64_t spdn = spd_inverse_doubles(ell);
+  double* Xp = buf;
+  double* Xnp = Xp + e2;
+  double* Zp = Xnp + e2;
+  double* spd = Zp + e2;            // spd_inverse_doubles(ell) + ell^2 (the step's product)
+  double* W = spd + spdn + e2;      // 2 ell^2
+  double* Q = W + 2 * e2;           // 2 ell^2
+  const int64_t need = 3 * e2 + spdn + e2 + 4 * e2;
+  if (need > buf_doubles || syev_scratch_doubles(ell) > spdn + 5 * e2) return -1;
+  scale_copy(R, ell, Xp, ell, ell, ell, 1.0 / alpha, false, s);
+  StepBufs sb;
+  sb.Z = Zp; sb.spd = spd; sb.W = W; sb.Q = Q; sb.flag = flag;
+  double* X = Xp;
+  double* Xn = Xnp;
+  for (const DwhStep& st : svd_schedule(1e-12, o.kappa_max, false)) {
+    if (st.kind == 1) cholqr_step(X, ell, st.a, st.b, st.c, W, Q, Zp, spd, flag, s, false);
+    else chol_step(X, Xn, ell, ell, st.a, st.b, st.c, false, sb, s);
+  }
+  int hf = 0;
+  QDWHP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  if (hf) {
+    QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    return -1;
+  }
+  // H = U_p^T R, symmetrised; its eigenvectors W land in Xn, U = U_p W in R
+  Gemm h;
+  h.M = ell; h.N = ell; h.K = ell; h.A = X; h.lda = ell; h.ta = true; h.B = R; h.ldb = ell; h.C = Zp; h.ldc = ell;
+  dgemm(h, s);
+  symmetrize(Zp, ell, ell, s);
+  const int sweeps = syev(Zp, ell, ell, vals, Xn, ell, spd, s);
+  if (sweeps < 0) return -1;
+  Gemm u;
+  u.M = ell; u.N = ell; u.K = ell; u.A = X; u.lda = ell; u.B = Xn; u.ldb = ell; u.C = R; u.ldc = ell;
+  dgemm(u, s);
+  V = Xn;
+  return sweeps;
 }
 
 // Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
@@ -960,8 +1013,16 @@ int svd_project(SolveState& S, std::vector<double>& sig, int64_t& ell, int64_t& 
   Ut = P.Z;
   upper_copy(Y, mm, Ut, ell, ell, s);
   S.ev->mark(5, s);
-  Vt = P.big + gesvj_scratch_doubles(ell, ell);
-  const int sweeps = gesvj(Ut, ell, ell, ell, P.vals, Vt, ell, P.big, s);
+  int sweeps = -1;
+  // the small SVD: QDWH-SVD (polar factor, then the symmetric
+  // eigenproblem) above "rr.svd_polar" rows, else one-sided Jacobi
+  const int64_t polar_min = qdwhp_tune_get("rr.svd_polar", 256);
+  if (polar_min > 0 && ell >= polar_min)
+    sweeps = polar_svd(Ut, ell, S.alpha, P.vals, Vt, P.big, P.big_doubles, o, P.flags, s);
+  if (sweeps < 0) {
+    Vt = P.big + gesvj_scratch_doubles(ell, ell);
+    sweeps = gesvj(Ut, ell, ell, ell, P.vals, Vt, ell, P.big, s);
+  }
   S.info->jacobi_sweeps = sweeps;
   if (sweeps < 0) { S.ret(QDWHP_ERR_NOCONV); return 0; }
   sig.resize(ell);

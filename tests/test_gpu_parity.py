@@ -256,3 +256,35 @@ def test_two_step_variant_vs_oracle(n, f, seed, spec):
     assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
     met = oracle.eig_metrics(A, w, V, exact)
     assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met
+
+
+# ------------------------------------------- QDWH-SVD small solve (f1, SVD side)
+@pytest.mark.parametrize("m,n,k,kind", [(600, 400, 40, "log"), (512, 512, 26, "geo"), (400, 700, 35, "log")])
+def test_svd_polar_small_solve_vs_oracle(m, n, k, kind):
+    """The SVD of the Rayleigh-Ritz factor R_Y by QDWH-SVD (Sec. 3.2: a
+    converged QDWH polar decomposition R_Y = U_p H, then the symmetric
+    eigenproblem of H), forced at small sizes, against the oracle (LAPACK SVD
+    of R_Y) and the planted singular values."""
+    torch, q = _gpu()
+    if kind == "geo":
+        A, sig = svd_geometric(m, n, 1001)
+    else:
+        A, sig = svd_loguniform(max(m, n), min(m, n), 1003)
+        if m < n:
+            A = A.T.copy()
+    print(f"svd polar small solve m={m} n={n} k={k}", flush=True)
+    old = q.tune_get("rr.svd_polar", 256)
+    try:
+        q.tune_set("rr.svd_polar", 32)
+        U, S, V, info = q.svd(torch.from_numpy(A).cuda(), k, opts=q.default_opts(tol=TOL_LIB), return_info=True)
+        torch.cuda.synchronize()
+    finally:
+        q.tune_set("rr.svd_polar", old)
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    r = oracle.svd_partial(A, k, tol=TOL_LIB)
+    print(f"  ell={info['ell']} sweeps={info['jacobi_sweeps']}", flush=True)
+    assert np.max(np.abs(S - r["S"]) / r["S"]) < 1e-12
+    met = oracle.svd_metrics(A, U, S, V, sig[:k])
+    assert met["value_rel_max"] < 1e-12 and met["residual"] < 1e-13, met
+    assert max(met["orth_u"], met["orth_v"]) < 1e-12, met
+    assert np.max(np.abs(V - r["V"])) < 1e-8 and np.max(np.abs(U - r["U"])) < 1e-8
