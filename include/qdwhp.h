@@ -356,6 +356,24 @@ int qdwhp_serve_destroy(qdwhp_server* srv);
 int qdwhp_serve_stats(qdwhp_server* srv, size_t* peak_bytes, size_t* arena_bytes, int* peak_running,
                       int64_t* groups, int64_t* grouped_requests, int reset);
 
+/* ---- full spectrum by QDWH-based spectral divide and conquer ---------- */
+/*
+ * All eigenpairs of the symmetric n x n matrix H (device, ld ldh, read only)
+ * by the QDWH-EIG recursion (Sec. 3.2): a shift sigma at the median of the
+ * spectrum (the count of a Lanczos quadrature), the sign function of
+ * (H - sigma I)/alpha by a converged QDWH polar decomposition, orthonormal
+ * bases of the ranges of the two spectral projectors (I +/- sign)/2, and the
+ * same on the two restricted matrices, down to blocks of at most "dc.leaf"
+ * rows (default 512), solved by block Jacobi.  A split whose check fails
+ * (a column of H Q - Q Q^T H Q above 5e-14 ||H||) falls back to Jacobi on
+ * that block.  Outputs: w[n] descending, W (n x n, ld ldw) eigenvectors.
+ * levels (may be NULL) gets the recursion depth reached.  Workspace:
+ * qdwhp_syev_dc_workspace(n) bytes.  Errors as for qdwhp_syev.
+ */
+size_t qdwhp_syev_dc_workspace(int64_t n);
+int qdwhp_syev_dc(const double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw,
+                  void* work, size_t lwork, void* stream, int* levels);
+
 /* ---- solve without allocation ------------------------------------------ */
 /*
  * For callers that cannot allocate device memory (code between graph-capture

@@ -96,6 +96,8 @@ _SIGS = {
     "qdwhp_orgqr": (_I, [_P, _I64, _I64, _I64, _P, _I64, _I64, _P, _I64, _P, _SZ, _P]),
     "qdwhp_syev_workspace": (_SZ, [_I64]),
     "qdwhp_syev": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
+    "qdwhp_syev_dc_workspace": (_SZ, [_I64]),
+    "qdwhp_syev_dc": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
     "qdwhp_gesvj_workspace": (_SZ, [_I64]),
     "qdwhp_gesvj": (_I, [_P, _I64, _I64, _P, _P, _I64, _P, _SZ, _P, ctypes.POINTER(_I)]),
     "qdwhp_problem_workspace": (_SZ, [ctypes.POINTER(Problem), ctypes.POINTER(Opts)]),
@@ -342,6 +344,22 @@ def syev(H):
     _check(lib().qdwhp_syev(_ptr(Hc), n, n, _ptr(w), _ptr(Wb), n, _ptr(ws), nbytes, _stream(torch),
                             ctypes.byref(sw)), "qdwhp_syev")
     return w, Wb.t(), sw.value
+
+
+def syev_dc(H):
+    """All eigenpairs of the symmetric float64 CUDA matrix H by QDWH-based
+    spectral divide and conquer: (w descending, W, recursion depth)."""
+    import torch
+    n = H.shape[0]
+    Hc = H.t().contiguous()
+    w = torch.empty(n, dtype=torch.float64, device=H.device)
+    Wb = torch.empty((n, n), dtype=torch.float64, device=H.device)
+    nbytes = lib().qdwhp_syev_dc_workspace(n)
+    ws = _workspace(torch, nbytes, H.device)
+    lv = ctypes.c_int(0)
+    _check(lib().qdwhp_syev_dc(_ptr(Hc), n, n, _ptr(w), _ptr(Wb), n, _ptr(ws), nbytes, _stream(torch),
+                               ctypes.byref(lv)), "qdwhp_syev_dc")
+    return w, Wb.t(), lv.value
 
 
 def gesvj(R):

@@ -587,6 +587,244 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
 }  // namespace
 
 // ===========================================================================
+// All eigenpairs of a symmetric matrix by QDWH-based spectral divide and
+// conquer (the QDWH-EIG of Sec. 3.2, applied recursively).
+namespace {
+
+struct Bump {
+  double* p = nullptr;
+  int64_t left = 0;
+  double* take(int64_t n) {
+    n = (n + 31) / 32 * 32;      // 256-byte steps
+    if (n > left) throw WorkspaceError{};
+    double* r = p;
+    p += n;
+    left -= n;
+    return r;
+  }
+};
+
+constexpr int kDcSteps = 32;     // Lanczos steps of the shift estimate
+constexpr int kDcVectors = 4;
+
+int64_t dc_node_doubles(int64_t ell) {
+  const int64_t e2 = ell * ell;
+  // polar phase: X, Xn, Z, spd + product, W, Q; then C
+  return 3 * e2 + spd_inverse_doubles(ell) + e2 + 4 * e2 + e2 + 1024;
+}
+
+// Orthonormal basis (ell x r, ld ell) of range(P) for the projector P (ell x
+// ell) of rank r: two subspace passes from a Philox Gaussian block, each
+// orthonormalised by a Cholesky QR round.  gram: r x r, spd:
+// spd_inverse_doubles(r), G, Y: ell x r.
+void projector_basis(const double* P, int64_t ell, int64_t r, uint64_t key, double* Q, double* G, double* Y,
+                     double* gram, double* spd, int* flag, hipStream_t s) {
+  gaussian_fill(G, ell * r, key, 0, s);
+  for (int pass = 0; pass < 2; ++pass) {
+    Gemm g;
+    g.M = ell; g.N = r; g.K = ell; g.A = P; g.lda = ell; g.B = pass ? Q : G; g.ldb = ell; g.C = Y; g.ldc = ell;
+    dgemm(g, s);
+    chol_qr(Y, ell, r, gram, spd, Q, flag, s);
+  }
+}
+
+// Block Q^T H Q (r x r) of H (ell x ell), symmetrised, and the largest
+// column norm of H Q - Q (Q^T H Q) (the split's check); Y: ell x r scratch,
+// gram: r x r scratch.
+double restricted(const double* H, int64_t ell, const double* Q, int64_t r, double* Hr, double* Y, double* gram,
+                  double* dbuf, hipStream_t s) {
+  Gemm g;
+  g.M = ell; g.N = r; g.K = ell; g.A = H; g.lda = ell; g.B = Q; g.ldb = ell; g.C = Y; g.ldc = ell;
+  dgemm(g, s);
+  Gemm h;
+  h.M = r; h.N = r; h.K = ell; h.A = Q; h.lda = ell; h.ta = true; h.B = Y; h.ldb = ell; h.C = Hr; h.ldc = r;
+  dgemm(h, s);
+  symmetrize(Hr, r, r, s);
+  Gemm e;
+  e.M = ell; e.N = r; e.K = r; e.alpha = -1.0; e.beta = 1.0; e.A = Q; e.lda = ell; e.B = Hr; e.ldb = r;
+  e.C = Y; e.ldc = ell;
+  dgemm(e, s);
+  Gemm n2;
+  n2.M = r; n2.N = r; n2.K = ell; n2.A = Y; n2.lda = ell; n2.ta = true; n2.B = Y; n2.ldb = ell;
+  n2.C = gram; n2.ldc = r; n2.tiles = TILES_UPPER;
+  dgemm(n2, s);
+  std::vector<double> cn(r);
+  diagonal(gram, r, r, dbuf, s);
+  QDWHP_HIP(hipMemcpyAsync(cn.data(), dbuf, sizeof(double) * r, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  double worst = 0.0;
+  for (double v : cn) worst = std::max(worst, std::isfinite(v) ? v : 1e300);
+  return std::sqrt(worst);
+}
+
+struct DcStats { int splits = 0, leaves = 0, fallbacks = 0, depth = 0; };
+
+// H (ell x ell, ld ell) symmetric, read only; vals[ell] descending, W (ell x
+// ell, ld ell) eigenvectors.  Returns the largest Jacobi sweep count of its
+// leaves, or -1 if a leaf did not converge.
+int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, const qdwhp_opts& o, int* flag,
+           double* dbuf, int depth, DcStats* st, hipStream_t s) {
+  st->depth = std::max(st->depth, depth);
+  const int64_t leaf = std::max<int64_t>(64, qdwhp_tune_get("dc.leaf", 512));
+  const int64_t e2 = ell * ell;
+  auto jacobi = [&]() {
+    ++st->leaves;
+    double* scr = mem.take(syev_scratch_doubles(ell));
+    return syev(const_cast<double*>(H), ell, ell, vals, W, ell, scr, s);   // syev reads H only
+  };
+  if (ell <= leaf || depth >= 24) return jacobi();
+  Bump m0 = mem;                        // released after the split
+  // ---- shift at the median of the spectrum: a Lanczos quadrature of H
+  const int64_t wsd = skinny_ws_doubles(ell, kDcVectors);
+  double* ws = mem.take(wsd);
+  double* lzb = mem.take(lanczos_doubles(ell, 1, kDcVectors, kDcSteps));
+  LanczosOp op;
+  op.rows_tmp = 1;
+  op.apply = [&](const double* in, int64_t ldi, double* out, int64_t ldo, double*, hipStream_t t) {
+    skinny_gemm(H, ell, ell, ell, in, ldi, kDcVectors, 1.0, out, ldo, ws, wsd, t);
+  };
+  const LanczosResult lz = lanczos(op, ell, kDcVectors, (int)std::min<int64_t>(kDcSteps, ell - 1),
+                                   o.seed + 11 + (uint64_t)depth, lzb, s);
+  if (lz.sweeps < 0) { ++st->fallbacks; mem = m0; return jacobi(); }
+  double lmax = -std::numeric_limits<double>::infinity(), lmin = std::numeric_limits<double>::infinity();
+  for (size_t i = 0; i < lz.nodes.size(); ++i) {
+    lmax = std::max(lmax, lz.nodes[i] + lz.resid[i]);
+    lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
+  }
+  double sigma = 0.0;
+  if (!cut_below(lz.nodes, lz.weights, ell, kDcVectors, lmax, lmin, ell / 2, &sigma)) {
+    ++st->fallbacks; mem = m0; return jacobi();
+  }
+  const double alpha = 1.05 * std::max(lmax - sigma, sigma - lmin);
+  if (!(alpha > 0.0) || !std::isfinite(alpha)) { ++st->fallbacks; mem = m0; return jacobi(); }
+  mem = m0;
+  // ---- X -> sign((H - sigma I) / alpha) by QDWH from l0 = 1e-12
+  double* X = mem.take(e2);
+  double* Xn = mem.take(e2);
+  double* Z = mem.take(e2);
+  double* spd = mem.take(spd_inverse_doubles(ell) + e2);
+  double* Wb = mem.take(2 * e2);
+  double* Qb = mem.take(2 * e2);
+  eig_x0(H, ell, X, ell, ell, 1.0 / alpha, -sigma, -1.0, 0.0, s);
+  StepBufs sb;
+  sb.Z = Z; sb.spd = spd; sb.W = Wb; sb.Q = Qb; sb.flag = flag;
+  for (const DwhStep& d : svd_schedule(1e-12, o.kappa_max, false)) {
+    if (d.kind == 1) cholqr_step(X, ell, d.a, d.b, d.c, Wb, Qb, Z, spd, flag, s);
+    else chol_step(X, Xn, ell, ell, d.a, d.b, d.c, true, sb, s);
+  }
+  // projectors C = (I + X)/2 onto the eigenvalues above sigma and I - C
+  double* C = Xn;
+  double* Cc = Z;
+  half_plus_identity(X, ell, C, ell, ell, s);
+  std::vector<double> dg(ell);
+  diagonal(C, ell, ell, dbuf, s);
+  int hf = 0;
+  QDWHP_HIP(hipMemcpyAsync(dg.data(), dbuf, sizeof(double) * ell, hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  double tr = 0.0;
+  for (double v : dg) tr += v;
+  const int64_t r = std::isfinite(tr) ? (int64_t)std::llround(tr) : -1;
+  if (hf || r <= 0 || r >= ell) {
+    if (hf) QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    ++st->fallbacks;
+    mem = m0;
+    return jacobi();
+  }
+  eig_x0(X, ell, Cc, ell, ell, 0.5, 1.0, 1.0, 0.0, s);   // Cc = (I - X)/2
+  // ---- bases of the two ranges, the two blocks and the check of the split
+  const int64_t r2 = ell - r;
+  double* Q1 = Wb;                        // ell x r
+  double* Q2 = Wb + ell * r;              // ell x r2
+  double* scratchY = Qb;                  // ell x max(r, r2)
+  double* Gb = Qb + e2;                   // ell x max(r, r2)
+  double* gram = X;                       // r x r (X no longer needed)
+  double* spd2 = spd;
+  projector_basis(C, ell, r, o.seed + 21 + (uint64_t)depth * 2, Q1, Gb, scratchY, gram, spd2, flag, s);
+  projector_basis(Cc, ell, r2, o.seed + 22 + (uint64_t)depth * 2, Q2, Gb, scratchY, gram, spd2, flag, s);
+  double* H1 = C;                          // r x r (C no longer needed)
+  double* H2 = Cc;                         // r2 x r2
+  const double hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
+  const double e1 = restricted(H, ell, Q1, r, H1, scratchY, gram, dbuf, s);
+  const double e2n = restricted(H, ell, Q2, r2, H2, scratchY, gram, dbuf, s);
+  QDWHP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  if (hf || !(e1 <= 5e-14 * hnorm) || !(e2n <= 5e-14 * hnorm)) {
+    if (hf) QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    ++st->fallbacks;
+    mem = m0;
+    return jacobi();
+  }
+  ++st->splits;
+  // ---- the two halves: Q1, Q2 (in Wb) and H1, H2 (in Xn, Z) stay; the rest is free
+  Bump rest = m0;
+  rest.take(e2);                            // X
+  rest.take(e2);                            // Xn (H1)
+  rest.take(e2);                            // Z (H2)
+  rest.take(spd_inverse_doubles(ell) + e2);
+  rest.take(2 * e2);                        // Wb (Q1, Q2)
+  double* W1 = rest.take(r * r);
+  double* W2 = rest.take(r2 * r2);
+  const int s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s);
+  if (s1 < 0) return -1;
+  const int s2 = dc_eig(H2, r2, vals + r, W2, rest, o, flag, dbuf, depth + 1, st, s);
+  if (s2 < 0) return -1;
+  // eigenvectors [Q1 W1, Q2 W2]: the eigenvalues above sigma come first
+  Gemm v1;
+  v1.M = ell; v1.N = r; v1.K = r; v1.A = Q1; v1.lda = ell; v1.B = W1; v1.ldb = r; v1.C = W; v1.ldc = ell;
+  dgemm(v1, s);
+  Gemm v2;
+  v2.M = ell; v2.N = r2; v2.K = r2; v2.A = Q2; v2.lda = ell; v2.B = W2; v2.ldb = r2; v2.C = W + ell * r;
+  v2.ldc = ell;
+  dgemm(v2, s);
+  return std::max(s1, s2);
+}
+
+}  // namespace
+
+extern "C" size_t qdwhp_syev_dc_workspace(int64_t n) {
+  if (n < 1) return 0;
+  // a node and, below it, its children; a leaf's Jacobi scratch
+  const int64_t e2 = n * n;
+  return (size_t)(2 * dc_node_doubles(n) + 2 * e2 + syev_scratch_doubles(n) + 4096) * 8;
+}
+
+extern "C" int qdwhp_syev_dc(const double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw,
+                             void* work, size_t lwork, void* stream, int* levels) {
+  if (!H) return -1;
+  if (n < 1) return -2;
+  if (ldh < n) return -3;
+  if (!w) return -4;
+  if (!W) return -5;
+  if (ldw < n) return -6;
+  if (!work) return -7;
+  if (lwork < qdwhp_syev_dc_workspace(n)) return QDWHP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    qdwhp_opts o;
+    qdwhp_opts_default(&o);
+    Bump mem{(double*)work, (int64_t)(lwork / 8)};
+    int* flag = (int*)mem.take(8);
+    double* dbuf = mem.take(n + 64);
+    double* Hc = mem.take(n * n);
+    double* Wc = mem.take(n * n);
+    QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    copy(H, ldh, Hc, n, n, n, s);
+    DcStats st;
+    const int sw = dc_eig(Hc, n, w, Wc, mem, o, flag, dbuf, 0, &st, s);
+    if (levels) *levels = st.depth;
+    if (sw < 0) return QDWHP_ERR_NOCONV;
+    copy(Wc, n, W, ldw, n, n, s);
+    QDWHP_HIP(hipStreamSynchronize(s));
+  } catch (const WorkspaceError&) {
+    return QDWHP_ERR_WORKSPACE;
+  } catch (const HipError&) {
+    return QDWHP_ERR_HIP;
+  }
+  return QDWHP_OK;
+}
+
+// ===========================================================================
 extern "C" size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_opts* opts) {
   (void)fraction;
   if (n < 1) return 0;

@@ -188,3 +188,42 @@ def test_dgemm_tile_size_does_not_change_results(m, n, k, ta, tb, upper):
     if upper:   # only the upper triangle is defined for an upper-tile output
         out = [torch.triu(c.t()) for c in out]
     assert bool((out[0] == out[1]).all())
+
+
+@pytest.mark.parametrize("n,spec,leaf", [(300, "uniform", 64), (1000, "uniform", 128), (1500, "clustered", 256),
+                                         (700, "median_cluster", 128), (900, "uniform", 4096)])
+def test_syev_dc(n, spec, leaf):
+    """Full spectrum by QDWH-based spectral divide and conquer (Sec. 3.2):
+    planted eigenvalues, residual and orthogonality of every eigenvector;
+    a spectrum with a tight cluster at the median makes a split fail its
+    check and fall back to Jacobi on that block."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import eig_uniform, eig_clustered, rng, haar, planted_sym
+    if spec == "uniform":
+        A, lam = eig_uniform(n, 900 + n)
+    elif spec == "clustered":
+        A, lam = eig_clustered(n, 901)
+    else:
+        g = rng(902)
+        Q = haar(g, n)
+        lam = np.concatenate([g.uniform(-1, 1, n // 2), 0.1 + 1e-13 * g.uniform(-1, 1, n - n // 2)])
+        A = planted_sym(Q, lam)
+    print(f"syev_dc n={n} {spec} leaf={leaf}", flush=True)
+    old = q.tune_get("dc.leaf", 512)
+    try:
+        q.tune_set("dc.leaf", leaf)
+        w, W, depth = q.syev_dc(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+    finally:
+        q.tune_set("dc.leaf", old)
+    w, W = w.cpu().numpy(), W.cpu().numpy()
+    print(f"  depth {depth}", flush=True)
+    ex = np.sort(lam)[::-1]
+    scale = np.abs(lam).max()
+    assert np.max(np.abs(w - ex)) / scale < 1e-13
+    R = A @ W - W * w[None, :]
+    assert np.linalg.norm(R, axis=0).max() / scale < 1e-13
+    assert np.abs(W.T @ W - np.eye(n)).max() < 1e-12
+    if leaf < n and spec != "median_cluster":
+        assert depth >= 1
