@@ -49,6 +49,8 @@ def parse():
     p.add_argument("--cpu-budget", type=float, default=150.0,
                    help="the oracle also runs at n = 8192 when 8x its n = 4096 time fits this (s)")
     p.add_argument("--no-workloads", action="store_true", help="skip the other benchmark configurations")
+    p.add_argument("--no-roofline", action="store_true",
+                   help="skip the extra solve with per-launch GEMM events (for counter runs under rocprofv3)")
     p.add_argument("--input", default="", help="load the headline matrix (and *_lam.npy) from this .npy "
                    "instead of generating it on the device")
     p.add_argument("--write-input", default="", help="write the generated headline matrix to this .npy and exit")
@@ -491,11 +493,13 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     d = info.as_dict()
     # roofline of the GEMM kernel: one more solve with per-launch events
-    q.profile_begin()
-    solve()
-    torch.cuda.synchronize()
-    gflops, gms, glaunch = q.profile_end()
-    print("[bench] roofline pass done", file=sys.stderr, flush=True)
+    gflops, gms, glaunch = 0.0, 0.0, 0
+    if not args.no_roofline:
+        q.profile_begin()
+        solve()
+        torch.cuda.synchronize()
+        gflops, gms, glaunch = q.profile_end()
+        print("[bench] roofline pass done", file=sys.stderr, flush=True)
 
     # accuracy of the timed solve: planted values, every returned vector
     exact = np.sort(lam)[::-1][:k]
