@@ -348,9 +348,16 @@ void chol_qr(const double* Y, int64_t rows, int64_t r, double* gram, double* spd
 // W = [sqrt(c) X; I] (2n x n) taken by shifted Cholesky QR in three rounds
 // (one round with the Gram shifted by 11 (2n^2 + n(n+1)) u ||W||^2 so that
 // its Cholesky factor exists for any cond(W) <= 1/u, then two plain
-// rounds, which make Q orthonormal to working accuracy): every round is a
-// Gram, the Cholesky-inverse of Eq. (3)'s step and a triangular product,
-// so the step has no per-column launches.  X+ = (b/c) X + (a - b/c)/sqrt(c)
+// rounds): every round is a Gram, the Cholesky-inverse of Eq. (3)'s step
+// and a triangular product, so the step has no per-column launches.  The
+// published analysis of shifted Cholesky QR proves Q orthonormal to working
+// accuracy only up to a smaller cond(W), which shrinks with the matrix size
+// (about 1e6-1e7 for n near 5000); the first step from l0 = 1e-12 has
+// cond(W) ~ sqrt(1 + c) ~ 1.3e8, beyond it.  There orthogonality is
+// observed, not proved (FP64 emulation: max |Q^T Q - I| = 1.3e-15 at
+// n = 2500).  Callers check the result of the whole polar decomposition
+// (the split's residual test), so a loss of orthogonality costs a fallback
+// to the plain solver, never a wrong result.  X+ = (b/c) X + (a - b/c)/sqrt(c)
 // Q1 Q2^T as in Eq. (2).  W and Q: 2n x n each; G: n x n; spd:
 // spd_inverse_doubles(n).  ||X||_2 <= 1 is assumed for the shift.
 void cholqr_step(double* X, int64_t n, double a, double b, double c, double* W, double* Q, double* G,

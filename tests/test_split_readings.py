@@ -74,6 +74,31 @@ def test_cholesky_qr_steps_reach_the_sign_function(seed):
     assert np.abs(Xc - S).max() < 1e-6 and np.abs(Xh - S).max() < 1e-6
 
 
+def test_cholesky_qr_orthogonality_at_large_size():
+    """The first QR-form step from l0 = 1e-12 (c ~ 1.6e16, cond(W) ~ 1.3e8)
+    at a size where the proved range of shifted Cholesky QR ends below that
+    condition number: Q must still come out orthonormal to working accuracy."""
+    n = 2048
+    g = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(g.standard_normal((n, n)))
+    lam = np.concatenate([np.geomspace(1e-12, 1.0, n // 2), -np.geomspace(1e-12, 1.0, n - n // 2)])
+    X = (Q * lam) @ Q.T
+    X = 0.5 * (X + X.T)
+    st = svd_schedule(1e-12, kappa_max=100.0, qr_first=False)[0]
+    assert st["kind"] == "qr" and st["c"] > 1e16
+    Xn, Qc = _cholqr3_step(X, st["a"], st["b"], st["c"])
+    assert np.abs(Qc.T @ Qc - np.eye(n)).max() < 50 * n * U
+    # and the step matches the oracle's Householder form of Eq. (2): to
+    # working accuracy on the directions of the eigenvalues >= 1e-3, and
+    # everywhere within the rounding amplification of the step itself (its
+    # slope at 0 is a ~ 2.5e8, so an O(u) perturbation of X moves X+ by a u)
+    Xh = qr_step(X, st["a"], st["b"], st["c"])
+    Xh = 0.5 * (Xh + Xh.T)
+    P = Q[:, np.abs(lam) >= 1e-3]
+    assert np.abs(P.T @ (Xn - Xh) @ P).max() < 1e-12
+    assert np.abs(Xn - Xh).max() < 4 * st["a"] * U
+
+
 def test_projector_counts_the_eigenvalues_above_the_shift():
     n = 140
     g = np.random.default_rng(5)
