@@ -11,6 +11,10 @@ constexpr int QB = 128;   // panel width and T-factor block
 struct QrScratch {
   double* part; double* piv; double* G; double* W1; double* W2;
   double* ws; int64_t ws_doubles;
+  // Cholesky-QR / Householder-reconstruction panels: partial Grams, small
+  // factors, failure flag, and a copy of the panel (backup_rows x QB)
+  double* cq_part = nullptr; double* cq_small = nullptr; int* cq_flag = nullptr;
+  double* backup = nullptr; int64_t backup_rows = 0;
 };
 
 int64_t qr_scratch_doubles(int64_t m, int64_t n);
@@ -24,8 +28,12 @@ using PanelWatch = std::function<bool(int64_t c0, int w)>;
 // In-place QR of A (m x n, m >= n): R above, reflectors below, tau[n];
 // per-panel T factors in Tall (QB x QB each, zero below the diagonal).
 // Returns the number of columns factored (n unless `watch` stopped early).
+// recon: factor sub-panels by Cholesky QR with Householder reconstruction
+// where they pass its checks (not while the stream is being captured; the
+// tuning key "qr.recon" = 0 turns it off); the host then waits for the
+// stream once per panel.
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-              const QrScratch& sc, hipStream_t s, const PanelWatch* watch = nullptr);
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch = nullptr, bool recon = true);
 // Q (m x q) = H_1 ... H_upto E, E = columns c0 .. c0+q-1 of the identity.
 // C (m x q) <- H_1 ... H_upto C.
 void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,

@@ -9,6 +9,27 @@
 //    sub-panel applied to the rest of the panel as a blocked update (the
 //    same T / three-GEMM form as the trailing update), so the per-column
 //    launches sweep at most 32 columns;
+//  * sub-panel by Cholesky QR with Householder reconstruction (default when
+//    the stream is not being captured): the sub-panel P (h x 32) is
+//    orthonormalised by two Cholesky-QR passes (P = Q R, R = R2 R1), and the
+//    Householder form of the same factorization is rebuilt from Q: an LU
+//    factorization without pivoting of S - Q1 (Q1 the top 32 x 32 block of
+//    Q, S = diag(+-1) chosen at each elimination step so that the pivot has
+//    magnitude 1 + |.|) gives the unit-lower reflector block Y1 = L and U;
+//    then Y2 = -Q2 U^{-1}, T = U S Y1^{-T}, tau = diag(T) and R_H = S R,
+//    which is exactly the LAPACK-convention Householder QR of P (Ballard,
+//    Demmel, Grigori, Jacquelin, Knight, Nguyen, "Reconstructing Householder
+//    vectors from tall-skinny QR", 2015).  Five launches per sub-panel
+//    instead of one per column.  A sub-panel whose first-pass pivots show a
+//    column within 1e-5 of the span of the earlier ones (relative), or whose
+//    first pass leaves Q^T Q more than 0.1 from I, sets a flag; the host
+//    checks it after each panel, restores the panel from a copy taken
+//    before it and factors it by the column steps below (the panel holding
+//    the first tiny |R_ii| of the projector QR takes this path).  The
+//    second pass and the reconstruction start from the first pass's Q as
+//    stored (Q = Q_1 R2^{-1}, Y2 = -Q2 U^{-1} with Q_1 = P R1^{-1} rounded
+//    once): folding R1^{-1} into a single product with P would carry
+//    rounding of order u cond(P) into Q;
 //  * column step: one launch per column over the whole grid.  Launch j forms
 //    reflector j from column statistics reduced from the previous launch
 //    (norm of the column below the pivot, its dot products with the other
@@ -20,7 +41,10 @@
 //    (split-K GEMM) and the forward recurrence T(0:j,j) = -tau_j T(0:j,0:j) G(0:j,j);
 //  * trailing update C <- (I - V T^T V^T) C as three GEMMs with V read in
 //    place from below the diagonal (unit-lower operand mask).
+#include <algorithm>
+
 #include "common.h"
+#include "qdwhp.h"
 #include "qr.h"
 
 namespace qdwhp {
@@ -275,6 +299,354 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
   }
 }
 
+// ---- sub-panel by Cholesky QR + Householder reconstruction -------------
+constexpr int RB = 32;          // reconstruction block (= QI)
+constexpr int GCH = 64;         // rows staged per chunk of the Gram kernels
+constexpr int NG_MAX = 64;      // workgroups of the row-parallel kernels (partial Grams)
+constexpr int ST = 1024;        // threads of the small (one-workgroup) kernels
+
+// Partial Gram matrices of a sub-panel: workgroup g sums, over its rows
+// [g rows_per, (g+1) rows_per) of P (h x w, w <= 32), the outer products
+// q_r^T q_r with q_r = p_r (APPLY: p_r Rinv, Rinv 32 x 32 upper, ld 32,
+// and q_r is written back over p_r), into part[g] (32 x 32, column-major;
+// entries beyond w are zero).
+template <bool APPLY>
+__global__ __launch_bounds__(256) void tsg_kernel(double* __restrict__ P, int64_t ld, int64_t h, int w,
+                                                  const double* __restrict__ Rinv, double* __restrict__ part,
+                                                  int64_t rows_per) {
+  __shared__ double S[GCH][RB + 1];
+  __shared__ double Ri[APPLY ? RB : 1][RB + 1];
+  const int t = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
+  const int64_t r1 = (r0 + rows_per < h) ? r0 + rows_per : h;
+  if constexpr (APPLY) {
+    for (int e = t; e < RB * RB; e += 256) {
+      const int i = e % RB, j = e / RB;
+      Ri[i][j] = (i <= j && j < w) ? Rinv[i + j * RB] : 0.0;
+    }
+  }
+  const int bi = t % 16, bj = t / 16;            // this thread's 2 x 2 block of the Gram
+  double a00 = 0.0, a01 = 0.0, a10 = 0.0, a11 = 0.0;
+  for (int64_t rb = r0; rb < r1; rb += GCH) {
+#pragma unroll
+    for (int q = 0; q < GCH * RB / 256; ++q) {
+      const int e = t + 256 * q, row = e % GCH, col = e / GCH;
+      const int64_t r = rb + row;
+      S[row][col] = (r < r1 && col < w) ? P[r + (int64_t)col * ld] : 0.0;
+    }
+    __syncthreads();
+    if constexpr (APPLY) {
+      const int row = t >> 2, c0 = (t & 3) * 8;
+      double y[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        double s0 = 0.0, s1 = 0.0;
+        const int cc = c0 + c;
+        int k = 0;
+        for (; k + 1 <= cc; k += 2) { s0 += S[row][k] * Ri[k][cc]; s1 += S[row][k + 1] * Ri[k + 1][cc]; }
+        if (k <= cc) s0 += S[row][k] * Ri[k][cc];
+        y[c] = s0 + s1;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < 8; ++c) S[row][c0 + c] = y[c];
+      __syncthreads();
+      // the first pass's Q replaces P: the second pass and the
+      // reconstruction work from these rounded values (recomputing them
+      // from P, or folding R1^{-1} into a later product, would carry the
+      // rounding of P R1^{-1}, of order u cond(P), into Q)
+#pragma unroll
+      for (int q = 0; q < GCH * RB / 256; ++q) {
+        const int e = t + 256 * q, row2 = e % GCH, col = e / GCH;
+        const int64_t r = rb + row2;
+        if (r < r1 && col < w) P[r + (int64_t)col * ld] = S[row2][col];
+      }
+    }
+    for (int row = 0; row < GCH; ++row) {
+      const double x0 = S[row][2 * bi], x1 = S[row][2 * bi + 1];
+      const double y0 = S[row][2 * bj], y1 = S[row][2 * bj + 1];
+      a00 += x0 * y0; a01 += x0 * y1; a10 += x1 * y0; a11 += x1 * y1;
+    }
+    __syncthreads();
+  }
+  double* o = part + (int64_t)blockIdx.x * RB * RB;
+  o[2 * bi + (2 * bj) * RB] = a00;
+  o[2 * bi + (2 * bj + 1) * RB] = a01;
+  o[2 * bi + 1 + (2 * bj) * RB] = a10;
+  o[2 * bi + 1 + (2 * bj + 1) * RB] = a11;
+}
+
+// Sum of ng (<= NG_MAX) partial Grams into G (LDS), ST threads: each entry
+// by one thread over the partials in a fixed order, 16 loads in flight.
+__device__ void sum_partials(const double* part, int ng, double (*G)[RB + 1]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < RB * RB / ST; ++q) {
+    const int e = t + ST * q;
+    double a[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) a[u] = 0.0;
+    for (int g0 = 0; g0 < ng; g0 += 16) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (g0 + u < ng) a[u] += part[(int64_t)(g0 + u) * RB * RB + e];
+    }
+#pragma unroll
+    for (int h = 8; h > 0; h >>= 1)
+#pragma unroll
+      for (int u = 0; u < h; ++u) a[u] += a[u + h];
+    G[e % RB][e / RB] = a[0];
+  }
+  __syncthreads();
+}
+
+// Upper Cholesky factor R (G = R^T R, G's upper triangle) of the leading
+// w x w block, G overwritten (LDS).  A pivot at or below rel * G(k,k), or
+// not finite, counts as a failure and is replaced by G(k,k) (or 1) so that
+// everything stays finite.  One barrier per step: step k reads row k of the
+// working matrix, updates the rows below it and writes row k of R (a
+// separate array), so no entry is read and written in the same step.
+// Returns the failure on every thread.  ST threads.
+__device__ bool small_chol(double (*G)[RB + 1], double (*R)[RB + 1], int w, double rel) {
+  const int t = threadIdx.x;
+  __shared__ double d0[RB];
+  __shared__ int bad;
+  if (t == 0) bad = 0;
+  if (t < RB) d0[t] = (t < w) ? G[t][t] : 1.0;
+  for (int e = t; e < RB * RB; e += ST) R[e % RB][e / RB] = 0.0;
+  __syncthreads();
+  for (int k = 0; k < w; ++k) {
+    double piv = G[k][k];
+    const double ref = d0[k];
+    const bool fail = !(piv > rel * ref) || !(ref > 0.0) || !isfinite(piv);
+    if (fail) piv = (ref > 0.0 && isfinite(ref)) ? ref : 1.0;
+    const double rk = sqrt(piv), rinv = 1.0 / rk, pinv = 1.0 / piv;
+    if (t == 0 && fail) bad = 1;
+    for (int e = t; e < RB * RB; e += ST) {
+      const int i = e % RB, j = e / RB;
+      if (j < w && i <= j && i >= k) {
+        if (i == k) R[k][j] = (j == k) ? rk : G[k][j] * rinv;
+        else G[i][j] -= G[k][i] * G[k][j] * pinv;
+      }
+    }
+    __syncthreads();
+  }
+  return bad != 0;
+}
+
+// Inverse of the upper triangular w x w block of R into Ri (zeros
+// elsewhere): thread j back-substitutes column j.
+__device__ void small_upper_inv(double (*R)[RB + 1], double (*Ri)[RB + 1], int w) {
+  const int t = threadIdx.x;
+  for (int e = t; e < RB * RB; e += ST) Ri[e % RB][e / RB] = 0.0;
+  __syncthreads();
+  if (t < w) {
+    const int j = t;
+    Ri[j][j] = 1.0 / R[j][j];
+    for (int i = j - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int p = i + 1; p <= j; ++p) s += R[i][p] * Ri[p][j];
+      Ri[i][j] = -s / R[i][i];
+    }
+  }
+  __syncthreads();
+}
+
+// Pass-one factor: R1 and R1^{-1} (32 x 32, ld 32) from the partial Grams.
+// first: this is the panel's first sub-panel (the flag is reset, else only set).
+__global__ __launch_bounds__(ST) void cq_chol_kernel(const double* __restrict__ part, int ng, int w,
+                                                      double* __restrict__ R1, double* __restrict__ R1inv,
+                                                      int* flag, int first) {
+  __shared__ double G[RB][RB + 1];
+  __shared__ double R[RB][RB + 1];
+  __shared__ double Ri[RB][RB + 1];
+  const int t = threadIdx.x;
+  sum_partials(part, ng, G);
+  const bool bad = small_chol(G, R, w, 1e-10);
+  small_upper_inv(R, Ri, w);
+  for (int e = t; e < RB * RB; e += ST) {
+    R1[e] = R[e % RB][e / RB];
+    R1inv[e] = Ri[e % RB][e / RB];
+  }
+  if (t == 0) {
+    if (first) *flag = bad ? 1 : 0;
+    else if (bad) *flag = 1;
+  }
+}
+
+// Pass two and the reconstruction (one workgroup; see the file comment).
+// P: the sub-panel's top-left corner, holding the first pass's Q (its first
+// w rows are the top block).  With R2 the factor of the second Gram:
+// Q = P R2^{-1}, W = S - Q1 = L U (signs chosen during the elimination).
+// Outputs: Nm = -R2^{-1} U^{-1} (32 x 32, ld 32, upper; Y2 = P2 Nm), RL
+// (32 x 32: R_H = S R2 R1 on and above the diagonal, L below), T (w x w
+// upper in the panel's T slot, ld QB) and tau (w).
+__global__ __launch_bounds__(ST) void cq_recon_kernel(const double* __restrict__ part, int ng, int w,
+                                                       const double* __restrict__ R1g,
+                                                       const double* __restrict__ P, int64_t ld,
+                                                       double* __restrict__ Nm, double* __restrict__ RL,
+                                                       double* __restrict__ T, double* __restrict__ tau,
+                                                       int* flag) {
+  __shared__ double A[RB][RB + 1];      // G2, then U^{-1}
+  __shared__ double B[RB][RB + 1];      // R2, then U
+  __shared__ double C[RB][RB + 1];      // R2^{-1}
+  __shared__ double D[RB][RB + 1];      // R1, then L^{-1}
+  __shared__ double Rm[RB][RB + 1];     // R = R2 R1
+  __shared__ double W[RB][RB + 1];      // -Q1 -> L (below) / U (on and above)
+  __shared__ double Pt[RB][RB + 1];     // the top block of the first pass's Q, then L
+  __shared__ double sg[RB], ud[RB];
+  __shared__ double red[ST];
+  const int t = threadIdx.x;
+  sum_partials(part, ng, A);
+  // distance of pass one's Q from orthonormal
+  double dev = 0.0;
+  for (int e = t; e < w * w; e += ST) {
+    const int i = e % w, j = e / w;
+    dev = fmax(dev, fabs(A[i][j] - (i == j ? 1.0 : 0.0)));
+  }
+  red[t] = dev;
+  __syncthreads();
+  for (int sft = ST / 2; sft > 0; sft >>= 1) {
+    if (t < sft) red[t] = fmax(red[t], red[t + sft]);
+    __syncthreads();
+  }
+  bool bad = !(red[0] <= 0.1);
+  __syncthreads();
+  bad = small_chol(A, B, w, 0.5) || bad;
+  small_upper_inv(B, C, w);
+  for (int e = t; e < RB * RB; e += ST) {
+    const int i = e % RB, j = e / RB;
+    D[i][j] = R1g[e];
+    Pt[i][j] = (i < w && j < w) ? P[i + (int64_t)j * ld] : 0.0;
+  }
+  __syncthreads();
+  // R = R2 R1; W = -Q1 = -P1 R2^{-1}
+  for (int e = t; e < RB * RB; e += ST) {
+    const int i = e % RB, j = e / RB;
+    double r = 0.0, q = 0.0;
+    if (i < w && j < w) {
+      if (i <= j)
+        for (int k = i; k <= j; ++k) r += B[i][k] * D[k][j];
+      for (int k = 0; k <= j; ++k) q += Pt[i][k] * C[k][j];
+    }
+    Rm[i][j] = r;
+    W[i][j] = -q;
+  }
+  __syncthreads();
+  double (*Lo)[RB + 1] = Pt;            // Pt is no longer needed
+  // LU of S - Q1 without pivoting, S(i) chosen at step i: U(i,i) = S(i) + c
+  // with S(i) = sign(c), c the updated (i,i) entry of -Q1.  One barrier per
+  // step: U(k,k) goes to ud, column k of L to Lo (separate arrays), so the
+  // entries read in step k are not written in it.
+  for (int k = 0; k < w; ++k) {
+    const double c = W[k][k];
+    const double sk = (c >= 0.0) ? 1.0 : -1.0;
+    const double ukk = sk + c, uinv = 1.0 / ukk;
+    if (t == 0) { sg[k] = sk; ud[k] = ukk; }
+    for (int e = t; e < RB * RB; e += ST) {
+      const int i = e % RB, j = e / RB;
+      if (i > k && i < w && j >= k && j < w) {
+        if (j == k) Lo[i][k] = W[i][k] * uinv;
+        else W[i][j] -= W[i][k] * W[k][j] * uinv;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < RB * RB; e += ST) {
+    const int i = e % RB, j = e / RB;
+    if (i < w && j < w) {
+      if (i == j) W[i][i] = ud[i];
+      else if (i > j) W[i][j] = Lo[i][j];
+    }
+  }
+  __syncthreads();
+  // U^{-1} into A (the upper part of W is U)
+  for (int e = t; e < RB * RB; e += ST) {
+    const int i = e % RB, j = e / RB;
+    B[i][j] = (i <= j && j < w) ? W[i][j] : 0.0;
+  }
+  __syncthreads();
+  small_upper_inv(B, A, w);
+  // L^{-1} (unit lower) into D: thread j forward-substitutes column j
+  for (int e = t; e < RB * RB; e += ST) D[e % RB][e / RB] = 0.0;
+  __syncthreads();
+  if (t < w) {
+    const int j = t;
+    D[j][j] = 1.0;
+    for (int i = j + 1; i < w; ++i) {
+      double s = 0.0;
+      for (int p = j; p < i; ++p) s += W[i][p] * D[p][j];
+      D[i][j] = -s;
+    }
+  }
+  __syncthreads();
+  // outputs
+  for (int e = t; e < RB * RB; e += ST) {
+    const int i = e % RB, j = e / RB;
+    double nm = 0.0, tv = 0.0, rl = 0.0;
+    if (i < w && j < w) {
+      if (i <= j) {
+        for (int k = i; k <= j; ++k) nm -= C[i][k] * A[k][j];
+        // T(i,j) = sum_k U(i,k) S(k) Linv(j,k), k in [i, j]
+        for (int k = i; k <= j; ++k) tv += W[i][k] * sg[k] * D[j][k];
+        rl = sg[i] * Rm[i][j];
+      } else {
+        rl = W[i][j];
+      }
+    }
+    Nm[e] = nm;
+    RL[e] = rl;
+    if (i < w && j < w) T[i + (int64_t)j * QB] = tv;
+    if (i == j && i < w) tau[i] = tv;
+  }
+  if (t == 0 && bad) *flag = 1;
+}
+
+// Writes the reconstructed sub-panel unless the flag is set: rows below the
+// first w (the first pass's Q) become Y2 = Q2 Nm, the first w rows R_H
+// (upper) and L (below).  Four threads per row, each writing 8 columns;
+// workgroup g takes rows [64 g, 64 g + 64).
+__global__ __launch_bounds__(256) void cq_write_kernel(double* __restrict__ P, int64_t ld, int64_t h, int w,
+                                                       const double* __restrict__ Nm,
+                                                       const double* __restrict__ RL, const int* flag) {
+  if (*flag) return;
+  __shared__ double Ns[RB][RB + 1];
+  const int t = threadIdx.x;
+  for (int e = t; e < RB * RB; e += 256) Ns[e % RB][e / RB] = Nm[e];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 64 + (t >> 2);
+  const int c0 = (t & 3) * 8;
+  if (r >= h) return;
+  if (r < w) {
+#pragma unroll
+    for (int c = c0; c < c0 + 8; ++c)
+      if (c < w) P[r + (int64_t)c * ld] = RL[r + c * RB];
+    return;
+  }
+  double x[RB];
+#pragma unroll
+  for (int c = 0; c < RB; ++c) x[c] = (c < w) ? P[r + (int64_t)c * ld] : 0.0;
+  // Nm is upper triangular with zeros stored below: the full sums give the
+  // triangular product, and every y depends on every loaded x
+  double y[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < RB; k += 2) {
+      s0 += x[k] * Ns[k][c0 + u];
+      s1 += x[k + 1] * Ns[k + 1][c0 + u];
+    }
+    y[u] = s0 + s1;
+  }
+  // The four threads of a row are lanes of one wave, and every store's
+  // value depends on all 32 loads of the row, so all of them have read the
+  // row before any of them overwrites it.
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (c0 + u < w) P[r + (int64_t)(c0 + u) * ld] = y[u];
+}
+
 // T (w x w, upper) of the compact WY form from G = V^T V and tau:
 // T(j,j) = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) G(0:j, j).  One LDS array
 // holds G above the diagonal and T^T on and below it.
@@ -286,12 +658,13 @@ __global__ __launch_bounds__(QT) void qr_col_kernel(Panel a, int j) {
 //      then -T1 Y (T1 upper), 32 columns of Y at a time in LDS.
 // The recurrence alone would leave row 0 a chain of w^2/2 dependent steps.
 constexpr int TL = 32;
-__global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
+constexpr int BTT = 1024;       // threads of build_t_kernel
+__global__ __launch_bounds__(BTT) void build_t_kernel(const double* G, int64_t ldg, const double* tau,
                                                      double* T, int64_t ldt, int w) {
   __shared__ double L[QB][QB];          // row pitch QB: the diagonal walk of step 1 has odd stride
   __shared__ double Ys[2 * TL][TL + 1];
   const int t = threadIdx.x;
-  for (int e = t; e < w * w; e += QB) {   // only the w x w corner is used
+  for (int e = t; e < w * w; e += BTT) {   // only the w x w corner is used
     const int r = e % w, c = e / w;
     L[r][c] = (r < c) ? G[r + (int64_t)c * ldg] : 0.0;
   }
@@ -319,7 +692,7 @@ __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ld
     const int ncombo = (QB / (2 * sz)) < 1 ? 1 : QB / (2 * sz);
     for (int cb = 0; cb < sz; cb += TL) {
       // Y(r, c) = sum_{k <= c} G(a0 + r, a0 + sz + k) T(a0 + sz + k, a0 + sz + c)
-      for (int e = t; e < ncombo * sz * TL; e += QB) {
+      for (int e = t; e < ncombo * sz * TL; e += BTT) {
         const int cc = e % TL, r = (e / TL) % sz, q = e / (TL * sz);
         const int a0 = q * 2 * sz, c = cb + cc;
         if (a0 + sz + c >= w) continue;
@@ -337,7 +710,7 @@ __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ld
       }
       __syncthreads();
       // T(a0 + r, a0 + sz + c) = -sum_{k >= r} T(a0 + r, a0 + k) Y(k, c)
-      for (int e = t; e < ncombo * sz * TL; e += QB) {
+      for (int e = t; e < ncombo * sz * TL; e += BTT) {
         const int cc = e % TL, r = (e / TL) % sz, q = e / (TL * sz);
         const int a0 = q * 2 * sz, c = cb + cc;
         if (a0 + sz + c >= w) continue;
@@ -356,7 +729,7 @@ __global__ __launch_bounds__(QB) void build_t_kernel(const double* G, int64_t ld
       __syncthreads();
     }
   }
-  for (int e = t; e < w * w; e += QB) {
+  for (int e = t; e < w * w; e += BTT) {
     const int r = e % w, c = e / w;
     T[r + (int64_t)c * ldt] = (r <= c) ? L[c][r] : 0.0;
   }
@@ -371,14 +744,15 @@ __global__ void eye_cols_kernel(double* Q, int64_t m, int64_t q, int64_t ldq, in
 }  // namespace
 
 int64_t qr_scratch_doubles(int64_t m, int64_t n) {
-  (void)m;
   const int64_t nn = n > 1 ? n : 1;
-  return 2 * 64 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256;
+  const int64_t mm = m > 1 ? m : 1;
+  return 2 * 64 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256 +
+         (int64_t)NG_MAX * RB * RB + 4 * RB * RB + 64 + QB * mm;
 }
 
 QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
-  (void)m;
   const int64_t nn = n > 1 ? n : 1;
+  const int64_t mm = m > 1 ? m : 1;
   QrScratch s;
   s.part = w; w += 2 * 64 * QB;
   s.piv = w; w += 2 * QB;
@@ -386,6 +760,11 @@ QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
   s.W1 = w; w += QB * nn;
   s.W2 = w; w += QB * nn;
   s.ws = w; s.ws_doubles = 64 * QB * QB + 8 * QB * nn;
+  w += s.ws_doubles + 256;
+  s.cq_part = w; w += (int64_t)NG_MAX * RB * RB;
+  s.cq_small = w; w += 4 * RB * RB;
+  s.cq_flag = reinterpret_cast<int*>(w); w += 64;
+  s.backup = w; s.backup_rows = mm;
   return s;
 }
 
@@ -400,7 +779,7 @@ void build_t(const double* V, int64_t h, int w, int64_t ld, const double* tau, d
   g.B = V; g.ldb = ld; g.b_unit_lower = true; g.C = sc.G; g.ldc = QB;
   g.ws = sc.ws; g.ws_doubles = sc.ws_doubles;
   dgemm(g, s);
-  build_t_kernel<<<1, QB, 0, s>>>(sc.G, QB, tau, T, QB, w);
+  build_t_kernel<<<1, BTT, 0, s>>>(sc.G, QB, tau, T, QB, w);
   QDWHP_LAUNCH_CHECK();
 }
 
@@ -424,18 +803,73 @@ void apply_qt(const double* V, int64_t h, int w, int64_t ld, const double* T, do
 
 }  // namespace
 
+namespace {
+
+// Sub-panels of one panel by Cholesky QR with Householder reconstruction
+// (V: the panel, h x w); sub-panel T factors go to the panel's T slot.
+// Returns false when a sub-panel failed its checks (the panel is then
+// partly overwritten and must be restored by the caller).
+bool panel_recon(double* V, int64_t h, int w, int64_t lda, double* tau, double* T, const QrScratch& sc,
+                 hipStream_t s) {
+  double* R1 = sc.cq_small;
+  double* R1inv = R1 + RB * RB;
+  double* Nm = R1inv + RB * RB;
+  double* RL = Nm + RB * RB;
+  for (int j0 = 0; j0 < w; j0 += QI) {
+    const int wi = (w - j0) < QI ? (w - j0) : QI;
+    double* P = V + j0 + j0 * lda;
+    const int64_t hp = h - j0;
+    const int ng = (int)std::min<int64_t>(NG_MAX, cdiv(hp, GCH));
+    const int64_t rows_per = cdiv(hp, ng);
+    tsg_kernel<false><<<ng, 256, 0, s>>>(P, lda, hp, wi, nullptr, sc.cq_part, rows_per);
+    QDWHP_LAUNCH_CHECK();
+    cq_chol_kernel<<<1, ST, 0, s>>>(sc.cq_part, ng, wi, R1, R1inv, sc.cq_flag, j0 == 0 ? 1 : 0);
+    QDWHP_LAUNCH_CHECK();
+    tsg_kernel<true><<<ng, 256, 0, s>>>(P, lda, hp, wi, R1inv, sc.cq_part, rows_per);
+    QDWHP_LAUNCH_CHECK();
+    cq_recon_kernel<<<1, ST, 0, s>>>(sc.cq_part, ng, wi, R1, P, lda, Nm, RL, T, tau + j0, sc.cq_flag);
+    QDWHP_LAUNCH_CHECK();
+    cq_write_kernel<<<(unsigned)cdiv(hp, 64), 256, 0, s>>>(P, lda, hp, wi, Nm, RL, sc.cq_flag);
+    QDWHP_LAUNCH_CHECK();
+    const int rest = w - j0 - wi;
+    if (rest > 0) apply_qt(P, hp, wi, lda, T, P + (int64_t)wi * lda, rest, sc, s);
+  }
+  int hf = 0;
+  QDWHP_HIP(hipMemcpyAsync(&hf, sc.cq_flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  QDWHP_HIP(hipStreamSynchronize(s));
+  return hf == 0;
+}
+
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
+  return st != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
+
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-              const QrScratch& sc, hipStream_t s, const PanelWatch* watch) {
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch, bool recon) {
+  const bool use_recon = recon && sc.cq_part && qdwhp_tune_get("qr.recon", 1) != 0 && !stream_capturing(s);
   for (int64_t c0 = 0; c0 < n; c0 += QB) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
     const int64_t h = m - c0;
     double* V = A + c0 + c0 * lda;
     double* T = Tall + (c0 / QB) * QB * QB;
-    // The panel itself is factored in sub-panels of QI columns: the column
+    bool done = false;
+    if (use_recon && h <= sc.backup_rows) {
+      QDWHP_HIP(hipMemcpy2DAsync(sc.backup, h * sizeof(double), V, lda * sizeof(double), h * sizeof(double),
+                                 w, hipMemcpyDeviceToDevice, s));
+      done = panel_recon(V, h, w, lda, tau + c0, T, sc, s);
+      if (!done)
+        QDWHP_HIP(hipMemcpy2DAsync(V, lda * sizeof(double), sc.backup, h * sizeof(double), h * sizeof(double),
+                                   w, hipMemcpyDeviceToDevice, s));
+    }
+    // The panel by column steps, in sub-panels of QI columns: the column
     // launches only sweep their sub-panel, and each finished sub-panel's
     // reflectors reach the rest of the panel as one blocked update (its T is
     // built in the panel's T slot, which the panel's own T overwrites below).
-    for (int j0 = 0; j0 < w; j0 += QI) {
+    for (int j0 = 0; !done && j0 < w; j0 += QI) {
       const int wi = (w - j0) < QI ? (w - j0) : QI;
       Panel p;
       p.P = V + j0 + j0 * lda; p.ld = lda; p.h = h - j0; p.w = wi;

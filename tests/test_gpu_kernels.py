@@ -89,6 +89,67 @@ def test_qr(m, n):
     assert np.abs(np.abs(np.diag(R)) - np.abs(np.diag(Rl))).max() < 1e-12 * np.abs(Rl).max()
 
 
+def _qr_path(q, torch, A, recon):
+    old = q.tune_get("qr.recon", 1)
+    q.tune_set("qr.recon", recon)
+    try:
+        Q, R, tau = q.qr(torch.from_numpy(A).cuda())
+        torch.cuda.synchronize()
+    finally:
+        q.tune_set("qr.recon", old)
+    return Q.cpu().numpy(), R.cpu().numpy(), tau.cpu().numpy()
+
+
+@pytest.mark.parametrize("m,n,kind", [(2000, 300, "gauss"), (517, 517, "gauss"), (3000, 700, "graded"),
+                                      (1200, 400, "dependent"), (800, 800, "projector")])
+def test_qr_reconstructed_panels_match_column_steps(m, n, kind):
+    """Sub-panels by Cholesky QR with Householder reconstruction give the
+    LAPACK-convention Householder factorization of the column steps (same
+    R, reflectors and tau to rounding); panels that fail the checks (exactly
+    dependent columns, the projector's rank drop) are restored and redone by
+    the column steps."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(m + 7 * n)
+    A = g.standard_normal((m, n))
+    if kind == "graded":
+        A = A * np.geomspace(1.0, 1e-4, n)[None, :]
+    elif kind == "dependent":
+        A[:, 200:230] = A[:, 10:40] @ g.standard_normal((30, 30))     # rank drop inside a panel
+    elif kind == "projector":
+        Qh, _ = np.linalg.qr(g.standard_normal((n, n)))
+        d = np.concatenate([np.ones(n - 150), np.geomspace(0.3, 1e-15, 150)])
+        A = (Qh * d) @ Qh.T
+    print(f"qr recon vs column steps m={m} n={n} {kind}", flush=True)
+    Q1, R1, t1 = _qr_path(q, torch, A, 1)
+    Q0, R0, t0 = _qr_path(q, torch, A, 0)
+    sc = np.abs(A).max()
+    for name, Q, R in (("reconstructed", Q1, R1), ("column steps", Q0, R0)):
+        res, orth = np.abs(Q @ R - A).max() / sc, np.abs(Q.T @ Q - np.eye(n)).max()
+        print(f"  {name}: residual {res:.2e} orthogonality {orth:.2e}", flush=True)
+        assert res < 4e-15 * np.sqrt(m)
+        assert orth < 4e-15 * np.sqrt(m)
+    if kind in ("gauss", "graded"):
+        # full rank: the two factorizations agree entry by entry, up to the
+        # sign of the last row of a square matrix (the column steps keep
+        # R(n,n) with tau = 0 there, the reconstruction reflects it, tau = 2:
+        # both are Householder factorizations)
+        D = np.sign(np.diag(R1)) * np.sign(np.diag(R0))
+        flips = np.nonzero(D < 0)[0]
+        assert len(flips) == 0 or (m == n and list(flips) == [n - 1])
+        assert np.abs(D[:, None] * R1 - R0).max() < 1e-12 * sc * np.sqrt(m)
+        assert np.abs(t1[D > 0] - t0[D > 0]).max() < 1e-12
+        assert np.abs(Q1 * D[None, :] - Q0).max() < 1e-11
+    else:
+        # rank drop: |R_ii| agree up to the first rounding-level one (after
+        # it the reflectors of the dependent columns are rounding noise and
+        # the later R_ii are not determined by A)
+        d1, d0 = np.abs(np.diag(R1)), np.abs(np.diag(R0))
+        first = int(np.argmax(d0 < 1e-8 * sc))
+        assert first > 0 and d1[first] < 1e-8 * sc
+        assert np.abs(d1[:first] - d0[:first]).max() < 1e-12 * sc * np.sqrt(m)
+
+
 @pytest.mark.parametrize("n,c0", [(300, 170), (700, 300)])
 def test_qr_trailing_columns(n, c0):
     """Columns c0.. of Q of a square matrix (the Q2 of the projector)."""

@@ -92,6 +92,43 @@ def test_eig_rr_split_vs_oracle(n, f, seed, which, kind, replay):
         assert np.max(np.abs(V - r["V"])) < 1e-9
 
 
+@pytest.mark.timeout(900)
+def test_eig_default_tuning_at_10240_vs_oracle():
+    """Default tuning, unforced: n = 10240, top 20% of the clustered spectrum
+    runs the 128-wide GEMM tiles, the multi-panel QR (Cholesky-QR panels)
+    and, with ell >= 3000, the exact split of the Rayleigh-Ritz matrix,
+    against the oracle and the planted spectrum."""
+    torch, q = _gpu()
+    n, f = 10240, 0.2
+    A, lam = eig_clustered(n, 1002)
+    print(f"eig default tuning n={n} f={f}", flush=True)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=q.default_opts(tol=TOL_LIB),
+                       return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    print(f"  gpu done: ell={info['ell']} split={info['rr_split']}; running the oracle", flush=True)
+    r = oracle.eig_partial(A, fraction=f, tol=TOL_LIB)
+    k = r["k"]
+    print(f"  k={k} ell gpu {info['ell']} oracle {r['ell']}", flush=True)
+    assert info["k"] == k
+    assert k <= info["rr_split"] < info["ell"]          # the split ran, unforced
+    assert abs(info["tau"] - r["tau"]) < 1e-8
+    assert info["kinds"] == [st["kind"] for st in r["sched"]]
+    assert abs(info["ell"] - r["ell"]) <= 2
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+    assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["residual"] < 1e-13, met
+    assert met["orth"] < 1e-12, met
+    # eigenvalues isolated by more than 1e-6 of the spread (the uniform part
+    # of the spectrum): the vectors themselves agree
+    gaps = np.minimum(np.abs(np.diff(np.concatenate([[np.inf], r["w"]]))),
+                      np.abs(np.diff(np.concatenate([r["w"], [-np.inf]]))))
+    sel = gaps > 2e-6
+    assert sel.sum() > k // 4
+    assert np.max(np.abs(V[:, sel] - r["V"][:, sel])) < 1e-7
+
+
 def test_eig_replay_intermediates():
     """Same tau / mu / rho / kinds on both sides: ell and Ritz values agree."""
     torch, q = _gpu()
