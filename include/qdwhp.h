@@ -414,7 +414,12 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
  * polar decomposition, then the symmetric eigenproblem of its Hermitian
  * factor; smaller ones, or 0, by one-sided Jacobi), "batch.grouped" and
  * "serve.grouped" (1, default: the iterations of same-shape instances run
- * as grouped launches; 0: each on its own lane).  Unset keys keep
+ * as grouped launches; 0: each on its own lane), "qr.recon" (1, default:
+ * Householder QR panels by Cholesky QR with Householder reconstruction
+ * where they pass its checks; 0: one launch per column), "qr.stacked" (1,
+ * default: the QR of [sqrt(c) X; I] in a QR-based step skips the rows of
+ * the identity block that no reflector has reached; 0: the full stacked
+ * matrix).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.
  */
 int qdwhp_tune_set(const char* key, int64_t value);

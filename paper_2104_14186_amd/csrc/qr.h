@@ -32,13 +32,19 @@ using PanelWatch = std::function<bool(int64_t c0, int w)>;
 // where they pass its checks (not while the stream is being captured; the
 // tuning key "qr.recon" = 0 turns it off); the host then waits for the
 // stream once per panel.
+// stacked > 0: A is [A1; I] with A1 the first `stacked` rows and an n x n
+// identity below (the QR-based step's [sqrt(c) X; I]); panels and updates
+// then skip the rows of the identity block no reflector has reached yet
+// (pass the same value to apply_q / orgqr).
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-              const QrScratch& sc, hipStream_t s, const PanelWatch* watch = nullptr, bool recon = true);
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch = nullptr, bool recon = true,
+              int64_t stacked = 0);
 // Q (m x q) = H_1 ... H_upto E, E = columns c0 .. c0+q-1 of the identity.
 // C (m x q) <- H_1 ... H_upto C.
 void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
-             double* C, int64_t q, int64_t ldc, const QrScratch& sc, hipStream_t s);
+             double* C, int64_t q, int64_t ldc, const QrScratch& sc, hipStream_t s, int64_t stacked = 0);
 void orgqr(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
-           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s);
+           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s,
+           int64_t stacked = 0);
 
 }  // namespace qdwhp

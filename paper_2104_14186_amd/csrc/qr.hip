@@ -805,6 +805,16 @@ void apply_qt(const double* V, int64_t h, int w, int64_t ld, const double* T, do
 
 namespace {
 
+// Rows a panel at column c0 (w columns) touches.  For a stacked matrix
+// [A; I] (stacked = rows of A, the identity below), the reflectors of
+// columns before c0 fill only rows 0 .. c0-1 of the identity block, so the
+// panel's columns are zero below stacked row stacked + c0 + w and its
+// reflectors (and the trailing update) stop there.
+int64_t panel_rows(int64_t m, int64_t c0, int w, int64_t stacked) {
+  const int64_t h = m - c0;
+  return stacked > 0 ? std::min<int64_t>(h, stacked + w) : h;
+}
+
 // Sub-panels of one panel by Cholesky QR with Householder reconstruction
 // (V: the panel, h x w); sub-panel T factors go to the panel's T slot.
 // Returns false when a sub-panel failed its checks (the panel is then
@@ -849,11 +859,11 @@ bool stream_capturing(hipStream_t s) {
 }  // namespace
 
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
-              const QrScratch& sc, hipStream_t s, const PanelWatch* watch, bool recon) {
+              const QrScratch& sc, hipStream_t s, const PanelWatch* watch, bool recon, int64_t stacked) {
   const bool use_recon = recon && sc.cq_part && qdwhp_tune_get("qr.recon", 1) != 0 && !stream_capturing(s);
   for (int64_t c0 = 0; c0 < n; c0 += QB) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
-    const int64_t h = m - c0;
+    const int64_t h = panel_rows(m, c0, w, stacked);
     double* V = A + c0 + c0 * lda;
     double* T = Tall + (c0 / QB) * QB * QB;
     bool done = false;
@@ -896,22 +906,22 @@ int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double*
 }
 
 void orgqr(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
-           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s) {
+           int64_t c0, int64_t q, double* Q, int64_t ldq, const QrScratch& sc, hipStream_t s, int64_t stacked) {
   if (q <= 0) return;
   dim3 grid((unsigned)cdiv(m, 256), (unsigned)(q < 65535 ? q : 65535));
   eye_cols_kernel<<<grid, 256, 0, s>>>(Q, m, q, ldq, c0);
   QDWHP_LAUNCH_CHECK();
-  apply_q(A, m, lda, Tall, upto, Q, q, ldq, sc, s);
+  apply_q(A, m, lda, Tall, upto, Q, q, ldq, sc, s, stacked);
 }
 
 void apply_q(const double* A, int64_t m, int64_t lda, const double* Tall, int64_t upto,
-             double* Q, int64_t q, int64_t ldq, const QrScratch& sc, hipStream_t s) {
+             double* Q, int64_t q, int64_t ldq, const QrScratch& sc, hipStream_t s, int64_t stacked) {
   if (upto <= 0 || q <= 0) return;
   const int64_t np = cdiv(upto, QB);
   for (int64_t pi = np - 1; pi >= 0; --pi) {
     const int64_t pc0 = pi * QB;
     const int w = (int)((upto - pc0) < QB ? (upto - pc0) : QB);
-    const int64_t h = m - pc0;
+    const int64_t h = panel_rows(m, pc0, w, stacked);
     const double* V = A + pc0 + pc0 * lda;
     const double* T = Tall + pi * QB * QB;
     double* Qp = Q + pc0;

@@ -182,9 +182,11 @@ void qr_step(double* X, int64_t m, int64_t n, double a, double b, double c, bool
              const StepBufs& B, hipStream_t s, const double* dw = nullptr) {
   const int64_t mn = m + n;
   stacked(X, m, B.W, mn, m, n, std::sqrt(c), s, dw ? dw + 3 : nullptr);
-  // Cholesky-QR panels only where cond(W) <= sqrt(1 + c) keeps them well inside their checks
-  geqrf(B.W, mn, n, mn, B.tau, B.Tall, B.qrs, s, nullptr, c <= 1e8);
-  orgqr(B.W, mn, mn, B.Tall, n, 0, n, B.Q, mn, B.qrs, s);
+  // Cholesky-QR panels only where cond(W) <= sqrt(1 + c) keeps them well inside their checks;
+  // the identity block's untouched rows are skipped (tuning key "qr.stacked", default on)
+  const int64_t st = qdwhp_tune_get("qr.stacked", 1) ? m : 0;
+  geqrf(B.W, mn, n, mn, B.tau, B.Tall, B.qrs, s, nullptr, c <= 1e8, st);
+  orgqr(B.W, mn, mn, B.Tall, n, 0, n, B.Q, mn, B.qrs, s, st);
   Gemm g;
   g.M = m; g.N = n; g.K = n; g.alpha = (a - b / c) / std::sqrt(c); g.beta = b / c;
   g.A = B.Q; g.lda = mn; g.B = B.Q + m; g.ldb = mn; g.tb = true; g.C = X; g.ldc = m;

@@ -166,6 +166,39 @@ def test_svd_vs_oracle(m, n, k, kind):
     assert info["kinds"] == [s["kind"] for s in r["sched"]]
 
 
+@pytest.mark.parametrize("m,n,k", [(900, 600, 30), (640, 640, 32)])
+def test_structured_stacked_qr_vs_full_and_oracle(m, n, k):
+    """The QR of [sqrt(c) X; I] that skips the identity rows no reflector
+    has reached yet (the structure of the stacked matrix) against the QR of
+    the full stacked matrix and the oracle, on an SVD whose first step is
+    QR-based (svd_qr_first = 1) and kappa = 1e16."""
+    torch, q = _gpu()
+    A, sig = svd_geometric(m, n, 1005, kappa=1e16)
+    print(f"structured stacked qr m={m} n={n} k={k}", flush=True)
+    o = q.default_opts(tol=TOL_LIB, svd_qr_first=1)
+    res = {}
+    old = q.tune_get("qr.stacked", 1)
+    try:
+        for stacked in (1, 0):
+            q.tune_set("qr.stacked", stacked)
+            U, S, V, info = q.svd(torch.from_numpy(A).cuda(), k, opts=o, return_info=True)
+            torch.cuda.synchronize()
+            res[stacked] = (U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy(), info)
+    finally:
+        q.tune_set("qr.stacked", old)
+    r = oracle.svd_partial(A, k, tol=TOL_LIB, qr_first=True)
+    assert res[1][3]["kinds"][0] == "qr" and res[1][3]["kinds"] == [st["kind"] for st in r["sched"]]
+    assert res[1][3]["ell"] == res[0][3]["ell"]
+    S1, S0 = res[1][1], res[0][1]
+    assert np.max(np.abs(S1 - S0) / S0) < 1e-13
+    assert np.max(np.abs(S1 - r["S"]) / r["S"]) < 1e-12
+    assert np.max(np.abs(S1 - sig[:k]) / sig[:k]) < 1e-12
+    met = oracle.svd_metrics(A, res[1][0], S1, res[1][2], sig[:k])
+    assert met["residual"] < 1e-13, met
+    assert max(met["orth_u"], met["orth_v"]) < 1e-12, met
+    assert np.max(np.abs(res[1][2] - res[0][2])) < 1e-9
+
+
 # ------------------------------------------------------------------ tol = 0.01
 # The paper's threshold (Sec. 4.1, Algorithms 1 and 2) on both sides.  The
 # guarantee the paper gives for the subspace is Theorem 1: sin angle(V0, Q2)
