@@ -21,6 +21,7 @@ from .estimator import lanczos_slq, choose_tau, choose_svd_threshold  # noqa: F4
 from .partial import eig_partial, svd_partial  # noqa: F401
 from .jacobi import jacobi_eig, jacobi_svd  # noqa: F401
 from .metrics import eig_metrics, svd_metrics  # noqa: F401
+from .zolo import zolo_coeffs, zolo_map, zolo_schedule, zolo_step  # noqa: F401
 
 # What pins each oracle function (see tests/test_oracle_*.py).
 PINS = {
@@ -35,4 +36,9 @@ PINS = {
     "svd_partial": "planted singular values to 1e-12; residuals; brute-force one-sided Jacobi n<=64; "
                    "paper's threshold/fraction mapping for D[i] = 0.5^(100 i/N)",
     "jacobi_eig/jacobi_svd": "closed-form 2x2 and diagonal cases, orthogonality, reconstruction",
+    "zolo_coeffs/zolo_map": "r = 1 equals the DWH closed form; composition (DWH twice = type (9,8), three "
+                            "times = type (27,26)); equioscillation (r+1 maxima 1, r+1 minima Z(l)); "
+                            "partial fractions reproduce the product",
+    "zolo_step": "planted iterates equal U Z(Sigma) V^T; Cholesky and QR terms agree; r = 1 equals the "
+                 "DWH step",
 }

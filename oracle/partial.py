@@ -36,8 +36,9 @@ import math
 import numpy as np
 import scipy.linalg as sla
 
-from .dwh import eig_schedule, svd_schedule
+from .dwh import eig_schedule, svd_schedule, QR_FIRST_BELOW
 from .polar import qr_step, chol_step
+from .zolo import zolo_schedule, zolo_step
 from .estimator import lanczos_slq, choose_tau, choose_svd_threshold
 from .philox import gaussian
 
@@ -93,18 +94,26 @@ def projector_subspace(B, tol=TOL, omega=None):
     return dict(diagR=np.diag(R).copy(), ind=ind, ell=ell, Q2=Q[:, ind - 1:])
 
 
-def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None, omega=None):
-    """Steps of Algorithm 1 after the setup: iterate, project, Rayleigh-Ritz."""
+def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None, omega=None, zolo_r=0):
+    """Steps of Algorithm 1 after the setup: iterate, project, Rayleigh-Ritz.
+    zolo_r > 0: Zolotarev steps of type (2r+1, 2r) instead of DWH steps
+    (oracle.zolo), from l_0 = s to convergence."""
     n = Aw.shape[0]
-    sched = eig_schedule(s, rho, iters, kappa_max)
-    if kinds is not None:
-        for st, kd in zip(sched, kinds):
-            st["kind"] = kd
+    if zolo_r:
+        sched = zolo_schedule(s, zolo_r, kappa_max, x0=max(1.0, (1.0 - s) * rho - s))
+    else:
+        sched = eig_schedule(s, rho, iters, kappa_max)
+        if kinds is not None:
+            for st, kd in zip(sched, kinds):
+                st["kind"] = kd
     # Scaled and shifted matrix (Sec. 4.1): wanted eigenvalues land in [-1, -s].
     X = ((1.0 - s) / mu) * (tau * np.eye(n) - Aw) - s * np.eye(n)
     for st in sched:
-        step = qr_step if st["kind"] == "qr" else chol_step
-        X = step(X, st["a"], st["b"], st["c"])
+        if zolo_r:
+            X = zolo_step(X, st)
+        else:
+            step = qr_step if st["kind"] == "qr" else chol_step
+            X = step(X, st["a"], st["b"], st["c"])
         if symmetrize:
             X = 0.5 * (X + X.T)
     B = 0.5 * (X + np.eye(n))
@@ -124,7 +133,7 @@ def _eig_core(Aw, tau, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds=None
 
 def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
                 tau=None, s=S_EIG, iters=3, tol=TOL, kappa_max=100.0, symmetrize=True,
-                nv=None, m=None, tau_policy="cost", use_omega=False):
+                nv=None, m=None, tau_policy="cost", use_omega=False, zolo_r=0):
     """Wanted eigenpairs of symmetric A by QDWHpartial-EIG (Algorithm 1).
 
     k mode (``fraction`` or ``k``): the k largest ('largest') or smallest
@@ -134,7 +143,9 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
     first), V (n x k) and the intermediates.  Raises NoSubspace when the
     certificate fails after one retry (k mode).  ``tau_policy`` picks the
     k-mode threshold ('cost' or 'plain', see estimator.choose_tau);
-    ``use_omega`` factors B Omega instead of B (Sec. 4.1).
+    ``use_omega`` factors B Omega instead of B (Sec. 4.1); ``zolo_r`` > 0
+    iterates Zolotarev steps of type (2 zolo_r + 1, 2 zolo_r) (oracle.zolo)
+    and then takes the plain threshold cut.
     """
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
@@ -158,7 +169,7 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
             spread = max(est["lmax"] - est["lmin"], abs(est["lmax"]), abs(est["lmin"]), 1e-300)
             mu = max(est["lmax"] - tw, 1e-3 * spread)
             rho = max(0.0, (tw - est["lmin"]) / mu)
-        r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega)
+        r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega, zolo_r)
         k = r["n_above"]
     else:
         if k is None:
@@ -167,8 +178,9 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
             if replay is not None:
                 tw, mu, rho = replay["tau"], replay["mu"], replay["rho"]
             else:
-                tw, mu, rho = choose_tau(est, k, boost, tau_policy, s, iters, kappa_max, tol)
-            r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega)
+                tw, mu, rho = choose_tau(est, k, boost, "plain" if zolo_r else tau_policy, s, iters,
+                                         kappa_max, tol)
+            r = _eig_core(Aw, tw, mu, rho, s, iters, tol, kappa_max, symmetrize, kinds, omega, zolo_r)
             if r["ell"] > 0 and (r["n_above"] >= k or r["ell"] >= n or replay is not None):
                 break
         else:
@@ -184,17 +196,26 @@ def eig_partial(A, fraction=None, k=None, which="largest", seed=0, replay=None,
     return r
 
 
-def _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds=None):
-    """Steps of Algorithm 2 after the norm estimate: iterate, project, small SVD."""
+def _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds=None, zolo_r=0):
+    """Steps of Algorithm 2 after the norm estimate: iterate, project, small SVD.
+    zolo_r > 0: Zolotarev steps (oracle.zolo); qr_first as for the DWH
+    schedule (None: forced when s < 1e-3, Sec. 4.2)."""
     n = A.shape[1]
-    sched = svd_schedule(s, kappa_max, qr_first)
-    if kinds is not None:
-        for st, kd in zip(sched, kinds):
-            st["kind"] = kd
+    if zolo_r:
+        force = (float(s) < QR_FIRST_BELOW) if qr_first is None else bool(qr_first)
+        sched = zolo_schedule(s, zolo_r, kappa_max, 1.0, qr_first=force)
+    else:
+        sched = svd_schedule(s, kappa_max, qr_first)
+        if kinds is not None:
+            for st, kd in zip(sched, kinds):
+                st["kind"] = kd
     X = A / alpha
     for st in sched:
-        step = qr_step if st["kind"] == "qr" else chol_step
-        X = step(X, st["a"], st["b"], st["c"])
+        if zolo_r:
+            X = zolo_step(X, st)
+        else:
+            step = qr_step if st["kind"] == "qr" else chol_step
+            X = step(X, st["a"], st["b"], st["c"])
     B = np.eye(n) - X.T @ X
     B = 0.5 * (B + B.T)
     sub = projector_subspace(B, tol)
@@ -211,7 +232,7 @@ def _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds=None):
 
 
 def svd_partial(A, k=None, seed=0, replay=None, s=None, tol=TOL, kappa_max=100.0,
-                qr_first=None, nv=None, m=None):
+                qr_first=None, nv=None, m=None, zolo_r=0):
     """Dominant singular triplets of A (m x n) by QDWHpartial-SVD (Algorithm 2).
 
     k mode: the k largest triplets.  Threshold mode (``s`` given, no k): every
@@ -221,7 +242,7 @@ def svd_partial(A, k=None, seed=0, replay=None, s=None, tol=TOL, kappa_max=100.0
     A = np.asarray(A, dtype=np.float64)
     if A.shape[0] < A.shape[1]:
         r = svd_partial(A.T, k, seed=seed, replay=replay, s=s, tol=tol,
-                        kappa_max=kappa_max, qr_first=qr_first, nv=nv, m=m)
+                        kappa_max=kappa_max, qr_first=qr_first, nv=nv, m=m, zolo_r=zolo_r)
         V, U = sign_normalize(r["U"], r["V"])
         r = dict(r)
         r["U"], r["V"] = U, V
@@ -239,7 +260,7 @@ def svd_partial(A, k=None, seed=0, replay=None, s=None, tol=TOL, kappa_max=100.0
         if s is None:
             raise ValueError("give k or s")
         alpha = replay["alpha"] if replay is not None else choose_svd_threshold(est, 1)[0]
-        r = _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds)
+        r = _svd_core(A, alpha, s, tol, kappa_max, qr_first, kinds, zolo_r)
         k = r["n_above"]
     else:
         for boost in (1, 2):
@@ -247,7 +268,7 @@ def svd_partial(A, k=None, seed=0, replay=None, s=None, tol=TOL, kappa_max=100.0
                 alpha, sv = replay["alpha"], replay["s"]
             else:
                 alpha, sv = choose_svd_threshold(est, k, boost)
-            r = _svd_core(A, alpha, sv, tol, kappa_max, qr_first, kinds)
+            r = _svd_core(A, alpha, sv, tol, kappa_max, qr_first, kinds, zolo_r)
             if r["ell"] > 0 and (r["n_above"] >= k or r["ell"] >= n or replay is not None):
                 break
         else:
