@@ -356,11 +356,16 @@ def workloads_leg(q, torch, dev, A16, lam16):
     out = []
     print("[bench] eig16384 top 1%", file=sys.stderr, flush=True)
     out.append(eig_entry(q, torch, "eig16384_top1pct_clustered", A16, lam16, 0.01))
+    print("[bench] eig16384 top 20% with Zolotarev steps (r = 2)", file=sys.stderr, flush=True)
+    out.append(eig_entry(q, torch, "eig16384_top20pct_clustered_zolo_r2", A16, lam16, 0.2,
+                         opts=q.default_opts(zolo_r=2)))
     print("[bench] svd4096 kappa 1e16 top 5%", file=sys.stderr, flush=True)
     A, sig = svd_geometric(4096, 4096, CONFIG_SEEDS["svd4096"], kappa=1e16, device=dev)
     out.append(svd_entry(q, torch, "svd4096_kappa1e16_top5pct", A, sig, 205, steps=3)[0])
     out.append(svd_entry(q, torch, "svd4096_kappa1e16_top5pct_qr_first", A, sig, 205, steps=3,
                          opts=q.default_opts(svd_qr_first=1))[0])
+    out.append(svd_entry(q, torch, "svd4096_kappa1e16_top5pct_zolo_r8", A, sig, 205, steps=3,
+                         opts=q.default_opts(zolo_r=8))[0])
     del A
     print("[bench] svd16384x8192 top 10%", file=sys.stderr, flush=True)
     A, sig = svd_loguniform(16384, 8192, CONFIG_SEEDS["svd16384x8192"], device=dev)

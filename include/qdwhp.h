@@ -108,6 +108,17 @@ typedef struct {
                                     entries of variance 1/n):
                                     the randomised rank-revealing QR of Sec. 4.1
                                     (costs one n^3 product more)                     */
+  int      zolo_r;         /* 0   : DWH steps (Sec. 3.1);
+                              r in 1..16: Zolotarev steps of type (2r+1, 2r), the
+                                    higher-order rational functions named beside DWH
+                                    (Sec. 3.1, Sec. 9), from l_0 = s until
+                                    |l_k - 1| < 5u; each step is
+                                    X+ = M (X + sum_j a_j X (X^T X + c_j I)^{-1}),
+                                    its r terms Cholesky- or QR-based by the kappa_max
+                                    rule (qdwhp_zolo_coeffs); FP64 only (precision,
+                                    polish_steps, graphs and kinds are ignored), and
+                                    the EIG threshold takes the plain cut (tau_policy
+                                    is ignored); info->weights[k] = (M, r, l_k)       */
 } qdwhp_opts;
 
 /* ---- per-call report (host struct) ------------------------------------ */
@@ -135,6 +146,14 @@ typedef struct {
 
 void qdwhp_opts_default(qdwhp_opts* opts);
 const char* qdwhp_strerror(int status);
+
+/* Coefficients of the Zolotarev step of type (2r+1, 2r) for lower bound l
+ * (host only, no GPU): c[2r] (c_1 .. c_2r), a[r] (partial fractions), *M and
+ * *l_next = Z(l), Z(x) = M x prod_j (x^2 + c_{2j}) / (x^2 + c_{2j-1}), the
+ * best approximation of sign on [l, 1] scaled to max 1 (Sec. 3.1 names these
+ * beside DWH; r = 1 is the DWH map).  Returns 0, or -1 / -2 for l outside
+ * (0, 1) / r outside 1..16, or QDWHP_ERR_NONFINITE. */
+int qdwhp_zolo_coeffs(double l, int r, double* c, double* a, double* M, double* l_next);
 
 /*
  * Workspace size in bytes (device memory, 256-byte aligned by the caller) for

@@ -24,7 +24,7 @@ each term by a Cholesky factorization of X^T X + c I or, when that is ill
 conditioned, by the QR factorization [X / sqrt(c); I] = [Q1; Q2] R, which
 gives X (X^T X + c I)^{-1} = Q1 Q2^T / sqrt(c).
 
-The elliptic functions come from mpmath at 40 significant digits (library
+The elliptic functions come from mpmath at 80 significant digits (library
 routines serving as steps).
 
 Readings (the paper gives no schedule for these steps):
@@ -44,7 +44,7 @@ import scipy.linalg as sla
 
 from .dwh import U_ROUND
 
-_DPS = 40
+_DPS = 80
 
 
 def zolo_coeffs(l, r):

@@ -35,7 +35,7 @@ class Opts(ctypes.Structure):
                 ("tau", ctypes.c_double), ("mu", ctypes.c_double), ("rho", ctypes.c_double),
                 ("alpha", ctypes.c_double), ("s_svd", ctypes.c_double),
                 ("kinds", ctypes.c_int * 16), ("graphs", ctypes.c_int),
-                ("tau_policy", ctypes.c_int), ("use_omega", ctypes.c_int)]
+                ("tau_policy", ctypes.c_int), ("use_omega", ctypes.c_int), ("zolo_r", ctypes.c_int)]
 
 
 Opts._field_names = frozenset(f for f, _ in Opts._fields_)
@@ -82,6 +82,7 @@ _PD = ctypes.POINTER(ctypes.c_double)
 _SIGS = {
     "qdwhp_opts_default": (None, [ctypes.POINTER(Opts)]),
     "qdwhp_strerror": (ctypes.c_char_p, [_I]),
+    "qdwhp_zolo_coeffs": (_I, [_D, _I, _PD, _PD, _PD, _PD]),
     "qdwhp_eig_workspace": (_SZ, [_I64, _D, ctypes.POINTER(Opts)]),
     "qdwhp_svd_workspace": (_SZ, [_I64, _I64, _I64, ctypes.POINTER(Opts)]),
     "qdwhp_eig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
@@ -344,6 +345,17 @@ def syev(H):
     _check(lib().qdwhp_syev(_ptr(Hc), n, n, _ptr(w), _ptr(Wb), n, _ptr(ws), nbytes, _stream(torch),
                             ctypes.byref(sw)), "qdwhp_syev")
     return w, Wb.t(), sw.value
+
+
+def zolo_coeffs(l, r):
+    """Zolotarev step coefficients computed by the library's host code:
+    dict(c=[c_1..c_2r], a=[a_1..a_r], M, l_next)."""
+    c = (ctypes.c_double * (2 * r))()
+    a = (ctypes.c_double * r)()
+    M, ln = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib().qdwhp_zolo_coeffs(float(l), int(r), c, a, ctypes.byref(M), ctypes.byref(ln)),
+           "qdwhp_zolo_coeffs")
+    return dict(c=list(c), a=list(a), M=M.value, l_next=ln.value)
 
 
 def syev_dc(H):

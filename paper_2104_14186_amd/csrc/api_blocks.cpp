@@ -5,6 +5,7 @@
 
 #include "qdwhp.h"
 #include "common.h"
+#include "dwh_sched.h"
 
 using namespace qdwhp;
 
@@ -27,6 +28,19 @@ extern "C" void qdwhp_opts_default(qdwhp_opts* o) {
   for (int i = 0; i < 16; ++i) o->kinds[i] = QDWHP_KIND_AUTO;
   o->tau_policy = 1;
   o->use_omega = 0;
+  o->zolo_r = 0;
+}
+
+extern "C" int qdwhp_zolo_coeffs(double l, int r, double* c, double* a, double* M, double* l_next) {
+  if (!(l > 0.0 && l < 1.0)) return -1;
+  if (r < 1 || r > kZoloMax) return -2;
+  ZoloStep z;
+  if (!zolo_coeffs(l, r, &z)) return QDWHP_ERR_NONFINITE;
+  for (int i = 0; i < 2 * r && c; ++i) c[i] = z.c[i];
+  for (int j = 0; j < r && a; ++j) a[j] = z.a[j];
+  if (M) *M = z.M;
+  if (l_next) *l_next = std::fmin(z.l_next, 1.0);
+  return 0;
 }
 
 extern "C" const char* qdwhp_strerror(int st) {

@@ -163,4 +163,135 @@ bool choose_tau_cost(const std::vector<double>& nodes, const std::vector<double>
   return found;
 }
 
+// ---- Zolotarev steps ------------------------------------------------------
+namespace {
+
+constexpr long double kPiL = 3.14159265358979323846264338327950288L;
+
+// Descending Landen (Gauss) transformation of the modulus k (complementary
+// modulus kc = sqrt(1 - k^2), Abramowitz and Stegun 16.12, 17.5):
+// k_{n+1} = (1 - kc_n)/(1 + kc_n), kc_{n+1} = 2 sqrt(kc_n)/(1 + kc_n), with
+// 1 - k_{n+1} = 2 kc_n/(1 + kc_n) kept as well, so that a modulus next to 1
+// (kc tiny) loses nothing to cancellation; stops once k_N < 1e-10 (then
+// sn(v, k_N) = sin v to rounding).  Returns N; k[1..N], omk[1..N] = 1 - k.
+// In long double: the coefficients decide the step count through
+// |Z(l) - 1| < 5u, so they are carried to better than double accuracy.
+int landen_chain(long double kc, long double* k, long double* omk) {
+  int n = 0;
+  long double kcn = kc;
+  while (n < 40) {
+    ++n;
+    k[n] = (1.0L - kcn) / (1.0L + kcn);
+    omk[n] = 2.0L * kcn / (1.0L + kcn);
+    kcn = 2.0L * sqrtl(kcn) / (1.0L + kcn);
+    if (k[n] < 1e-10L) break;
+  }
+  return n;
+}
+
+long double ellip_k_ld(long double kc) {
+  long double k[41], omk[41];
+  const int n = landen_chain(kc, k, omk);
+  long double K = 0.5L * kPiL;
+  for (int i = 1; i <= n; ++i) K *= 1.0L + k[i];
+  return K;
+}
+
+void sncndn_ld(long double u, long double kc, long double* sn, long double* cn, long double* dn) {
+  long double k[41], omk[41];
+  const int n = landen_chain(kc, k, omk);
+  long double v = u;
+  for (int i = 1; i <= n; ++i) v /= 1.0L + k[i];
+  long double s = sinl(v), c = cosl(v), d = 1.0L;
+  for (int i = n; i >= 1; --i) {
+    const long double den = 1.0L + k[i] * s * s;
+    const long double s1 = (1.0L + k[i]) * s / den;
+    const long double c1 = c * d / den;
+    const long double d1 = (c * c + omk[i] * s * s) / den;
+    s = s1; c = c1; d = d1;
+  }
+  *sn = s; *cn = c; *dn = d;
+}
+
+}  // namespace
+
+// K(k) = (pi/2) prod_n (1 + k_n) over the Landen chain.
+double ellip_k(double kc) { return (double)ellip_k_ld(kc); }
+
+// sn, cn, dn by the Landen chain: v_n = u / prod_{i<=n} (1 + k_i); at the
+// bottom sn = sin, cn = cos, dn = 1; then, going up with s, c, d of modulus
+// k_{n+1}: D = 1 + k s^2, sn = (1 + k) s / D, cn = c d / D,
+// dn = (1 - k s^2)/D = (c^2 + (1 - k) s^2)/D (the last form without the
+// cancellation of 1 - k s^2 when k and s are both next to 1).
+void jacobi_sncndn(double u, double kc, double* sn, double* cn, double* dn) {
+  long double s, c, d;
+  sncndn_ld(u, kc, &s, &c, &d);
+  *sn = (double)s; *cn = (double)c; *dn = (double)d;
+}
+
+bool zolo_coeffs(double l, int r, ZoloStep* z) {
+  if (!(l > 0.0 && l < 1.0) || r < 1 || r > kZoloMax) return false;
+  const long double L = l;
+  const long double kp = ellip_k_ld(L);        // K' = K(l'), l' = sqrt(1 - l^2): complementary modulus l
+  const int d = 2 * r + 1;
+  long double c[2 * kZoloMax];
+  z->r = r;
+  for (int i = 1; i <= 2 * r; ++i) {
+    long double sn, cn, dn;
+    if (2 * i <= d) {                          // argument below K'/2: c_i = l^2 sc^2(u)
+      sncndn_ld(i * kp / d, L, &sn, &cn, &dn);
+      c[i - 1] = L * L * (sn / cn) * (sn / cn);
+    } else {                                   // u = K' - v: c_i = cs^2(v), v below K'/2
+      sncndn_ld((d - i) * kp / d, L, &sn, &cn, &dn);
+      c[i - 1] = (cn / sn) * (cn / sn);
+    }
+    z->c[i - 1] = (double)c[i - 1];
+  }
+  long double M = 1.0L;
+  for (int j = 0; j < r; ++j) M *= (1.0L + c[2 * j]) / (1.0L + c[2 * j + 1]);
+  z->M = (double)M;
+  for (int j = 0; j < r; ++j) {
+    const long double cj = c[2 * j];
+    long double aj = c[2 * j + 1] - cj;
+    for (int k = 0; k < r; ++k)
+      if (k != j) aj *= (c[2 * k + 1] - cj) / (c[2 * k] - cj);
+    z->a[j] = (double)aj;
+  }
+  // next lower bound from the extended-precision coefficients
+  long double v = M * L;
+  for (int j = 0; j < r; ++j) v *= (L * L + c[2 * j + 1]) / (L * L + c[2 * j]);
+  z->l_next = (double)v;
+  for (int i = 0; i < 2 * r; ++i)
+    if (!std::isfinite(z->c[i]) || !(z->c[i] > 0.0)) return false;
+  for (int j = 0; j < r; ++j)
+    if (!std::isfinite(z->a[j])) return false;
+  return std::isfinite(z->M) && z->M > 0.0 && std::isfinite(z->l_next);
+}
+
+double zolo_map(double x, const ZoloStep& z) {
+  const double y = x * x;
+  double v = z.M * x;
+  for (int j = 0; j < z.r; ++j) v *= (y + z.c[2 * j + 1]) / (y + z.c[2 * j]);
+  return v;
+}
+
+std::vector<ZoloStep> zolo_schedule(double s, int r, double kappa_max, double x0, bool qr_first) {
+  std::vector<ZoloStep> sched;
+  double l = s, x = std::max(1.0, x0);
+  while (std::fabs(l - 1.0) >= 5.0 * kUnitRoundoff && sched.size() < 8) {
+    ZoloStep z;
+    if (!zolo_coeffs(std::min(l, 1.0 - 1e-16), r, &z)) break;
+    z.l = l;
+    z.x = x;
+    for (int j = 0; j < r; ++j) {
+      const bool force = qr_first && sched.empty();
+      z.kinds[j] = (force || 1.0 + x * x / z.c[2 * j] > kappa_max) ? 1 : 2;
+    }
+    sched.push_back(z);
+    l = std::min(z.l_next, 1.0);
+    x = std::max(1.0, zolo_map(x, z));
+  }
+  return sched;
+}
+
 }  // namespace qdwhp

@@ -26,6 +26,40 @@ std::vector<DwhStep> eig_schedule(double s, double rho, int iters, double kappa_
 // [0, 1]).
 std::vector<DwhStep> svd_schedule(double s, double kappa_max, bool qr_first);
 
+// Zolotarev steps of type (2r+1, 2r): the higher-order rational functions
+// the paper names beside DWH (Sec. 3.1; Sec. 9).  Z(x) = M x prod_j (x^2 +
+// c_{2j}) / (x^2 + c_{2j-1}) is the best approximation of sign on [l, 1]
+// scaled to max 1 (r = 1: the DWH map), with c_i = l^2 sc^2(i K'/(2r+1); l')
+// (l' = sqrt(1 - l^2), K' = K(l')) and M = prod_j (1 + c_{2j-1})/(1 + c_{2j})
+// (Nakatsukasa and Freund, SIAM Review 58, 2016).  One step is
+// X+ = M (X + sum_j a_j X (X^T X + c_{2j-1} I)^{-1}), the a_j the partial
+// fractions of the product in x^2.
+constexpr int kZoloMax = 16;
+struct ZoloStep {
+  int r = 0;
+  double M = 0.0;
+  double c[2 * kZoloMax] = {};   // c_1 .. c_2r
+  double a[kZoloMax] = {};       // a_1 .. a_r
+  int kinds[kZoloMax] = {};      // per term: 1 = QR form, 2 = Cholesky form
+  double l = 0.0, x = 1.0;       // lower bound and bound on the largest value before the step
+  double l_next = 0.0;           // Z(l), from the coefficients in extended precision
+};
+// Jacobi's sn, cn, dn of argument u for the modulus k = sqrt(1 - kc^2), given
+// the complementary modulus kc in (0, 1] (so that k next to 1 keeps its
+// accuracy), and K(k): descending Landen transformation (Abramowitz and
+// Stegun 16.12, 17.5).
+void jacobi_sncndn(double u, double kc, double* sn, double* cn, double* dn);
+double ellip_k(double kc);
+// Coefficients (and l_next = Z(l)) for lower bound l in (0, 1), computed in
+// long double and stored in double; false when they are not finite.
+bool zolo_coeffs(double l, int r, ZoloStep* z);
+double zolo_map(double x, const ZoloStep& z);
+// Steps from l_0 = s until |l_k - 1| < 5u (at most 8).  A term is QR-based
+// when 1 + x_k^2 / c_{2j-1} (its bound on cond(I + X^T X / c_{2j-1})) exceeds
+// kappa_max, every term of step 0 when qr_first; x_0 = x0 and
+// x_{k+1} = max(1, Z(x_k)) (x0 = 1 for the SVD).
+std::vector<ZoloStep> zolo_schedule(double s, int r, double kappa_max, double x0, bool qr_first);
+
 // Threshold below the pooled Lanczos quadrature node at which the estimated
 // count first reaches kt; returns false when the count never reaches kt.
 // nonneg: nodes of A^T A (>= 0, many decades): distinctness is relative to

@@ -95,6 +95,7 @@ struct StepBufs {
   double* Tall;     // qr_t_doubles(n)
   QrScratch qrs;
   int* flag;
+  double* G = nullptr;   // n x n, Zolotarev steps only
 };
 
 // Eq. (3): Z = I + c X^T X = W^T W, X+ = (b/c) X + (a - b/c) (X W^{-1}) W^{-T}.
@@ -195,6 +196,67 @@ void qr_step(double* X, int64_t m, int64_t n, double a, double b, double c, bool
   if (sym) symmetrize(X, n, m, s);
 }
 
+// One Zolotarev step (type (2r+1, 2r), the higher-order variant of Sec. 3.1):
+// X+ = M X + sum_j (M a_j) X (X^T X + c_j I)^{-1}, c_j = c_{2j-1}.  The
+// Cholesky-form terms share the Gram G = X^T X: Z = I + G / c_j = W^T W, and
+// X (X^T X + c_j I)^{-1} = (1/c_j) (X W^{-1}) W^{-T} (the two triangular
+// products of Eq. (3)); the QR-form terms take [X / sqrt(c_j); I] = [Q1; Q2] R,
+// X (X^T X + c_j I)^{-1} = Q1 Q2^T / sqrt(c_j) (the structured QR of Eq. (2)).
+// The terms accumulate into Xn (upper tiles and one mirror when sym).
+void zolo_step(double*& X, double*& Xn, int64_t m, int64_t n, const ZoloStep& z, bool sym, const StepBufs& B,
+               hipStream_t s) {
+  const double* Wi = B.spd;
+  double* T = B.spd + spd_inverse_doubles(n);
+  bool first = true, have_gram = false;
+  auto accumulate = [&](Gemm& u) {
+    if (first) { u.beta = z.M; u.Cin = X; u.ldcin = m; }
+    else { u.beta = 1.0; u.Cin = Xn; u.ldcin = m; }
+    u.C = Xn; u.ldc = m;
+    if (sym) u.tiles = TILES_UPPER;
+    dgemm(u, s);
+    first = false;
+  };
+  for (int pass = 0; pass < 2; ++pass) {          // Cholesky-form terms first: the QR ones reuse B.W
+    for (int j = 0; j < z.r; ++j) {
+      const bool qr = z.kinds[j] == 1;
+      if (qr != (pass == 1)) continue;
+      const double cj = z.c[2 * j];
+      const double coef = z.M * z.a[j];
+      if (!qr) {
+        if (!have_gram) {
+          Gemm g;
+          g.M = n; g.N = n; g.K = m; g.A = X; g.lda = m; g.ta = true; g.B = X; g.ldb = m; g.C = B.G; g.ldc = n;
+          g.tiles = TILES_UPPER;
+          dgemm(g, s);
+          have_gram = true;
+        }
+        eig_x0(B.G, n, B.Z, n, n, 1.0, 1.0, -1.0 / cj, 0.0, s);   // Z = I + G / c_j (upper part read)
+        chol_inverse_factor(B.Z, n, n, B.spd, B.flag, s);
+        Gemm t;
+        t.M = m; t.N = n; t.K = n; t.A = X; t.lda = m; t.B = Wi; t.ldb = n; t.C = T; t.ldc = m;
+        t.khi = KHI_COL;
+        dgemm(t, s);
+        Gemm u;
+        u.M = m; u.N = n; u.K = n; u.alpha = coef / cj;
+        u.A = T; u.lda = m; u.B = Wi; u.ldb = n; u.tb = true; u.klo = KLO_COL;
+        accumulate(u);
+      } else {
+        const int64_t mn = m + n;
+        stacked(X, m, B.W, mn, m, n, 1.0 / std::sqrt(cj), s);
+        const int64_t st = qdwhp_tune_get("qr.stacked", 1) ? m : 0;
+        geqrf(B.W, mn, n, mn, B.tau, B.Tall, B.qrs, s, nullptr, 1.0 / cj <= 1e8, st);
+        orgqr(B.W, mn, mn, B.Tall, n, 0, n, B.Q, mn, B.qrs, s, st);
+        Gemm g;
+        g.M = m; g.N = n; g.K = n; g.alpha = coef / std::sqrt(cj);
+        g.A = B.Q; g.lda = mn; g.B = B.Q + m; g.ldb = mn; g.tb = true;
+        accumulate(g);
+      }
+    }
+  }
+  if (sym) mirror_upper(Xn, n, m, s);
+  std::swap(X, Xn);
+}
+
 // ---------------------------------------------------------------------------
 struct Plan {
   double *X, *Xn, *Z, *big;
@@ -202,9 +264,10 @@ struct Plan {
   double *tau, *Tall, *diag, *vals, *lz, *wts;
   QrScratch qrs;
   int* flags;       // [0] Cholesky breakdown, [1] non-finite input
+  double* G = nullptr;   // n x n Gram of the Zolotarev steps (only with zolo_r > 0)
 };
 
-Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd) {
+Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd, bool zolo) {
   Plan p;
   const int64_t np = jacobi_padded(nn);
   p.X = ar.take(mm * nn);
@@ -225,13 +288,14 @@ Plan carve(Arena& ar, int64_t mm, int64_t nn, int nv, int64_t msteps, bool svd) 
   p.lz = ar.take(lanczos_doubles(nn, mm, nv, (int)msteps));
   p.flags = (int*)ar.take(8);
   p.wts = ar.take(16 * 8);
+  if (zolo) p.G = ar.take(nn * nn);
   return p;
 }
 
 StepBufs step_bufs(const Plan& p, int64_t m, int64_t n) {
   StepBufs b;
   b.Z = p.Z; b.spd = p.big; b.spd_doubles = p.big_doubles; b.W = p.big; b.Q = p.big + (m + n) * n;
-  b.tau = p.tau; b.Tall = p.Tall; b.qrs = p.qrs; b.flag = p.flags;
+  b.tau = p.tau; b.Tall = p.Tall; b.qrs = p.qrs; b.flag = p.flags; b.G = p.G;
   return b;
 }
 
@@ -243,6 +307,34 @@ void fill_info(qdwhp_info* info, const std::vector<DwhStep>& sched) {
     info->weights[i][1] = sched[i].b;
     info->weights[i][2] = sched[i].c;
   }
+}
+
+void fill_info_zolo(qdwhp_info* info, const std::vector<ZoloStep>& zs) {
+  info->n_iter = (int)zs.size();
+  for (size_t i = 0; i < zs.size() && i < 16; ++i) {
+    int kind = 2;
+    for (int j = 0; j < zs[i].r; ++j) if (zs[i].kinds[j] == 1) kind = 1;
+    info->kinds[i] = kind;
+    info->weights[i][0] = zs[i].M;
+    info->weights[i][1] = zs[i].r;
+    info->weights[i][2] = zs[i].l;
+  }
+}
+
+// Table 1's accounting for Zolotarev steps: the Gram 2mn^2 once per step with
+// a Cholesky-form term, each Cholesky-form term n^3/3 + 2mn^2 (factor and
+// the two triangular solves), each QR-form term 6mn^2 + 8/3 n^3.
+double table1_zolo_flops(const std::vector<ZoloStep>& zs, double m, double n) {
+  double f = 0.0;
+  for (const auto& z : zs) {
+    bool gram = false;
+    for (int j = 0; j < z.r; ++j) {
+      if (z.kinds[j] == 1) f += 6.0 * m * n * n + 8.0 / 3.0 * n * n * n;
+      else { f += n * n * n / 3.0 + 2.0 * m * n * n; gram = true; }
+    }
+    if (gram) f += 2.0 * m * n * n;
+  }
+  return f;
 }
 
 // first 1-based i with |R_ii| < tol, n + 1 if none
@@ -841,7 +933,7 @@ extern "C" size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_op
   qdwhp_opts o;
   if (opts) o = *opts; else qdwhp_opts_default(&o);
   Arena ar(nullptr, 0);
-  carve(ar, n, n, lz_vectors(o), lz_steps(o, n), false);
+  carve(ar, n, n, lz_vectors(o), lz_steps(o, n), false, o.zolo_r > 0);
   return ar.off;
 }
 
@@ -852,7 +944,7 @@ extern "C" size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdw
   if (opts) o = *opts; else qdwhp_opts_default(&o);
   const int64_t mm = std::max(m, n), nn = std::min(m, n);
   Arena ar(nullptr, 0);
-  carve(ar, mm, nn, lz_vectors(o), lz_steps(o, nn), true);
+  carve(ar, mm, nn, lz_vectors(o), lz_steps(o, nn), true, o.zolo_r > 0);
   return ar.off;
 }
 
@@ -890,6 +982,7 @@ struct SolveState {
   bool replay = false;
   int boost = 1;
   std::vector<DwhStep> sched;
+  std::vector<ZoloStep> zsched;    // Zolotarev steps instead of sched (opts.zolo_r > 0)
   std::vector<int> polish;
   bool mixed = false;
   double tau = 0.0, mu = 1.0, rho = 0.0;   // EIG threshold, scale, unwanted-side bound
@@ -900,6 +993,16 @@ struct SolveState {
   int status = QDWHP_OK;
   int ret(int st) { info->status = st; status = st; return st; }
 };
+
+// The iterations of a set-up solve: its Zolotarev steps, or its DWH
+// schedule (optionally as a captured graph) with the polish plan.
+void iterate_state(SolveState& S, bool graphs, hipStream_t s) {
+  if (!S.zsched.empty()) {
+    for (const ZoloStep& z : S.zsched) zolo_step(S.X, S.Xn, S.mm, S.nn, z, !S.svd, S.sb, s);
+    return;
+  }
+  run_iterations(S.X, S.Xn, S.mm, S.nn, !S.svd, S.sched, S.mixed, S.polish, S.P, S.sb, graphs, s);
+}
 }  // namespace qdwhp
 
 namespace {
@@ -909,7 +1012,8 @@ using qdwhp::SolveState;
 // ---- EIG (Algorithm 1) -----------------------------------------------------
 int eig_setup(SolveState& S) {
   const qdwhp_opts& o = S.o;
-  if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16)
+  if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16 ||
+      o.zolo_r < 0 || o.zolo_r > kZoloMax)
     return S.ret(-11);
   const int64_t n = S.n;
   int64_t k = (int64_t)std::floor(S.fraction * (double)n + 0.5);
@@ -920,7 +1024,7 @@ int eig_setup(SolveState& S) {
   S.sgn = (S.which == QDWHP_SMALLEST) ? -1.0 : 1.0;
   S.mm = S.nn = n;
   Arena ar(S.work, S.lwork);
-  S.P = carve(ar, n, n, S.nv, S.msteps, false);
+  S.P = carve(ar, n, n, S.nv, S.msteps, false, o.zolo_r > 0);
   S.ev.reset(new Events(true));
   S.ev->mark(0, S.s);
   hipStream_t s = S.s;
@@ -974,7 +1078,7 @@ void eig_prepare(SolveState& S) {
     } else {
       double cut;
       const int64_t kt = target_count(n, S.k, S.boost);
-      const bool ok = o.tau_policy == 1
+      const bool ok = (o.tau_policy == 1 && o.zolo_r == 0)
           ? choose_tau_cost(S.lz.nodes, S.lz.weights, n, S.nv, S.lmax, S.lmin, kt, sfix, o.eig_iters,
                             o.kappa_max, o.tol, &cut)
           : cut_below(S.lz.nodes, S.lz.weights, n, S.nv, S.lmax, S.lmin, kt, &cut);
@@ -983,16 +1087,22 @@ void eig_prepare(SolveState& S) {
     S.mu = std::max(S.lmax - S.tau, 1e-3 * spread);
     S.rho = std::max(0.0, (S.tau - S.lmin) / S.mu);
   }
-  S.sched = eig_schedule(sfix, S.rho, o.eig_iters, o.kappa_max);
-  for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
-    if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  S.zsched.clear();
+  if (o.zolo_r > 0) {
+    S.sched.clear();
+    S.zsched = zolo_schedule(sfix, o.zolo_r, o.kappa_max, std::max(1.0, (1.0 - sfix) * S.rho - sfix), false);
+  } else {
+    S.sched = eig_schedule(sfix, S.rho, o.eig_iters, o.kappa_max);
+    for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
+      if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  }
   S.info->retries = S.boost - 1;
   // ---- iterations on the scaled, shifted matrix (Sec. 4.1)
   S.X = S.P.X;
   S.Xn = S.P.Xn;
   eig_x0(S.A, S.lda, S.X, n, n, (1.0 - sfix) / S.mu, S.tau, S.sgn, sfix, S.s);
   S.sb = step_bufs(S.P, n, n);
-  S.mixed = (o.precision == QDWHP_MIXED_FP32);
+  S.mixed = (o.precision == QDWHP_MIXED_FP32) && o.zolo_r == 0;
   double xbound = 1.0;
   for (const auto& st : S.sched) xbound = std::max(1.0, dwh_map(st.x, st.a, st.b, st.c));
   S.polish.clear();
@@ -1094,12 +1204,12 @@ int eig_finish(SolveState& S) {
   while (eig_project(S, theta, ell, ind, n_above, Q2, Wv) == 1 && S.boost < 2) {
     ++S.boost;
     eig_prepare(S);
-    run_iterations(S.X, S.Xn, n, n, true, S.sched, S.mixed, S.polish, S.P, S.sb, S.o.graphs != 0, s);
+    iterate_state(S, S.o.graphs != 0, s);
   }
   qdwhp_info* info = S.info;
   info->tau = S.sgn * S.tau; info->mu = S.mu; info->rho = S.rho;
   info->ell = ell; info->ind = ind; info->n_above = n_above;
-  fill_info(info, S.sched);
+  if (S.zsched.empty()) fill_info(info, S.sched); else fill_info_zolo(info, S.zsched);
   if (S.status != QDWHP_OK) return S.ret(S.status);
   if (ell < k) return S.ret(QDWHP_ERR_NO_SUBSPACE);
   // ---- V = Q2 W(:, 1:k), w = sgn theta(1:k)
@@ -1116,7 +1226,8 @@ int eig_finish(SolveState& S) {
   S.ev->mark(7, s);
   S.ev->fill(info->ms);
   const double dn = (double)n, dl = (double)ell, dk = (double)k;
-  info->flops_table1 = table1_iter_flops(S.sched, dn, dn) + 4.0 / 3.0 * dn * dn * dn +
+  info->flops_table1 = (S.zsched.empty() ? table1_iter_flops(S.sched, dn, dn) : table1_zolo_flops(S.zsched, dn, dn)) +
+                       4.0 / 3.0 * dn * dn * dn +
                        2.0 * dn * dn * dl + 2.0 * dn * dl * dl + 9.0 * dl * dl * dl + 2.0 * dn * dl * dk;
   return S.ret(QDWHP_OK);
 }
@@ -1124,7 +1235,7 @@ int eig_finish(SolveState& S) {
 // ---- SVD (Algorithm 2) -----------------------------------------------------
 int svd_setup(SolveState& S) {
   const qdwhp_opts& o = S.o;
-  if (!(o.tol > 0.0)) return S.ret(-13);
+  if (!(o.tol > 0.0) || o.zolo_r < 0 || o.zolo_r > kZoloMax) return S.ret(-13);
   hipStream_t s = S.s;
   const int64_t m = S.m, n = S.n;
   S.tr = m < n;                       // process M = A^T when A is wide
@@ -1134,7 +1245,7 @@ int svd_setup(SolveState& S) {
   S.nv = lz_vectors(o);
   S.msteps = lz_steps(o, nn);
   Arena ar(S.work, S.lwork);
-  S.P = carve(ar, mm, nn, S.nv, S.msteps, true);
+  S.P = carve(ar, mm, nn, S.nv, S.msteps, true, o.zolo_r > 0);
   Plan& P = S.P;
   S.ev.reset(new Events(true));
   S.ev->mark(0, s);
@@ -1208,15 +1319,21 @@ void svd_prepare(SolveState& S) {
       S.sthr = std::min(1.0, std::max(1e-15, std::sqrt(t) / S.alpha));
     }
   }
-  S.sched = svd_schedule(S.sthr, o.kappa_max, o.svd_qr_first != 0);
-  for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
-    if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  S.zsched.clear();
+  if (o.zolo_r > 0) {
+    S.sched.clear();
+    S.zsched = zolo_schedule(S.sthr, o.zolo_r, o.kappa_max, 1.0, o.svd_qr_first != 0 || S.sthr < 1e-3);
+  } else {
+    S.sched = svd_schedule(S.sthr, o.kappa_max, o.svd_qr_first != 0);
+    for (size_t i = 0; i < S.sched.size() && i < 16; ++i)
+      if (o.kinds[i] == QDWHP_KIND_QR || o.kinds[i] == QDWHP_KIND_CHOL) S.sched[i].kind = o.kinds[i];
+  }
   S.info->retries = S.boost - 1;
   S.X = S.P.X;
   S.Xn = S.P.Xn;
   scale_copy(S.A, S.lda, S.X, mm, mm, nn, 1.0 / S.alpha, S.tr, S.s);
   S.sb = step_bufs(S.P, mm, nn);
-  S.mixed = (o.precision == QDWHP_MIXED_FP32);
+  S.mixed = (o.precision == QDWHP_MIXED_FP32) && o.zolo_r == 0;
   // FP64 Newton-Schulz polish steps (singular values of X lie in [0, 1 + O(u_32)])
   S.polish.assign(S.mixed ? std::max(0, o.polish_steps) : 0, 0);
 }
@@ -1294,12 +1411,12 @@ int svd_finish(SolveState& S) {
   while (svd_project(S, sig, ell, ind, n_above, Q2, Y, Ut, Vt) == 1 && S.boost < 2) {
     ++S.boost;
     svd_prepare(S);
-    run_iterations(S.X, S.Xn, mm, nn, false, S.sched, S.mixed, S.polish, S.P, S.sb, S.o.graphs != 0, s);
+    iterate_state(S, S.o.graphs != 0, s);
   }
   qdwhp_info* info = S.info;
   info->alpha = S.alpha; info->s = S.sthr;
   info->ell = ell; info->ind = ind; info->n_above = n_above;
-  fill_info(info, S.sched);
+  if (S.zsched.empty()) fill_info(info, S.sched); else fill_info_zolo(info, S.zsched);
   if (S.status != QDWHP_OK) return S.ret(S.status);
   if (ell < k) return S.ret(QDWHP_ERR_NO_SUBSPACE);
   Plan& P = S.P;
@@ -1324,7 +1441,8 @@ int svd_finish(SolveState& S) {
   S.ev->mark(7, s);
   S.ev->fill(info->ms);
   const double dm = (double)mm, dn = (double)nn, dl = (double)ell, dk = (double)k;
-  info->flops_table1 = table1_iter_flops(S.sched, dm, dn) + dm * dn * dn + 4.0 / 3.0 * dn * dn * dn +
+  info->flops_table1 = (S.zsched.empty() ? table1_iter_flops(S.sched, dm, dn) : table1_zolo_flops(S.zsched, dm, dn)) +
+                       dm * dn * dn + 4.0 / 3.0 * dn * dn * dn +
                        2.0 * dm * dn * dl + 2.0 * dm * dl * dl + 17.0 * dl * dl * dl +
                        2.0 * dm * dl * dk + 2.0 * dn * dl * dk;
   return S.ret(QDWHP_OK);
@@ -1413,8 +1531,7 @@ int solve_setup(SolveState* S) {
 int solve_iterate(SolveState* S) {
   SolveState& st = *S;
   return guarded(st, [&] {
-    run_iterations(st.X, st.Xn, st.mm, st.nn, !st.svd, st.sched, st.mixed, st.polish, st.P, st.sb,
-                   st.o.graphs != 0, st.s);
+    iterate_state(st, st.o.graphs != 0, st.s);
     return QDWHP_OK;
   });
 }
@@ -1598,14 +1715,15 @@ extern "C" int qdwhp_gesvj(double* R, int64_t n, int64_t ldr, double* S, double*
 // DWH steps of a group of solves of one shape (phase 2 of a batch or a server
 // group): the operations of chol_step for all Cholesky-based members at once.
 int64_t qdwhp::solve_shape(const SolveState* S) {
+  // solves with Zolotarev steps never share a key (they are not grouped)
+  if (!S->zsched.empty()) return -1 - (int64_t)(intptr_t)S;
   return ((S->svd ? 1 : 0) | ((int64_t)(S->mixed ? 1 : 0) << 1)) + 4 * (S->mm * 2000003 + S->nn);
 }
 
 void qdwhp::iterations_grouped(SolveState* const* v, int count, void* table, hipStream_t s) {
   if (count <= 0) return;
   if (count == 1) {    // a group of one is the solve's own iterations
-    SolveState& S = *v[0];
-    run_iterations(S.X, S.Xn, S.mm, S.nn, !S.svd, S.sched, S.mixed, S.polish, S.P, S.sb, false, s);
+    iterate_state(*v[0], false, s);
     return;
   }
   const int64_t m = v[0]->mm, n = v[0]->nn;

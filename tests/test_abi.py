@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -92,3 +93,34 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(cls), cname
         for field, _ in cls._fields_:
             assert got[(cname, field)] == getattr(cls, field).offset, (cname, field)
+
+
+def test_zolotarev_coefficients_match_the_oracle():
+    """The library's host-side Zolotarev coefficients (Landen-chain elliptic
+    functions in long double) against the oracle's (mpmath at 80 digits), down to
+    l = 1e-16 where the modulus l' is within 1e-32 of 1."""
+    import paper_2104_14186_amd as q
+    from oracle.zolo import zolo_coeffs
+    for l in [1e-16, 1e-12, 1e-8, 1e-4, 1e-2, 0.2, 0.5, 0.9, 0.999]:
+        for r in [1, 2, 3, 5, 8, 13, 16]:
+            a, b = q.zolo_coeffs(l, r), zolo_coeffs(l, r)
+            assert np.max(np.abs(np.array(a["c"]) - b["c"]) / np.array(b["c"])) < 1e-15
+            assert np.max(np.abs(np.array(a["a"]) - b["a"]) / np.abs(b["a"])) < 1e-15
+            assert abs(a["M"] - b["M"]) < 1e-15 * b["M"]
+            assert abs(a["l_next"] - b["l_next"]) < 1e-15
+    with pytest.raises(RuntimeError):
+        q.zolo_coeffs(1.0, 2)
+
+
+def test_zolotarev_step_counts_match_the_oracle():
+    """The step count depends on |Z(l) - 1| < 5u at the rounding level; the
+    library's extended-precision l_next takes the oracle's decisions."""
+    import paper_2104_14186_amd as q
+    from oracle.zolo import zolo_schedule
+    for s in [0.875, 0.2, 0.05, 1e-3, 1e-8, 1e-16]:
+        for r in range(1, 17):
+            l, k = s, 0
+            while abs(l - 1.0) >= 5 * 2.0 ** -53 and k < 8:
+                l = min(q.zolo_coeffs(min(l, 1 - 1e-16), r)["l_next"], 1.0)
+                k += 1
+            assert k == len(zolo_schedule(s, r)), (s, r)

@@ -199,6 +199,66 @@ def test_structured_stacked_qr_vs_full_and_oracle(m, n, k):
     assert np.max(np.abs(res[1][2] - res[0][2])) < 1e-9
 
 
+# ------------------------------------------------------- Zolotarev steps (r > 1)
+@pytest.mark.parametrize("n,f,seed,r,spec", [(512, 0.1, 1000, 2, "uniform"), (600, 0.2, 41, 13, "clustered"),
+                                             (700, 0.15, 42, 3, "uniform"), (400, 0.1, 43, 1, "uniform")])
+def test_zolotarev_eig_vs_oracle(n, f, seed, r, spec):
+    """Zolotarev steps of type (2r+1, 2r) in Algorithm 1 (r = 13 from s = 0.2:
+    one step, its terms with small c_{2j-1} QR-based; r = 1: the DWH steps),
+    against the oracle's Zolotarev iteration and the planted spectrum."""
+    torch, q = _gpu()
+    A, lam = (eig_uniform if spec == "uniform" else eig_clustered)(n, seed)
+    print(f"zolotarev eig n={n} f={f} r={r} {spec}", flush=True)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=q.default_opts(tol=TOL_LIB, zolo_r=r),
+                       return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    o = oracle.eig_partial(A, fraction=f, tol=TOL_LIB, zolo_r=r)
+    k = o["k"]
+    print(f"  steps {info['n_iter']} kinds {info['kinds']} ell {info['ell']} / {o['ell']}", flush=True)
+    assert abs(info["tau"] - o["tau"]) < 1e-8
+    assert info["kinds"] == [st["kind"] for st in o["sched"]]
+    assert [round(x[1]) for x in info["weights"][:info["n_iter"]]] == [r] * info["n_iter"]
+    assert abs(info["ell"] - o["ell"]) <= 2
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - o["w"]) / np.abs(o["w"])) < 1e-12
+    assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["residual"] < 1e-13, met
+    assert met["orth"] < 1e-12, met
+    if r == 1:     # the DWH steps with the plain threshold cut
+        w0, V0, i0 = q.eig(torch.from_numpy(A).cuda(), fraction=f, return_info=True,
+                           opts=q.default_opts(tol=TOL_LIB, tau_policy=0))
+        assert i0["ell"] == info["ell"] and i0["kinds"] == info["kinds"]
+        assert np.max(np.abs(w0.cpu().numpy() - w) / np.abs(w)) < 1e-13
+
+
+@pytest.mark.parametrize("m,n,k,r,kind", [(500, 300, 15, 8, "geo"), (400, 400, 20, 3, "log"),
+                                          (300, 500, 25, 2, "log")])
+def test_zolotarev_svd_vs_oracle(m, n, k, r, kind):
+    """Zolotarev steps in Algorithm 2: kappa = 1e16 with r = 8 (the first
+    step's terms QR-based, s < 1e-3), and log-uniform spectra (wide too)."""
+    torch, q = _gpu()
+    if kind == "geo":
+        A, sig = svd_geometric(m, n, 1011, kappa=1e16)
+    else:
+        A, sig = svd_loguniform(max(m, n), min(m, n), 1012)
+        if m < n:
+            A = A.T.copy()
+    print(f"zolotarev svd m={m} n={n} k={k} r={r}", flush=True)
+    U, S, V, info = q.svd(torch.from_numpy(A).cuda(), k, opts=q.default_opts(tol=TOL_LIB, zolo_r=r),
+                          return_info=True)
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    o = oracle.svd_partial(A, k, tol=TOL_LIB, zolo_r=r)
+    print(f"  steps {info['n_iter']} kinds {info['kinds']} ell {info['ell']} / {o['ell']}", flush=True)
+    assert info["kinds"] == [st["kind"] for st in o["sched"]]
+    assert abs(info["ell"] - o["ell"]) <= 2
+    assert np.max(np.abs(S - o["S"]) / o["S"]) < 1e-12
+    assert np.max(np.abs(S - sig[:k]) / sig[:k]) < 1e-12
+    met = oracle.svd_metrics(A, U, S, V, sig[:k])
+    assert met["residual"] < 1e-13, met
+    assert max(met["orth_u"], met["orth_v"]) < 1e-12, met
+
+
 # ------------------------------------------------------------------ tol = 0.01
 # The paper's threshold (Sec. 4.1, Algorithms 1 and 2) on both sides.  The
 # guarantee the paper gives for the subspace is Theorem 1: sin angle(V0, Q2)
