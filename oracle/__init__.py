@@ -22,6 +22,7 @@ from .partial import eig_partial, svd_partial  # noqa: F401
 from .jacobi import jacobi_eig, jacobi_svd  # noqa: F401
 from .metrics import eig_metrics, svd_metrics  # noqa: F401
 from .zolo import zolo_coeffs, zolo_map, zolo_schedule, zolo_step  # noqa: F401
+from .hermitian import heig_partial, heig_metrics, qr_step_h, chol_step_h  # noqa: F401
 
 # What pins each oracle function (see tests/test_oracle_*.py).
 PINS = {
@@ -41,4 +42,6 @@ PINS = {
                             "partial fractions reproduce the product",
     "zolo_step": "planted iterates equal U Z(Sigma) V^T; Cholesky and QR terms agree; r = 1 equals the "
                  "DWH step",
+    "heig_partial": "real input gives the real eig_partial's result; planted complex spectra to 1e-12; "
+                    "LAPACK zheevd on small n; complex steps on planted iterates equal U r(Sigma) V^H",
 }

@@ -98,6 +98,46 @@ def eig_clustered(n, seed, bulk_frac=0.9, bulk=(-1.0, 0.5), top=(0.5, 1.0),
     return planted_sym(Q, lam), lam
 
 
+def haar_complex(g, n):
+    """Haar-distributed n x n unitary: QR of a complex Gaussian matrix with
+    the phases of diag(R) moved into Q."""
+    G = (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))) / np.sqrt(2.0)
+    Q, R = np.linalg.qr(G)
+    d = np.diag(R)
+    ph = np.where(np.abs(d) > 0, d / np.abs(d), 1.0)
+    return Q * ph[None, :]
+
+
+def planted_herm(Q, lam):
+    """A = Q diag(lam) Q^H, made Hermitian exactly."""
+    A = (Q * lam[None, :]) @ Q.conj().T
+    return 0.5 * (A + A.conj().T)
+
+
+def heig_uniform(n, seed, lo=-1.0, hi=1.0):
+    """Complex Hermitian n x n, eigenvalues i.i.d. uniform on [lo, hi]."""
+    g = rng(seed)
+    Q = haar_complex(g, n)
+    lam = g.uniform(lo, hi, size=n)
+    return planted_herm(Q, lam), lam
+
+
+def heig_clustered(n, seed, bulk_frac=0.9, bulk=(-1.0, 0.5), top=(0.5, 1.0), nclusters=8, width=1e-8):
+    """Complex Hermitian counterpart of eig_clustered (same spectrum recipe)."""
+    g = rng(seed)
+    Q = haar_complex(g, n)
+    nb = int(round(bulk_frac * n))
+    nc = n - nb
+    lam_b = g.uniform(bulk[0], bulk[1], size=nb)
+    sizes = [nc // nclusters + (1 if j < nc % nclusters else 0) for j in range(nclusters)]
+    parts = [lam_b]
+    for j, sz in enumerate(sizes):
+        c = top[0] + (j + 0.5) * (top[1] - top[0]) / nclusters
+        parts.append(c + g.uniform(-0.5 * width, 0.5 * width, size=sz))
+    lam = np.concatenate(parts)
+    return planted_herm(Q, lam), lam
+
+
 def svd_geometric(m, n, seed, kappa=1e16, device=None):
     """m x n (m >= n), sigma_i = kappa^{-(i-1)/(n-1)} (geometric, 1 .. 1/kappa)."""
     g = rng(seed)
