@@ -147,6 +147,26 @@ typedef struct {
 void qdwhp_opts_default(qdwhp_opts* opts);
 const char* qdwhp_strerror(int status);
 
+/* QDWHpartial-EIG of a complex Hermitian matrix (Sec. 4: the Hermitian case
+ * carries over from the real symmetric one with conjugate transposes).
+ * A: n x n complex, interleaved (re, im) doubles, column-major, ld lda in
+ * complex elements, read-only; the full matrix is read (Hermitian assumed).
+ * k = floor(fraction n + 1/2) clamped to [1, n]; which as for qdwhp_eig.
+ * Outputs (device, caller-owned): w[k] real (most wanted first), V (n x k
+ * complex interleaved, ld ldv in complex elements), each column scaled so
+ * that its largest-magnitude entry is real positive (lowest index on ties).
+ * The solve runs the real path on the 2n x 2n real symmetric embedding
+ * [Re A, -Im A; Im A, Re A] (every eigenvalue twice) and takes each cluster
+ * of 2p real Ritz pairs back to p complex ones; info describes that real
+ * solve (ell, kinds, ... of the embedding) with info->k = k.  work:
+ * qdwhp_heig_workspace(n, fraction, opts) bytes.  Returns 0, -i for a bad
+ * argument i, or QDWHP_ERR_* (QDWHP_ERR_NO_SUBSPACE also when a cluster
+ * yields fewer complex vectors than its share). */
+size_t qdwhp_heig_workspace(int64_t n, double fraction, const qdwhp_opts* opts);
+int qdwhp_heig(const double* A, int64_t n, int64_t lda, double fraction, int which, double* w,
+               double* V, int64_t ldv, void* work, size_t lwork, const qdwhp_opts* opts,
+               void* stream, qdwhp_info* info);
+
 /* Coefficients of the Zolotarev step of type (2r+1, 2r) for lower bound l
  * (host only, no GPU): c[2r] (c_1 .. c_2r), a[r] (partial fractions), *M and
  * *l_next = Z(l), Z(x) = M x prod_j (x^2 + c_{2j}) / (x^2 + c_{2j-1}), the

@@ -83,6 +83,9 @@ _SIGS = {
     "qdwhp_opts_default": (None, [ctypes.POINTER(Opts)]),
     "qdwhp_strerror": (ctypes.c_char_p, [_I]),
     "qdwhp_zolo_coeffs": (_I, [_D, _I, _PD, _PD, _PD, _PD]),
+    "qdwhp_heig_workspace": (_SZ, [_I64, _D, ctypes.POINTER(Opts)]),
+    "qdwhp_heig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
+                        ctypes.POINTER(Opts), _P, ctypes.POINTER(Info)]),
     "qdwhp_eig_workspace": (_SZ, [_I64, _D, ctypes.POINTER(Opts)]),
     "qdwhp_svd_workspace": (_SZ, [_I64, _I64, _I64, ctypes.POINTER(Opts)]),
     "qdwhp_eig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
@@ -345,6 +348,28 @@ def syev(H):
     _check(lib().qdwhp_syev(_ptr(Hc), n, n, _ptr(w), _ptr(Wb), n, _ptr(ws), nbytes, _stream(torch),
                             ctypes.byref(sw)), "qdwhp_syev")
     return w, Wb.t(), sw.value
+
+
+def eig_hermitian(A, fraction, which="largest", opts=None, return_info=False):
+    """Wanted eigenpairs of the complex Hermitian complex128 CUDA tensor A
+    (n x n): (w, V[, info]) with w the k real eigenvalues (most wanted first)
+    and V (n x k, complex128), each column's largest-magnitude entry real
+    positive.  Calls qdwhp_heig."""
+    import torch
+    n = A.shape[0]
+    Ac = A.t().contiguous()                      # column-major, interleaved (re, im)
+    k = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    o = opts if opts is not None else default_opts()
+    w = torch.empty(k, dtype=torch.float64, device=A.device)
+    Vb = torch.empty((k, n), dtype=torch.complex128, device=A.device)
+    nbytes = lib().qdwhp_heig_workspace(n, fraction, ctypes.byref(o))
+    ws = _workspace(torch, nbytes, A.device)
+    info = Info()
+    wh = LARGEST if which == "largest" else SMALLEST
+    _check(lib().qdwhp_heig(_ptr(Ac), n, n, fraction, wh, _ptr(w), _ptr(Vb), n, _ptr(ws), nbytes,
+                            ctypes.byref(o), _stream(torch), ctypes.byref(info)), "qdwhp_heig")
+    V = Vb.t()
+    return (w, V, info.as_dict()) if return_info else (w, V)
 
 
 def zolo_coeffs(l, r):
