@@ -98,34 +98,46 @@ def eig_clustered(n, seed, bulk_frac=0.9, bulk=(-1.0, 0.5), top=(0.5, 1.0),
     return planted_sym(Q, lam), lam
 
 
-def haar_complex(g, n):
+def haar_complex(g, n, device=None):
     """Haar-distributed n x n unitary: QR of a complex Gaussian matrix with
-    the phases of diag(R) moved into Q."""
+    the phases of diag(R) moved into Q (on ``device`` with torch when given)."""
     G = (g.standard_normal((n, n)) + 1j * g.standard_normal((n, n))) / np.sqrt(2.0)
-    Q, R = np.linalg.qr(G)
-    d = np.diag(R)
-    ph = np.where(np.abs(d) > 0, d / np.abs(d), 1.0)
+    if device is None:
+        Q, R = np.linalg.qr(G)
+        d = np.diag(R)
+        ph = np.where(np.abs(d) > 0, d / np.abs(d), 1.0)
+        return Q * ph[None, :]
+    import torch
+    Q, R = torch.linalg.qr(torch.from_numpy(G).to(device))
+    d = torch.diagonal(R)
+    ph = torch.where(d.abs() > 0, d / d.abs(), torch.ones_like(d))
     return Q * ph[None, :]
 
 
 def planted_herm(Q, lam):
     """A = Q diag(lam) Q^H, made Hermitian exactly."""
-    A = (Q * lam[None, :]) @ Q.conj().T
-    return 0.5 * (A + A.conj().T)
+    if isinstance(Q, np.ndarray):
+        A = (Q * lam[None, :]) @ Q.conj().T
+        return 0.5 * (A + A.conj().T)
+    import torch
+    lt = torch.as_tensor(lam, dtype=Q.dtype, device=Q.device)
+    A = (Q * lt[None, :]) @ Q.conj().t().contiguous()
+    return 0.5 * (A + A.conj().t())
 
 
-def heig_uniform(n, seed, lo=-1.0, hi=1.0):
+def heig_uniform(n, seed, lo=-1.0, hi=1.0, device=None):
     """Complex Hermitian n x n, eigenvalues i.i.d. uniform on [lo, hi]."""
     g = rng(seed)
-    Q = haar_complex(g, n)
+    Q = haar_complex(g, n, device)
     lam = g.uniform(lo, hi, size=n)
     return planted_herm(Q, lam), lam
 
 
-def heig_clustered(n, seed, bulk_frac=0.9, bulk=(-1.0, 0.5), top=(0.5, 1.0), nclusters=8, width=1e-8):
+def heig_clustered(n, seed, bulk_frac=0.9, bulk=(-1.0, 0.5), top=(0.5, 1.0), nclusters=8, width=1e-8,
+                   device=None):
     """Complex Hermitian counterpart of eig_clustered (same spectrum recipe)."""
     g = rng(seed)
-    Q = haar_complex(g, n)
+    Q = haar_complex(g, n, device)
     nb = int(round(bulk_frac * n))
     nc = n - nb
     lam_b = g.uniform(bulk[0], bulk[1], size=nb)
