@@ -458,11 +458,18 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
  * where they pass its checks; 0: one launch per column), "qr.stacked" (1,
  * default: the QR of [sqrt(c) X; I] in a QR-based step skips the rows of
  * the identity block that no reflector has reached; 0: the full stacked
- * matrix).  Unset keys keep
+ * matrix; the recon choice is read per panel height h as "qr.recon@b",
+ * b = ceil(log2 h), when set), "gemm.shallow_k" (GEMMs with k at most this
+ * run 64x64 tiles; default 128), "batch.lanes.mixed" (lanes of a batch in
+ * mixed precision; default batch.lanes).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.
  */
 int qdwhp_tune_set(const char* key, int64_t value);
 int64_t qdwhp_tune_get(const char* key, int64_t fallback);
+/* Size-bucketed lookup: the value of "key@b" for b = ceil(log2(size)) when
+ * set, else of "key", else fallback (sized keys: "qr.recon@b" by panel
+ * height, "gemm.shallow_k" by none; see above). */
+int64_t qdwhp_tune_get_sized(const char* key, int64_t size, int64_t fallback);
 void qdwhp_tune_clear(void);
 
 /*

@@ -121,6 +121,7 @@ _SIGS = {
                                ctypes.POINTER(Info)]),
     "qdwhp_tune_set": (_I, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_get": (_I64, [ctypes.c_char_p, _I64]),
+    "qdwhp_tune_get_sized": (_I64, [ctypes.c_char_p, _I64, _I64]),
     "qdwhp_tune_clear": (None, []),
     "qdwhp_profile_begin": (None, []),
     "qdwhp_profile_end": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),

@@ -73,8 +73,9 @@ using namespace qdwhp;
 namespace {
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-int default_lanes(int count) {
-  const int64_t t = qdwhp_tune_get("batch.lanes", 8);
+int default_lanes(int count, bool mixed) {
+  const int64_t base = qdwhp_tune_get("batch.lanes", 8);
+  const int64_t t = mixed ? qdwhp_tune_get("batch.lanes.mixed", base) : base;
   return (int)std::max<int64_t>(1, std::min<int64_t>(t, count));
 }
 }  // namespace
@@ -122,7 +123,8 @@ extern "C" int qdwhp_batched(int count, const qdwhp_problem* probs, void* work, 
   for (int i = 0; i < count; ++i) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return problem_cost(probs[a]) > problem_cost(probs[b]); });
-  const int L = std::min(lanes > 0 ? lanes : default_lanes(count), count);
+  const bool mixed = opts && opts->precision == QDWHP_MIXED_FP32;
+  const int L = std::min(lanes > 0 ? lanes : default_lanes(count, mixed), count);
   const bool grouped = qdwhp_tune_get("batch.grouped", 1) != 0;
   int dev = 0;
   int rc = QDWHP_OK;

@@ -516,7 +516,8 @@ void dgemm(const Gemm& g0, hipStream_t s) {
   // FP32-operand launches always take 64x64 tiles: the 128-wide FP32 tile
   // carries FP64 fold registers that limit it to one workgroup per CU (18
   // against 72 TF/s for a 16384^3 Gram).
-  if (g.f32 || (g.splitk == 1 && (tiles < qdwhp_tune_get("gemm.small_tiles", 96) || g.K <= 128))) {
+  if (g.f32 || (g.splitk == 1 && (tiles < qdwhp_tune_get("gemm.small_tiles", 96) ||
+                                  g.K <= qdwhp_tune_get("gemm.shallow_k", 128)))) {
     tm = cdiv(g.M, 64); tn = cdiv(g.N, 64);
     launch_tiles<64>(g, tm, tn, s);
   } else {

@@ -861,13 +861,14 @@ bool stream_capturing(hipStream_t s) {
 int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double* Tall,
               const QrScratch& sc, hipStream_t s, const PanelWatch* watch, bool recon, int64_t stacked) {
   const bool use_recon = recon && sc.cq_part && qdwhp_tune_get("qr.recon", 1) != 0 && !stream_capturing(s);
+  // per panel height: "qr.recon@b" (b = ceil(log2 h)) where the autotuner set it
   for (int64_t c0 = 0; c0 < n; c0 += QB) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
     const int64_t h = panel_rows(m, c0, w, stacked);
     double* V = A + c0 + c0 * lda;
     double* T = Tall + (c0 / QB) * QB * QB;
     bool done = false;
-    if (use_recon && h <= sc.backup_rows) {
+    if (use_recon && h <= sc.backup_rows && qdwhp_tune_get_sized("qr.recon", h, 1) != 0) {
       QDWHP_HIP(hipMemcpy2DAsync(sc.backup, h * sizeof(double), V, lda * sizeof(double), h * sizeof(double),
                                  w, hipMemcpyDeviceToDevice, s));
       done = panel_recon(V, h, w, lda, tau + c0, T, sc, s);

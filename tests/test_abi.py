@@ -124,3 +124,21 @@ def test_zolotarev_step_counts_match_the_oracle():
                 l = min(q.zolo_coeffs(min(l, 1 - 1e-16), r)["l_next"], 1.0)
                 k += 1
             assert k == len(zolo_schedule(s, r)), (s, r)
+
+
+def test_sized_tuning_lookup():
+    """qdwhp_tune_get_sized: "key@b" with b = ceil(log2(size)) first, then "key",
+    then the fallback (host-only calls)."""
+    import paper_2104_14186_amd as q
+    L = q.lib()
+    old = {k: q.tune_get(k, -777) for k in ("zz.test", "zz.test@10")}
+    try:
+        q.tune_set("zz.test", 5)
+        q.tune_set("zz.test@10", 9)
+        assert L.qdwhp_tune_get_sized(b"zz.test", 1000, -1) == 9        # ceil(log2 1000) = 10
+        assert L.qdwhp_tune_get_sized(b"zz.test", 1024, -1) == 9
+        assert L.qdwhp_tune_get_sized(b"zz.test", 1025, -1) == 5        # bucket 11 unset
+        assert L.qdwhp_tune_get_sized(b"zz.none", 1000, -3) == -3
+    finally:
+        L.qdwhp_tune_clear()
+        q.load_tuning()
