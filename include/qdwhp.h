@@ -256,7 +256,10 @@ int qdwhp_spd_inverse(double* Z, int64_t n, int64_t ldz, void* work, size_t lwor
  * R in the upper triangle, the essential parts of the reflectors below it,
  * tau[n] on the device (LAPACK geqrf layout).  Used on the stacked matrix of
  * Eq. (2) and on the spectral projector (Sec. 4.1, Theorem 1).
- * work: qdwhp_geqrf_workspace(m, n) bytes.
+ * work: qdwhp_geqrf_workspace(m, n) bytes.  Panels factored by the
+ * reconstruction path hand the wide part of their trailing update to a
+ * library-owned helper stream; the call's stream waits for it before the
+ * call returns, so the result is ordered on `stream` as usual.
  */
 size_t qdwhp_geqrf_workspace(int64_t m, int64_t n);
 int qdwhp_geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau,
@@ -459,7 +462,10 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
  * default: the QR of [sqrt(c) X; I] in a QR-based step skips the rows of
  * the identity block that no reflector has reached; 0: the full stacked
  * matrix; the recon choice is read per panel height h as "qr.recon@b",
- * b = ceil(log2 h), when set), "gemm.shallow_k" (GEMMs with k at most this
+ * b = ceil(log2 h), when set), "qr.overlap" (1, default: with the
+ * reconstruction path, the trailing update beyond the next panel runs on a
+ * helper stream while the next panel is factored; 0: all on the call's
+ * stream; the two agree to rounding), "gemm.shallow_k" (GEMMs with k at most this
  * run 64x64 tiles; default 128), "batch.lanes.mixed" (lanes of a batch in
  * mixed precision; default batch.lanes).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.

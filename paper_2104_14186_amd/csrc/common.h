@@ -74,6 +74,28 @@ double gemm_flops(const Gemm& g);
 // iterations run uncaptured, Jacobi updates H and V in one launch per round).
 bool no_alloc_mode();
 
+// ------------------------------------------------ helper streams ----
+// A helper stream with a ring of event pairs, leased from a per-device pool
+// (aux_stream.cpp): the sets live until the process ends, so a solve that
+// overlaps work on a second stream creates no stream or event per call.
+constexpr int kAuxRing = 4;
+struct AuxSet {
+  hipStream_t s;
+  hipEvent_t ready[kAuxRing], done[kAuxRing];
+};
+class AuxLease {
+ public:
+  explicit AuxLease(int dev);
+  ~AuxLease();     // waits for the helper stream, then returns the set to the pool
+  AuxSet* operator->() const { return set_; }
+  AuxLease(const AuxLease&) = delete;
+  AuxLease& operator=(const AuxLease&) = delete;
+
+ private:
+  int dev_;
+  AuxSet* set_ = nullptr;
+};
+
 // Live kernel timing (prof.cpp).
 bool prof_active();
 void prof_begin_launch(hipStream_t s, void** tok);

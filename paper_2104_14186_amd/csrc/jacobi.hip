@@ -620,48 +620,7 @@ bool converged(double off, double prev, double tol, int sw) {
 // overlapping the next rounds' pair solves and tile updates.  The rotations
 // and skip flags of kRing consecutive rounds live in a ring of slots; a
 // round waits for the update that last read its slot before refilling it.
-constexpr int kRing = 4;
-
-struct AuxSet {
-  hipStream_t s;
-  hipEvent_t ready[kRing], done[kRing];
-};
-
-std::mutex aux_mu;
-std::map<int, std::vector<AuxSet*>> aux_free;   // per device; sets live until the process ends
-
-class AuxLease {
- public:
-  explicit AuxLease(int dev) : dev_(dev) {
-    {
-      std::lock_guard<std::mutex> g(aux_mu);
-      auto& v = aux_free[dev];
-      if (!v.empty()) { set_ = v.back(); v.pop_back(); }
-    }
-    if (!set_) {
-      AuxSet* a = new AuxSet;
-      QDWHP_HIP(hipStreamCreateWithFlags(&a->s, hipStreamNonBlocking));
-      for (int i = 0; i < kRing; ++i) {
-        QDWHP_HIP(hipEventCreateWithFlags(&a->ready[i], hipEventDisableTiming));
-        QDWHP_HIP(hipEventCreateWithFlags(&a->done[i], hipEventDisableTiming));
-      }
-      set_ = a;
-    }
-  }
-  ~AuxLease() {
-    // work still queued (an error path) finishes before the set is reused
-    (void)hipStreamSynchronize(set_->s);
-    std::lock_guard<std::mutex> g(aux_mu);
-    aux_free[dev_].push_back(set_);
-  }
-  AuxSet* operator->() const { return set_; }
-  AuxLease(const AuxLease&) = delete;
-  AuxLease& operator=(const AuxLease&) = delete;
-
- private:
-  int dev_;
-  AuxSet* set_ = nullptr;
-};
+constexpr int kRing = kAuxRing;   // the helper set's event ring (common.h)
 
 }  // namespace
 

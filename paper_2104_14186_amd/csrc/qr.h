@@ -15,6 +15,8 @@ struct QrScratch {
   // factors, failure flag, and a copy of the panel (backup_rows x QB)
   double* cq_part = nullptr; double* cq_small = nullptr; int* cq_flag = nullptr;
   double* backup = nullptr; int64_t backup_rows = 0;
+  // the trailing updates' buffers on the helper stream (W1, W2, split-K scratch)
+  double* W1b = nullptr; double* W2b = nullptr; double* wsb = nullptr; int64_t wsb_doubles = 0;
 };
 
 int64_t qr_scratch_doubles(int64_t m, int64_t n);
@@ -31,7 +33,10 @@ using PanelWatch = std::function<bool(int64_t c0, int w)>;
 // recon: factor sub-panels by Cholesky QR with Householder reconstruction
 // where they pass its checks (not while the stream is being captured; the
 // tuning key "qr.recon" = 0 turns it off); the host then waits for the
-// stream once per panel.
+// stream once per panel.  Then the trailing updates also run on a helper
+// stream, overlapping the factorization of the next panel ("qr.overlap" =
+// 0 turns that off; the next panel's columns then go through a narrower
+// product whose K split differs, so results agree to rounding, not bits).
 // stacked > 0: A is [A1; I] with A1 the first `stacked` rows and an n x n
 // identity below (the QR-based step's [sqrt(c) X; I]); panels and updates
 // then skip the rows of the identity block no reflector has reached yet

@@ -42,6 +42,7 @@
 //  * trailing update C <- (I - V T^T V^T) C as three GEMMs with V read in
 //    place from below the diagonal (unit-lower operand mask).
 #include <algorithm>
+#include <memory>
 
 #include "common.h"
 #include "qdwhp.h"
@@ -747,7 +748,7 @@ int64_t qr_scratch_doubles(int64_t m, int64_t n) {
   const int64_t nn = n > 1 ? n : 1;
   const int64_t mm = m > 1 ? m : 1;
   return 2 * 64 * QB + 2 * QB + QB * QB + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn + 256 +
-         (int64_t)NG_MAX * RB * RB + 4 * RB * RB + 64 + QB * mm;
+         (int64_t)NG_MAX * RB * RB + 4 * RB * RB + 64 + QB * mm + 2 * QB * nn + 64 * QB * QB + 8 * QB * nn;
 }
 
 QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
@@ -764,7 +765,10 @@ QrScratch carve_qr_scratch(double* w, int64_t m, int64_t n) {
   s.cq_part = w; w += (int64_t)NG_MAX * RB * RB;
   s.cq_small = w; w += 4 * RB * RB;
   s.cq_flag = reinterpret_cast<int*>(w); w += 64;
-  s.backup = w; s.backup_rows = mm;
+  s.backup = w; s.backup_rows = mm; w += QB * mm;
+  s.W1b = w; w += QB * nn;
+  s.W2b = w; w += QB * nn;
+  s.wsb = w; s.wsb_doubles = 64 * QB * QB + 8 * QB * nn;
   return s;
 }
 
@@ -784,21 +788,31 @@ void build_t(const double* V, int64_t h, int w, int64_t ld, const double* tau, d
 }
 
 // C (h x nc, ld) <- (I - V T^T V^T) C: W1 = V^T C, W2 = T^T W1, C -= V W2.
+// Work buffers of a block-reflector update (one set per stream).
+struct QtBufs {
+  double* W1; double* W2; double* ws; int64_t ws_doubles;
+};
+QtBufs main_bufs(const QrScratch& sc) { return QtBufs{sc.W1, sc.W2, sc.ws, sc.ws_doubles}; }
+
 void apply_qt(const double* V, int64_t h, int w, int64_t ld, const double* T, double* C, int64_t nc,
-              const QrScratch& sc, hipStream_t s) {
+              const QtBufs& b, hipStream_t s) {
   Gemm g1;   // W1 = V^T C
   g1.M = w; g1.N = nc; g1.K = h; g1.A = V; g1.lda = ld; g1.ta = true; g1.a_unit_lower = true;
-  g1.B = C; g1.ldb = ld; g1.C = sc.W1; g1.ldc = QB; g1.ws = sc.ws; g1.ws_doubles = sc.ws_doubles;
+  g1.B = C; g1.ldb = ld; g1.C = b.W1; g1.ldc = QB; g1.ws = b.ws; g1.ws_doubles = b.ws_doubles;
   dgemm(g1, s);
   Gemm g2;   // W2 = T^T W1
   g2.M = w; g2.N = nc; g2.K = w; g2.A = T; g2.lda = QB; g2.ta = true;
-  g2.B = sc.W1; g2.ldb = QB; g2.C = sc.W2; g2.ldc = QB;
+  g2.B = b.W1; g2.ldb = QB; g2.C = b.W2; g2.ldc = QB;
   dgemm(g2, s);
   Gemm g3;   // C -= V W2
   g3.M = h; g3.N = nc; g3.K = w; g3.alpha = -1.0; g3.beta = 1.0;
-  g3.A = V; g3.lda = ld; g3.a_unit_lower = true; g3.B = sc.W2; g3.ldb = QB;
+  g3.A = V; g3.lda = ld; g3.a_unit_lower = true; g3.B = b.W2; g3.ldb = QB;
   g3.C = C; g3.ldc = ld;
   dgemm(g3, s);
+}
+void apply_qt(const double* V, int64_t h, int w, int64_t ld, const double* T, double* C, int64_t nc,
+              const QrScratch& sc, hipStream_t s) {
+  apply_qt(V, h, w, ld, T, C, nc, main_bufs(sc), s);
 }
 
 }  // namespace
@@ -862,7 +876,29 @@ int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double*
               const QrScratch& sc, hipStream_t s, const PanelWatch* watch, bool recon, int64_t stacked) {
   const bool use_recon = recon && sc.cq_part && qdwhp_tune_get("qr.recon", 1) != 0 && !stream_capturing(s);
   // per panel height: "qr.recon@b" (b = ceil(log2 h)) where the autotuner set it
-  for (int64_t c0 = 0; c0 < n; c0 += QB) {
+  // Overlap (only where the host already waits per panel): the update of
+  // the next panel's columns stays on the main stream, the rest of the
+  // trailing update goes to a helper stream and runs while the next panel
+  // is factored.  A panel's columns must have every earlier update, so
+  // the main stream waits for the helper's previous update before touching
+  // the next panel.  Every column gets the same updates in the same order
+  // as on one stream; only the K split of the narrow V^T C product (chosen
+  // from its tile count) differs, a rounding-level difference.
+  const bool overlap = use_recon && sc.W1b && !no_alloc_mode() && qdwhp_tune_get("qr.overlap", 1) != 0;
+  std::unique_ptr<AuxLease> aux;
+  if (overlap) {
+    int dev = 0;
+    QDWHP_HIP(hipGetDevice(&dev));
+    aux.reset(new AuxLease(dev));
+  }
+  const QtBufs mb = main_bufs(sc);
+  const QtBufs ab = overlap ? QtBufs{sc.W1b, sc.W2b, sc.wsb, sc.wsb_doubles} : mb;
+  int64_t last_wide = -1;        // panel index of the helper stream's last update
+  auto join = [&]() {
+    if (last_wide >= 0) QDWHP_HIP(hipStreamWaitEvent(s, (*aux)->done[last_wide % kAuxRing], 0));
+  };
+  int64_t pi = 0;
+  for (int64_t c0 = 0; c0 < n; c0 += QB, ++pi) {
     const int w = (int)((n - c0) < QB ? (n - c0) : QB);
     const int64_t h = panel_rows(m, c0, w, stacked);
     double* V = A + c0 + c0 * lda;
@@ -899,10 +935,27 @@ int64_t geqrf(double* A, int64_t m, int64_t n, int64_t lda, double* tau, double*
       }
     }
     build_t(V, h, w, lda, tau + c0, T, sc, s);
-    if (watch && (*watch)(c0, w)) return c0 + w;   // the caller needs no further columns
+    if (watch && (*watch)(c0, w)) { join(); return c0 + w; }   // the caller needs no further columns
     const int64_t nc = n - c0 - w;
-    if (nc > 0) apply_qt(V, h, w, lda, T, A + c0 + (c0 + w) * lda, nc, sc, s);
+    if (nc <= 0) continue;
+    double* C = A + c0 + (c0 + w) * lda;
+    if (!overlap) { apply_qt(V, h, w, lda, T, C, nc, mb, s); continue; }
+    const int64_t nnext = nc < QB ? nc : QB;
+    const int64_t nrest = nc - nnext;
+    if (nrest > 0) {                           // the rest, on the helper stream
+      hipStream_t sb = (*aux)->s;
+      QDWHP_HIP(hipEventRecord((*aux)->ready[pi % kAuxRing], s));
+      QDWHP_HIP(hipStreamWaitEvent(sb, (*aux)->ready[pi % kAuxRing], 0));
+      apply_qt(V, h, w, lda, T, C + nnext * lda, nrest, ab, sb);
+    }
+    join();                                    // the next panel has the earlier updates
+    apply_qt(V, h, w, lda, T, C, nnext, mb, s);
+    if (nrest > 0) {
+      QDWHP_HIP(hipEventRecord((*aux)->done[pi % kAuxRing], (*aux)->s));
+      last_wide = pi;
+    }
   }
+  join();
   return n;
 }
 

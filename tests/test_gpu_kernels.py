@@ -100,6 +100,33 @@ def _qr_path(q, torch, A, recon):
     return Q.cpu().numpy(), R.cpu().numpy(), tau.cpu().numpy()
 
 
+
+@pytest.mark.parametrize("m,n", [(3000, 1000), (1500, 1500), (4100, 193)])
+def test_qr_overlapped_trailing_updates(m, n):
+    """The trailing updates on a helper stream, overlapping the next
+    panel's factorization, give the one-stream factorization to rounding
+    (only the K split of the narrow product differs)."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    g = np.random.default_rng(m + 3 * n)
+    A = g.standard_normal((m, n)) * np.geomspace(1.0, 1e-3, n)[None, :]
+    print(f"qr overlap m={m} n={n}", flush=True)
+    old = q.tune_get("qr.overlap", 1)
+    out = {}
+    try:
+        for ov in (0, 1):
+            q.tune_set("qr.overlap", ov)
+            out[ov] = _qr_path(q, torch, A, 1)
+    finally:
+        q.tune_set("qr.overlap", old)
+    (Q0, R0, t0), (Q1, R1, t1) = out[0], out[1]
+    sc = np.abs(A).max()
+    assert np.abs(Q1 @ R1 - A).max() / sc < 4e-15 * np.sqrt(m)
+    assert np.abs(Q1.T @ Q1 - np.eye(n)).max() < 4e-15 * np.sqrt(m)
+    assert np.abs(R1 - R0).max() < 1e-12 * sc * np.sqrt(m)
+    assert np.abs(t1 - t0).max() < 1e-12
+    assert np.abs(Q1 - Q0).max() < 1e-11
+
 @pytest.mark.parametrize("m,n,kind", [(2000, 300, "gauss"), (517, 517, "gauss"), (3000, 700, "graded"),
                                       (1200, 400, "dependent"), (800, 800, "projector")])
 def test_qr_reconstructed_panels_match_column_steps(m, n, kind):
