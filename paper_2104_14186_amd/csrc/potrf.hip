@@ -197,9 +197,17 @@ struct Rec {
 
 }  // namespace
 
+// Largest n1 x n2 product buffer over every level of the recursion on m
+// rows: a lopsided split (n2 much smaller than n1, e.g. m = 2 NB + 1) needs
+// less at the top than its first half needs one level down.
+static int64_t rec_t_doubles(int64_t m) {
+  if (m <= NB) return 0;
+  const int64_t n1 = NB * cdiv(cdiv(m, NB), 2), n2 = m - n1;
+  return std::max(n1 * n2, std::max(rec_t_doubles(n1), rec_t_doubles(n2)));
+}
+
 int64_t spd_inverse_doubles(int64_t n) {
-  const int64_t n1 = NB * cdiv(cdiv(n, NB), 2);
-  return n * n + n1 * (n - n1 > 0 ? n - n1 : 1) + 64;
+  return n * n + std::max<int64_t>(rec_t_doubles(n), 1) + 64;
 }
 
 void chol_inverse_factor(double* Z, int64_t n, int64_t ldz, double* work, int* flag, hipStream_t s) {
