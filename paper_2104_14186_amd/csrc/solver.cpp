@@ -356,6 +356,17 @@ double table1_iter_flops(const std::vector<DwhStep>& sched, double m, double n) 
   return f;
 }
 
+// Columns of the projector QR that can matter: a solve for k values needs
+// ell = n - ind + 1 >= k, i.e. its first small diagonal entry at index
+// ind <= n - k + 1, and an attempt with a smaller ell is retried whatever
+// the later columns hold.  The leading columns of a Householder QR do not
+// depend on the later ones, so only the first n - k + 1 columns are
+// factored and updated (the trailing updates of the rest are skipped); a
+// threshold given by the caller (replay) bounds nothing and keeps all n.
+int64_t projector_qr_cols(int64_t n, int64_t k, bool replay) {
+  return replay ? n : std::max<int64_t>(1, std::min<int64_t>(n, n - k + 1));
+}
+
 // Projector QR watch: after each panel, read its part of diag(R) (final
 // once the panel is factored) and stop at the first panel holding an entry
 // below tol, or a non-finite one: ind is the first such index, and only the
@@ -1144,7 +1155,7 @@ int eig_project(SolveState& S, std::vector<double>& theta, int64_t& ell, int64_t
   }
   std::vector<double> d;
   const PanelWatch watch = diag_watch(Bq, n, P.diag, o.tol, &d, s);
-  geqrf(Bq, n, n, n, P.tau, P.Tall, P.qrs, s, &watch);
+  geqrf(Bq, n, projector_qr_cols(n, k, S.replay), n, P.tau, P.Tall, P.qrs, s, &watch);
   int hflags[8];
   QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
   QDWHP_HIP(hipStreamSynchronize(s));
@@ -1154,7 +1165,7 @@ int eig_project(SolveState& S, std::vector<double>& theta, int64_t& ell, int64_t
   if (any_nonfinite(d)) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
   ind = find_ind(d, o.tol);
   ell = n - ind + 1;
-  if (ell <= 0) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
+  if (ell <= 0 || (ell < k && !S.replay)) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
   // ---- Q2 = H_1 ... H_{ind-1} [0; I_ell]
   Q2 = Q2buf;
   double* Y = o.use_omega ? P.Z : X;          // the buffers free once Q2 is formed
@@ -1354,7 +1365,7 @@ int svd_project(SolveState& S, std::vector<double>& sig, int64_t& ell, int64_t& 
   mirror_upper(P.Z, nn, nn, s);
   std::vector<double> d;
   const PanelWatch watch = diag_watch(P.Z, nn, P.diag, o.tol, &d, s);
-  geqrf(P.Z, nn, nn, nn, P.tau, P.Tall, P.qrs, s, &watch);
+  geqrf(P.Z, nn, projector_qr_cols(nn, k, S.replay), nn, P.tau, P.Tall, P.qrs, s, &watch);
   int hflags[8];
   QDWHP_HIP(hipMemcpyAsync(hflags, P.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
   QDWHP_HIP(hipStreamSynchronize(s));
@@ -1364,7 +1375,7 @@ int svd_project(SolveState& S, std::vector<double>& sig, int64_t& ell, int64_t& 
   if (any_nonfinite(d)) { S.ret(QDWHP_ERR_NONFINITE); return 0; }
   ind = find_ind(d, o.tol);
   ell = nn - ind + 1;
-  if (ell <= 0) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
+  if (ell <= 0 || (ell < k && !S.replay)) { S.status = QDWHP_ERR_NO_SUBSPACE; return S.replay ? 0 : 1; }
   Q2 = (X == P.X) ? P.Xn : P.X;
   Y = X;
   orgqr(P.Z, nn, nn, P.Tall, ind - 1, ind - 1, ell, Q2, nn, P.qrs, s);
