@@ -4,7 +4,7 @@
 
 namespace qdwhp {
 
-// Doubles of workspace needed for at least one k split (more allow more).
+// Doubles of workspace for up to 16 splits of k (at least m * 8 allow one).
 int64_t skinny_ws_doubles(int64_t m, int nv);
 // C (m x nv, ldc) = alpha A (m x k, lda) B (k x nv, ldb); nv <= 32; ws holds
 // the per-split partial sums (ws_doubles >= skinny_ws_doubles(m, nv)).

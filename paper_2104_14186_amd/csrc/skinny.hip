@@ -15,6 +15,7 @@ namespace {
 
 constexpr int ST = 256;   // threads (rows) per workgroup
 constexpr int KC = 128;   // k values staged per pass
+constexpr int KMIN = 32;  // fewest k values of one split
 
 template <int NVC>
 __global__ __launch_bounds__(ST) void skinny_kernel(const double* A, int64_t lda, int64_t m, int64_t k,
@@ -38,16 +39,14 @@ __global__ __launch_bounds__(ST) void skinny_kernel(const double* A, int64_t lda
     if (i < m) {
       const double* Ai = A + i + kb * lda;
       int kk = 0;
-      for (; kk + 4 <= kn; kk += 4) {   // four independent loads in flight
-        const double a0 = Ai[(int64_t)kk * lda], a1 = Ai[(int64_t)(kk + 1) * lda];
-        const double a2 = Ai[(int64_t)(kk + 2) * lda], a3 = Ai[(int64_t)(kk + 3) * lda];
+      for (; kk + 8 <= kn; kk += 8) {   // eight independent loads in flight
+        double a[8];
 #pragma unroll
-        for (int j = 0; j < NVC; ++j) {
-          acc[j] += a0 * Bs[kk][j];
-          acc[j] += a1 * Bs[kk + 1][j];
-          acc[j] += a2 * Bs[kk + 2][j];
-          acc[j] += a3 * Bs[kk + 3][j];
-        }
+        for (int u = 0; u < 8; ++u) a[u] = Ai[(int64_t)(kk + u) * lda];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int j = 0; j < NVC; ++j) acc[j] += a[u] * Bs[kk + u][j];
       }
       for (; kk < kn; ++kk) {
         const double a = Ai[(int64_t)kk * lda];
@@ -77,15 +76,18 @@ __global__ void skinny_reduce(const double* part, int64_t m, int nvc, int nv, in
 template <int NVC>
 void launch(const double* A, int64_t lda, int64_t m, int64_t k, const double* B, int64_t ldb, int nv,
             double alpha, double* C, int64_t ldc, double* ws, int64_t ws_doubles, hipStream_t s) {
+  // Small m has few row blocks, so k is split finely (down to KMIN values
+  // per split) to keep enough workgroups reading A at once; large m splits
+  // k coarsely and reads A in long runs.
   const int64_t rb = cdiv(m, ST);
   int64_t S = cdiv(1024, rb);                       // about 1024 workgroups
-  const int64_t smax_k = cdiv(k, 4 * KC);            // at least 4 staged passes per split
+  const int64_t smax_k = cdiv(k, KMIN);
   if (S > smax_k) S = smax_k;
   const int64_t smax_ws = ws_doubles / (m * NVC);
   if (S > smax_ws) S = smax_ws;
   if (S > 64) S = 64;
   if (S < 1) throw HipError{hipErrorInvalidValue};   // workspace below one split
-  const int64_t kchunk = cdiv(cdiv(k, S), KC) * KC;
+  const int64_t kchunk = cdiv(cdiv(k, S), KMIN) * KMIN;
   S = cdiv(k, kchunk);
   skinny_kernel<NVC><<<dim3((unsigned)rb, (unsigned)S), ST, 0, s>>>(A, lda, m, k, B, ldb, nv, kchunk, ws);
   QDWHP_LAUNCH_CHECK();
@@ -155,7 +157,8 @@ void skinny_gemm_t(const double* A, int64_t lda, int64_t m, int64_t n, const dou
   QDWHP_LAUNCH_CHECK();
 }
 
-int64_t skinny_ws_doubles(int64_t m, int nv) { return m * (nv <= 8 ? 8 : nv <= 16 ? 16 : 32); }
+// Room for 16 splits of k (fewer when a caller passes less).
+int64_t skinny_ws_doubles(int64_t m, int nv) { return 16 * m * (nv <= 8 ? 8 : nv <= 16 ? 16 : 32); }
 
 void skinny_gemm(const double* A, int64_t lda, int64_t m, int64_t k, const double* B, int64_t ldb, int nv,
                  double alpha, double* C, int64_t ldc, double* ws, int64_t ws_doubles, hipStream_t s) {

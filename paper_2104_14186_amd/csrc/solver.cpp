@@ -722,8 +722,9 @@ constexpr int kDcVectors = 4;
 
 int64_t dc_node_doubles(int64_t ell) {
   const int64_t e2 = ell * ell;
-  // polar phase: X, Xn, Z, spd + product, W, Q; then C
-  return 3 * e2 + spd_inverse_doubles(ell) + e2 + 4 * e2 + e2 + 1024;
+  // polar phase: X, Xn, Z, spd + product, W, Q; then C; the shift's
+  // Lanczos products
+  return 3 * e2 + spd_inverse_doubles(ell) + e2 + 4 * e2 + e2 + 1024 + skinny_ws_doubles(ell, kDcVectors);
 }
 
 // Orthonormal basis (ell x r, ld ell) of range(P) for the projector P (ell x
