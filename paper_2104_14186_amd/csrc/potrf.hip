@@ -13,7 +13,7 @@
 //      [Z11 Z12; . Z22] gives W11 = chol(Z11), W12 = W11^{-T} Z12,
 //      Z22 <- Z22 - W12^T W12, W22 = chol(Z22) and
 //      W^{-1}_{12} = -W11^{-1} W12 W22^{-1}; 64x64 leaves are factored and
-//      inverted by one wave (rows in registers, broadcasts through LDS);
+//      inverted by one workgroup of four waves (below);
 //   2. Z^{-1} = W^{-1} W^{-T}, upper tiles only, K starting at the tile column;
 //   3. mirror the upper triangle.
 #include <algorithm>
@@ -29,97 +29,134 @@ constexpr int NB = 64;
 
 // Factor the bs x bs leaf (bs <= 64) at Z (upper triangle read) and write its
 // inverse factor W^{-1} (upper, zeros below) to Wi.  The factor W itself is
-// written back to Z's upper triangle.
+// written back to Z's upper triangle.  Rows and columns past bs are padded
+// with the identity, so the padded block factors to the identity and leaves
+// the leading block untouched.
 //
-// One wave of 64 lanes, no workgroup barriers on the critical path.  With
-// L = W^T (lower), lane i keeps row i of the matrix in registers (a[0..i]);
-// rows past bs are padded with the identity, so the padded block factors to
-// the identity and leaves the leading block untouched.
-//   factorisation (right-looking): at step k the lanes publish a(:, k) in
-//   LDS, every lane reads the pivot a_kk, scales its own entry to
-//   L_ik = a_ik / sqrt(a_kk) and updates a_ij -= L_ik L_jk for j > k, reading
-//   L_jk = a_jk / sqrt(a_kk) as a broadcast from LDS;
-//   inverse M = L^{-1} (forward substitution, lane j owning column j of M):
-//   M_kj = (delta_kj - sum_{i<k} L_ki M_ij) / L_kk, the row L_k,0..k-1 read
-//   as a broadcast from LDS; W^{-1} = M^T is written column by column.
-constexpr int LW = 64;   // lanes of the leaf wave
-__device__ __forceinline__ void leaf_body(double* Z, int64_t ldz, double* Wi, int64_t ldw, int bs, int* flag) {
-  __shared__ double S[NB][NB + 1];     // S[r][c]: the input, then L, then M^T
-  __shared__ double colbuf[2][NB];
-  const int i = threadIdx.x;
-  // coalesced load of the upper triangle (lane = row of Z); identity padding
-#pragma clang loop unroll_count(4)
-  for (int c = 0; c < NB; ++c) {
-    double v = (i == c) ? 1.0 : 0.0;
-    if (c < bs && i <= c) v = Z[i + (int64_t)c * ldz];
-    S[i][c] = v;
-  }
-  __syncthreads();
-  double a[NB];
+// One workgroup of four waves (one per SIMD), one barrier per step.  With
+// L = W^T (lower):
+//   factorisation (right-looking): wave w keeps the columns j = 4c + w of
+//   the matrix in registers, lane = row.  At step k every wave reads column
+//   k from the LDS buffer, forms L(i, k) = A(i, k) / sqrt(A(k, k)) and
+//   updates its trailing columns, A(i, j) -= L(i, k) L(j, k); the wave that
+//   owns column k + 1 updates it first and publishes it into the other
+//   buffer.  The pivot's reciprocal square root is the hardware estimate
+//   refined by two Newton steps.
+//   inverse M = L^{-1} (right-looking): lane = column j, wave w keeps the
+//   sums U(r, j) = sum_{k < r} L(r, k) M(k, j) for the rows r = 4q + w.
+//   Row k of M, (delta - U(k, :)) / L(k, k), is published by the wave that
+//   owns row k one step ahead and stored at once as column k of W^{-1} = M^T;
+//   every wave then adds L(r, k) M(k, :) to its rows past k + 1.
+// The cyclic layouts keep all four waves busy as the active part shrinks;
+// each wave runs its own copy of the steps, so every register index and
+// every skipped update is decided at compile time.
+constexpr int LW = 256;   // threads of the leaf workgroup
+constexpr int LQ = NB / 4;   // columns / rows per wave
+
+template <int W>
+__device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, int64_t ldw, int bs, int* flag,
+                                          double (*S)[NB + 1], double (*cl)[NB], double* rpv) {
+  const int i = threadIdx.x & 63;
+  double a[LQ];                        // a[c] = A(i, 4c + W) (lower part; the upper part is never read)
 #pragma clang loop unroll(full)
-  for (int j = 0; j < NB; ++j) a[j] = S[j][i];   // row i of the lower triangle (S is zero below its diagonal)
+  for (int c = 0; c < LQ; ++c) a[c] = S[i][4 * c + W];
+  if (W == 0) cl[0][i] = a[0];         // column 0
+  __syncthreads();
   bool bad = false;
-  double piv = 1.0;                      // this lane's L_ii
 #pragma clang loop unroll(full)
   for (int k = 0; k < NB; ++k) {
-    // branch-free step: every lane publishes a_ik, reads the pivot, then
-    // publishes its L_ik in the other buffer
-    double* craw = colbuf[0];
-    double* cl = colbuf[1];
-    craw[i] = a[k];
-    __syncthreads();
-    double d = craw[k];
+    const double* buf = cl[k & 1];
+    double d = buf[k];
+    const double ai = buf[i];
     const bool nonpos = !(d > 0.0) || !isfinite(d);
     bad = bad || nonpos;
     d = nonpos ? 1.0 : d;
-    const double p = sqrt(d);
-    const double lik = a[k] / p;
-    a[k] = (i == k) ? p : lik;
-    piv = (i == k) ? p : piv;
-    cl[i] = lik;
-    __syncthreads();
+    double y = __builtin_amdgcn_rsq(d);
 #pragma clang loop unroll(full)
-    for (int j = k + 1; j < NB; ++j) a[j] -= lik * cl[j];   // L_jk as a broadcast
+    for (int it = 0; it < 2; ++it) y = __builtin_fma(y, __builtin_fma(-0.5 * d * y, y, 0.5), y);
+    const double p = d * y;                       // L(k, k)
+    const double lik = (i > k) ? ai * y : 0.0;    // L(i, k) for the rows past k
+    const double li2 = lik * y;                   // times A(j, k) gives L(i, k) L(j, k)
+    if ((k & 3) == W) a[k >> 2] = (i == k) ? p : ((i > k) ? lik : a[k >> 2]);   // keep L(:, k)
+    if (W == 0 && i == 0) rpv[k] = y;
+    if (k + 1 < NB && ((k + 1) & 3) == W) {       // column k + 1 first, then publish it
+      a[(k + 1) >> 2] = __builtin_fma(-li2, buf[k + 1], a[(k + 1) >> 2]);
+      cl[(k + 1) & 1][i] = a[(k + 1) >> 2];
+    }
+#pragma clang loop unroll(full)
+    for (int c = 0; c < LQ; ++c) {
+      const int j = 4 * c + W;
+      if (j <= k || j == k + 1) continue;         // finished, or published above
+      a[c] = __builtin_fma(-li2, buf[j], a[c]);
+    }
     __syncthreads();
   }
-  if (bad && i == 0) *flag = 1;
-  // L to LDS (row i; entries past the diagonal are never read)
+  if (bad && W == 0 && i == 0) *flag = 1;
+  // L to LDS (row i), then W = L^T into Z's upper triangle: Z(r, c) =
+  // L(c, r) for c >= r; this wave writes the columns c = 4q + W (lane = row)
 #pragma clang loop unroll(full)
-  for (int j = 0; j < NB; ++j) S[i][j] = a[j];
+  for (int c = 0; c < LQ; ++c) S[i][4 * c + W] = a[c];
   __syncthreads();
-  // W = L^T into Z's upper triangle (lane = row of Z)
   if (i < bs) {
-#pragma clang loop unroll_count(4)
-    for (int c = i; c < bs; ++c) Z[i + (int64_t)c * ldz] = S[c][i];
+#pragma clang loop unroll(full)
+    for (int q = 0; q < LQ; ++q) {
+      const int c = 4 * q + W;
+      if (c < bs && c >= i) Z[i + (int64_t)c * ldz] = S[c][i];
+    }
   }
-  // inverse M = L^{-1}, lane j owning column j; the diagonal reciprocals
-  // are formed once (lane k holds 1/L_kk) and read across the wave, so the
-  // chain of each column has no division
-  const double rd = 1.0 / piv;
-  const long long rdb = __double_as_longlong(rd);
-  const int rd_lo = (int)(rdb & 0xffffffffLL), rd_hi = (int)(rdb >> 32);
-  double m[NB];
+  double acc[LQ];                      // U(4q + W, j)
+#pragma clang loop unroll(full)
+  for (int q = 0; q < LQ; ++q) acc[q] = 0.0;
+  if (W == 0) {                        // row 0 of M
+    const double m0 = ((i == 0) ? 1.0 : 0.0) * rpv[0];
+    cl[0][i] = m0;
+    if (i < bs) Wi[i] = m0;
+  }
+  __syncthreads();
 #pragma clang loop unroll(full)
   for (int k = 0; k < NB; ++k) {
-    double s0 = (k == i) ? 1.0 : 0.0, s1 = 0.0;   // two independent chains
-#pragma clang loop unroll(full)
-    for (int q = 0; q < k; ++q) {
-      if (q & 1) s1 -= S[k][q] * m[q]; else s0 -= S[k][q] * m[q];
-      if ((q & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+    const double mk = cl[k & 1][i];    // M(k, j)
+    if (k + 1 < NB && ((k + 1) & 3) == W) {       // row k + 1 of M, published one step ahead
+      const int q1 = (k + 1) >> 2;
+      acc[q1] = __builtin_fma(S[k + 1][k], mk, acc[q1]);
+      const double m1 = (((i == k + 1) ? 1.0 : 0.0) - acc[q1]) * rpv[k + 1];
+      cl[(k + 1) & 1][i] = m1;
+      if (i < bs && k + 1 < bs) Wi[i + (int64_t)(k + 1) * ldw] = m1;   // W^{-1}(j, k + 1) = M(k + 1, j)
     }
-    const long long rk = ((long long)__builtin_amdgcn_readlane(rd_hi, k) << 32) |
-                         (unsigned)__builtin_amdgcn_readlane(rd_lo, k);
-    m[k] = (s0 + s1) * __longlong_as_double(rk);
+#pragma clang loop unroll(full)
+    for (int q = 0; q < LQ; ++q) {
+      const int r = 4 * q + W;
+      if (r <= k + 1) continue;                   // finished, or published above
+      acc[q] = __builtin_fma(S[r][k], mk, acc[q]);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void leaf_body(double* Z, int64_t ldz, double* Wi, int64_t ldw, int bs, int* flag) {
+  __shared__ double S[NB][NB + 1];     // the input (S[i][j] = A(i, j), j <= i), then L
+  __shared__ double cl[2][NB];         // column k of the factorisation / row k of M
+  __shared__ double rpv[NB];           // 1 / L(k, k)
+  const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
+  {   // coalesced load of Z's upper triangle, all loads in flight: wave w
+      // loads the columns c = 4q + w; S[c][r] = Z(r, c) = A(c, r), r <= c
+    double v[LQ];
+#pragma clang loop unroll(full)
+    for (int q = 0; q < LQ; ++q) {
+      const int c = 4 * q + w;
+      double x = (i == c) ? 1.0 : 0.0;
+      if (c < bs && i <= c) x = Z[i + (int64_t)c * ldz];
+      v[q] = x;
+    }
+#pragma clang loop unroll(full)
+    for (int q = 0; q < LQ; ++q) S[4 * q + w][i] = v[q];
   }
   __syncthreads();
-  // W^{-1} = M^T: M's column i (held by lane i) is row i of W^{-1}; staged
-  // through LDS so the stores run down columns
-#pragma clang loop unroll(full)
-  for (int k = 0; k < NB; ++k) S[k][i] = m[k];
-  __syncthreads();
-  if (i < bs) {
-#pragma clang loop unroll_count(4)
-    for (int c = 0; c < bs; ++c) Wi[i + (int64_t)c * ldw] = (c >= i) ? S[c][i] : 0.0;
+  switch (w) {
+    case 0: leaf_wave<0>(Z, ldz, Wi, ldw, bs, flag, S, cl, rpv); break;
+    case 1: leaf_wave<1>(Z, ldz, Wi, ldw, bs, flag, S, cl, rpv); break;
+    case 2: leaf_wave<2>(Z, ldz, Wi, ldw, bs, flag, S, cl, rpv); break;
+    default: leaf_wave<3>(Z, ldz, Wi, ldw, bs, flag, S, cl, rpv); break;
   }
 }
 
@@ -128,7 +165,7 @@ __global__ __launch_bounds__(LW) void chol_inv_leaf(double* Z, int64_t ldz, doub
   leaf_body(Z, ldz, Wi, ldw, bs, flag);
 }
 
-// The diagonal leaves of up to LEAF_CHUNK matrices of a batch, one wave each.
+// The diagonal leaves of up to LEAF_CHUNK matrices of a batch, one workgroup each.
 constexpr int LEAF_CHUNK = 32;
 struct LeafDesc { double* Z; int64_t ldz; double* Wi; int64_t ldw; int* flag; int bs; };
 struct LeafChunk { LeafDesc d[LEAF_CHUNK]; };

@@ -665,9 +665,9 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
     dgemm(g, s);
     Gemm h;
     h.M = r; h.N = r; h.K = ell; h.A = Q1; h.lda = ell; h.ta = true; h.B = Yb; h.ldb = ell;
-    h.C = H1; h.ldc = r;
+    h.C = H1; h.ldc = r; h.tiles = TILES_UPPER;   // symmetric: the upper tiles, then mirrored
     dgemm(h, s);
-    symmetrize(H1, r, r, s);
+    mirror_upper(H1, r, r, s);
     Gemm e;   // Yb <- H Q1 - Q1 H1
     e.M = ell; e.N = r; e.K = r; e.alpha = -1.0; e.beta = 1.0; e.A = Q1; e.lda = ell; e.B = H1; e.ldb = r;
     e.C = Yb; e.ldc = ell;
@@ -752,8 +752,9 @@ double restricted(const double* H, int64_t ell, const double* Q, int64_t r, doub
   dgemm(g, s);
   Gemm h;
   h.M = r; h.N = r; h.K = ell; h.A = Q; h.lda = ell; h.ta = true; h.B = Y; h.ldb = ell; h.C = Hr; h.ldc = r;
+  h.tiles = TILES_UPPER;   // symmetric: the upper tiles, then mirrored
   dgemm(h, s);
-  symmetrize(Hr, r, r, s);
+  mirror_upper(Hr, r, r, s);
   Gemm e;
   e.M = ell; e.N = r; e.K = r; e.alpha = -1.0; e.beta = 1.0; e.A = Q; e.lda = ell; e.B = Hr; e.ldb = r;
   e.C = Y; e.ldc = ell;
@@ -1181,9 +1182,9 @@ int eig_project(SolveState& S, std::vector<double>& theta, int64_t& ell, int64_t
   double* H = P.big;
   Gemm g2;
   g2.M = ell; g2.N = ell; g2.K = n; g2.A = Q2; g2.lda = n; g2.ta = true; g2.B = Y; g2.ldb = n;
-  g2.C = H; g2.ldc = ell;
+  g2.C = H; g2.ldc = ell; g2.tiles = TILES_UPPER;   // symmetric: the upper tiles, then mirrored
   dgemm(g2, s);
-  symmetrize(H, ell, ell, s);
+  mirror_upper(H, ell, ell, s);
   S.ev->mark(5, s);
   Wv = Wfree;
   int sweeps = -1;
