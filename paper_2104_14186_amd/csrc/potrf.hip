@@ -40,13 +40,16 @@ constexpr int NB = 64;
 //   k from the LDS buffer, forms L(i, k) = A(i, k) / sqrt(A(k, k)) and
 //   updates its trailing columns, A(i, j) -= L(i, k) L(j, k); the wave that
 //   owns column k + 1 updates it first and publishes it into the other
-//   buffer.  The pivot's reciprocal square root is the hardware estimate
-//   refined by two Newton steps.
+//   buffer (three buffers: the rest of step k's update is applied at step
+//   k + 1, while the next pivot's loads are in flight).  The pivot's
+//   reciprocal square root is the hardware estimate refined by two Newton
+//   steps.
 //   inverse M = L^{-1} (right-looking): lane = column j, wave w keeps the
 //   sums U(r, j) = sum_{k < r} L(r, k) M(k, j) for the rows r = 4q + w.
 //   Row k of M, (delta - U(k, :)) / L(k, k), is published by the wave that
-//   owns row k one step ahead and stored at once as column k of W^{-1} = M^T;
-//   every wave then adds L(r, k) M(k, :) to its rows past k + 1.
+//   owns row k one step ahead; every wave then adds L(r, k) M(k, :) to its
+//   rows past k + 1, and at the end stores its rows of M as columns of
+//   W^{-1} = M^T.
 // The cyclic layouts keep all four waves busy as the active part shrinks;
 // each wave runs its own copy of the steps, so every register index and
 // every skipped update is decided at compile time.
@@ -63,11 +66,22 @@ __device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, in
   if (W == 0) cl[0][i] = a[0];         // column 0
   __syncthreads();
   bool bad = false;
+  double pli2 = 0.0;                   // step k - 1's L(i, k-1) / L(k-1, k-1), for its deferred update
 #pragma clang loop unroll(full)
   for (int k = 0; k < NB; ++k) {
-    const double* buf = cl[k & 1];
+    const double* buf = cl[k % 3];
+    const double* pbuf = cl[(k + 2) % 3];        // column k - 1 as published
     double d = buf[k];
     const double ai = buf[i];
+    // step k - 1's update of this wave's columns past k (issued while the
+    // pivot's loads are in flight; column k came updated from its owner)
+    if (k > 0) {
+#pragma clang loop unroll(full)
+      for (int c = 0; c < LQ; ++c) {
+        const int j = 4 * c + W;
+        if (j > k) a[c] = __builtin_fma(-pli2, pbuf[j], a[c]);
+      }
+    }
     const bool nonpos = !(d > 0.0) || !isfinite(d);
     bad = bad || nonpos;
     d = nonpos ? 1.0 : d;
@@ -79,16 +93,11 @@ __device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, in
     const double li2 = lik * y;                   // times A(j, k) gives L(i, k) L(j, k)
     if ((k & 3) == W) a[k >> 2] = (i == k) ? p : ((i > k) ? lik : a[k >> 2]);   // keep L(:, k)
     if (W == 0 && i == 0) rpv[k] = y;
-    if (k + 1 < NB && ((k + 1) & 3) == W) {       // column k + 1 first, then publish it
+    if (k + 1 < NB && ((k + 1) & 3) == W) {       // column k + 1 now, then publish it
       a[(k + 1) >> 2] = __builtin_fma(-li2, buf[k + 1], a[(k + 1) >> 2]);
-      cl[(k + 1) & 1][i] = a[(k + 1) >> 2];
+      cl[(k + 1) % 3][i] = a[(k + 1) >> 2];
     }
-#pragma clang loop unroll(full)
-    for (int c = 0; c < LQ; ++c) {
-      const int j = 4 * c + W;
-      if (j <= k || j == k + 1) continue;         // finished, or published above
-      a[c] = __builtin_fma(-li2, buf[j], a[c]);
-    }
+    pli2 = li2;
     __syncthreads();
   }
   if (bad && W == 0 && i == 0) *flag = 1;
@@ -104,13 +113,13 @@ __device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, in
       if (c < bs && c >= i) Z[i + (int64_t)c * ldz] = S[c][i];
     }
   }
-  double acc[LQ];                      // U(4q + W, j)
+  double acc[LQ], mrow[LQ];            // U(4q + W, j); M(4q + W, j) once final
 #pragma clang loop unroll(full)
-  for (int q = 0; q < LQ; ++q) acc[q] = 0.0;
+  for (int q = 0; q < LQ; ++q) { acc[q] = 0.0; mrow[q] = 0.0; }
   if (W == 0) {                        // row 0 of M
     const double m0 = ((i == 0) ? 1.0 : 0.0) * rpv[0];
     cl[0][i] = m0;
-    if (i < bs) Wi[i] = m0;
+    mrow[0] = m0;
   }
   __syncthreads();
 #pragma clang loop unroll(full)
@@ -121,7 +130,7 @@ __device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, in
       acc[q1] = __builtin_fma(S[k + 1][k], mk, acc[q1]);
       const double m1 = (((i == k + 1) ? 1.0 : 0.0) - acc[q1]) * rpv[k + 1];
       cl[(k + 1) & 1][i] = m1;
-      if (i < bs && k + 1 < bs) Wi[i + (int64_t)(k + 1) * ldw] = m1;   // W^{-1}(j, k + 1) = M(k + 1, j)
+      mrow[q1] = m1;
     }
 #pragma clang loop unroll(full)
     for (int q = 0; q < LQ; ++q) {
@@ -131,11 +140,18 @@ __device__ __forceinline__ void leaf_wave(double* Z, int64_t ldz, double* Wi, in
     }
     __syncthreads();
   }
+  if (i < bs) {                        // W^{-1}(j, r) = M(r, j): this wave's rows of M as columns
+#pragma clang loop unroll(full)
+    for (int q = 0; q < LQ; ++q) {
+      const int r = 4 * q + W;
+      if (r < bs) Wi[i + (int64_t)r * ldw] = mrow[q];
+    }
+  }
 }
 
 __device__ __forceinline__ void leaf_body(double* Z, int64_t ldz, double* Wi, int64_t ldw, int bs, int* flag) {
   __shared__ double S[NB][NB + 1];     // the input (S[i][j] = A(i, j), j <= i), then L
-  __shared__ double cl[2][NB];         // column k of the factorisation / row k of M
+  __shared__ double cl[3][NB];         // column k of the factorisation / row k of M
   __shared__ double rpv[NB];           // 1 / L(k, k)
   const int w = threadIdx.x >> 6, i = threadIdx.x & 63;
   {   // coalesced load of Z's upper triangle, all loads in flight: wave w
