@@ -465,7 +465,11 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
  * b = ceil(log2 h), when set), "qr.overlap" (1, default: with the
  * reconstruction path, the trailing update beyond the next panel runs on a
  * helper stream while the next panel is factored; 0: all on the call's
- * stream; the two agree to rounding), "gemm.shallow_k" (GEMMs with k at most this
+ * stream; the two agree to rounding), "rr.split2_min" (0, default: off;
+ * from this many rows the wanted block of the Rayleigh-Ritz split is split
+ * once more at the median of its spectrum, Jacobi on both halves, when at
+ * least "rr.split2_pct" percent of it (12) lies in tight clusters by the
+ * estimator's quadrature), "gemm.shallow_k" (GEMMs with k at most this
  * run 64x64 tiles; default 128), "batch.lanes.mixed" (lanes of a batch in
  * mixed precision; default batch.lanes).  Unset keys keep
  * their defaults.  Values apply to calls made after they are set.

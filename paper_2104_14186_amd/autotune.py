@@ -224,6 +224,37 @@ def tune_split(q, torch, log, quick=False):
     return best, rows
 
 
+def tune_split2(q, torch, log, quick=False):
+    """One more split of the wanted block (when it is clustered) against
+    Jacobi on all of it, by the wanted block's rows r; the threshold is the
+    smallest r from which the second split wins."""
+    from synthetic import eig_clustered
+    rows = []
+    for n in ((12288,) if quick else (10240, 12288, 16384)):
+        A, _ = eig_clustered(n, 3300 + n, device=torch.device("cuda"))
+        t, r = {}, 0
+        for name, thr in (("split2", 64), ("jacobi", 0)):
+            q.tune_set("rr.split2_min", thr)
+            q.eig(A, fraction=0.2, return_info=True)
+            torch.cuda.synchronize()
+            _, _, info = q.eig(A, fraction=0.2, return_info=True)
+            t[name] = _phase(info, "small_solve")
+            r = info["rr_split"]
+        rows.append(dict(n=n, r=r, ms_split2=t["split2"], ms_jacobi=t["jacobi"]))
+        log(f"eig {n} 20% (wanted block {r}): small solve second split {t['split2']:.1f} ms, "
+            f"Jacobi {t['jacobi']:.1f} ms")
+        del A
+        torch.cuda.empty_cache()
+    rows.sort(key=lambda x: x["r"])
+    best = 0
+    for x in reversed(rows):
+        if x["r"] > 0 and x["ms_split2"] < x["ms_jacobi"]:
+            best = x["r"]
+        else:
+            break
+    return best, rows
+
+
 def tune_lanes(q, torch, log, count=24, seed=7, precision=None):
     from synthetic import eig_uniform, svd_geometric
     import numpy as np
@@ -253,12 +284,23 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--quick", action="store_true", help="fewer sizes per sweep")
+    ap.add_argument("--only", choices=["split2"], default=None,
+                    help="run one sweep on top of the committed table and update it")
     args = ap.parse_args()
     import torch
     import paper_2104_14186_amd as q
     q.lib()
-    q.lib().qdwhp_tune_clear()
     log = lambda s: print("[autotune] " + s, flush=True)
+    if args.only == "split2":
+        path = args.out or q.TUNING_PATH
+        table = json.load(open(q.TUNING_PATH))
+        s2, table["rr_split2"] = tune_split2(q, torch, log, args.quick)
+        table["params"]["rr.split2_min"] = s2
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1)
+        log(f"wrote {path}: rr.split2_min = {s2}")
+        return
+    q.lib().qdwhp_tune_clear()
     params, meas = {}, {}
     small, meas["gemm"] = tune_gemm(q, torch, log)
     params["gemm.small_tiles"] = small
@@ -283,6 +325,9 @@ def main():
     spl, meas["rr_split"] = tune_split(q, torch, log, args.quick)
     params["rr.split_min"] = spl
     q.tune_set("rr.split_min", spl)
+    s2, meas["rr_split2"] = tune_split2(q, torch, log, args.quick)
+    params["rr.split2_min"] = s2
+    q.tune_set("rr.split2_min", s2)
     lanes, meas["lanes"] = tune_lanes(q, torch, log)
     lanes_mx, meas["lanes_mixed"] = tune_lanes(q, torch, log, precision=q.MIXED_FP32)
     params.update({"batch.lanes": lanes, "batch.lanes.mixed": lanes_mx, "serve.lanes": min(lanes, 3)})

@@ -545,6 +545,28 @@ int polar_svd(double* R, int64_t ell, double alpha, double* vals, double*& V, do
   return sweeps;
 }
 
+struct Bump {
+  double* p = nullptr;
+  int64_t left = 0;
+  double* take(int64_t n) {
+    n = (n + 31) / 32 * 32;      // 256-byte steps
+    if (n > left) throw WorkspaceError{};
+    double* r = p;
+    p += n;
+    left -= n;
+    return r;
+  }
+};
+
+constexpr int kDcSteps = 32;     // Lanczos steps of the shift estimate
+constexpr int kDcVectors = 4;
+struct DcStats { int splits = 0, leaves = 0, fallbacks = 0, depth = 0; };
+
+// QDWH-based divide and conquer of a symmetric block (defined below).
+int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, const qdwhp_opts& o, int* flag,
+           double* dbuf, int depth, DcStats* st, hipStream_t s, int64_t leaf);
+int64_t dc_node_doubles(int64_t ell);
+
 // Exact spectral split of the Rayleigh-Ritz matrix H (ell x ell, the
 // Sec. 3.2 mechanism of QDWH-EIG): sigma is placed by a Lanczos estimate so
 // that about k + margin eigenvalues lie above it; the polar factor of
@@ -590,6 +612,19 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
   const bool have_top = top && !top->nodes.empty();
   int64_t r = 0;
   double sigma = 0.0, alpha = 0.0, hnorm = 0.0;
+  // eigenvalues above sigma in tight clusters: quadrature nodes that have
+  // converged (residual bound within 1e-6 of the spread) and stand for at
+  // least 8 eigenvalues each
+  double clustered = 0.0;
+  auto cluster_mass = [&](const LanczosResult& q, int64_t dim, double lmx, double lmn) {
+    const double spread = std::max(lmx - lmn, 1e-300), scale = (double)dim / q.nv;
+    double c = 0.0;
+    for (size_t i = 0; i < q.nodes.size(); ++i) {
+      const double cnt = scale * q.weights[i];
+      if (q.nodes[i] > sigma && q.resid[i] <= 1e-6 * spread && cnt >= 8.0) c += cnt;
+    }
+    return c;
+  };
   int hf = 0;
   auto failed = [&]() {
     QDWHP_HIP(hipMemsetAsync(P.flags, 0, sizeof(int), s));
@@ -599,6 +634,7 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
     double lmax = top_lmax, lmin = top_lmin;
     if (attempt == 0) {
       if (!cut_below(top->nodes, top->weights, n, top->nv, lmax, lmin, k + margin, &sigma)) continue;
+      clustered = cluster_mass(*top, n, lmax, lmin);
     } else {
       LanczosOp op;
       op.rows_tmp = 1;
@@ -614,6 +650,7 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
         lmin = std::min(lmin, lz.nodes[i] - lz.resid[i]);
       }
       if (!cut_below(lz.nodes, lz.weights, ell, nv, lmax, lmin, k + margin, &sigma)) return 0;
+      clustered = cluster_mass(lz, ell, lmax, lmin);
     }
     alpha = 1.05 * std::max(lmax - sigma, sigma - lmin);
     hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
@@ -686,9 +723,26 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
     for (double v : cn) worst = std::max(worst, std::isfinite(v) ? v : 1e300);
     if (!(std::sqrt(worst) <= 5e-14 * hnorm)) return 0;
   }
-  // ---- Jacobi on the wanted block; eigenvectors Q1 W1
+  // ---- the wanted block: Jacobi, or one more split at the median of its
+  // spectrum (the same QDWH split, Sec. 3.2) with Jacobi on the two halves;
+  // eigenvectors Q1 W1.  Jacobi needs many more sweeps when a good part of
+  // the block lies in tight clusters (the rotations inside a cluster only
+  // settle once everything else has converged); halving the rows of both
+  // Jacobi problems then more than pays for the split.  Taken from
+  // "rr.split2_min" rows when at least an eighth of the block is clustered
+  // (cluster_mass above; "rr.split2_pct" = 0 drops that condition).
   double* W1 = ybuf;             // r x r (the iterates are no longer needed)
-  *sweeps = syev(H1, r, r, vals, W1, r, jscr, s);
+  const int64_t split2 = qdwhp_tune_get("rr.split2_min", 0);
+  const int64_t pct2 = qdwhp_tune_get("rr.split2_pct", 12);
+  if (split2 > 0 && r >= split2 && 100.0 * clustered >= (double)pct2 * (double)r &&
+      dc_node_doubles(r) + r * r + syev_scratch_doubles(r) + 4096 <= zbuf_doubles) {
+    DcStats st;
+    Bump mem{Wv, zbuf_doubles};  // free until the final product
+    // one level: the recursion's depth limit (24) makes both halves Jacobi leaves
+    *sweeps = dc_eig(H1, r, vals, W1, mem, o, P.flags, P.diag, 23, &st, s, r - 1);
+  } else {
+    *sweeps = syev(H1, r, r, vals, W1, r, jscr, s);
+  }
   if (*sweeps < 0) return 0;
   fill(vals + r, ell - r, 1, ell - r, -1e300, -1e300, s);
   Gemm v;
@@ -704,21 +758,6 @@ int64_t rr_split(const double* H, int64_t ell, int64_t k, int64_t n, const Lancz
 // conquer (the QDWH-EIG of Sec. 3.2, applied recursively).
 namespace {
 
-struct Bump {
-  double* p = nullptr;
-  int64_t left = 0;
-  double* take(int64_t n) {
-    n = (n + 31) / 32 * 32;      // 256-byte steps
-    if (n > left) throw WorkspaceError{};
-    double* r = p;
-    p += n;
-    left -= n;
-    return r;
-  }
-};
-
-constexpr int kDcSteps = 32;     // Lanczos steps of the shift estimate
-constexpr int kDcVectors = 4;
 
 int64_t dc_node_doubles(int64_t ell) {
   const int64_t e2 = ell * ell;
@@ -772,15 +811,13 @@ double restricted(const double* H, int64_t ell, const double* Q, int64_t r, doub
   return std::sqrt(worst);
 }
 
-struct DcStats { int splits = 0, leaves = 0, fallbacks = 0, depth = 0; };
 
 // H (ell x ell, ld ell) symmetric, read only; vals[ell] descending, W (ell x
 // ell, ld ell) eigenvectors.  Returns the largest Jacobi sweep count of its
 // leaves, or -1 if a leaf did not converge.
 int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, const qdwhp_opts& o, int* flag,
-           double* dbuf, int depth, DcStats* st, hipStream_t s) {
+           double* dbuf, int depth, DcStats* st, hipStream_t s, int64_t leaf) {
   st->depth = std::max(st->depth, depth);
-  const int64_t leaf = std::max<int64_t>(64, qdwhp_tune_get("dc.leaf", 512));
   const int64_t e2 = ell * ell;
   auto jacobi = [&]() {
     ++st->leaves;
@@ -880,9 +917,9 @@ int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, cons
   rest.take(2 * e2);                        // Wb (Q1, Q2)
   double* W1 = rest.take(r * r);
   double* W2 = rest.take(r2 * r2);
-  const int s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s);
+  const int s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s, leaf);
   if (s1 < 0) return -1;
-  const int s2 = dc_eig(H2, r2, vals + r, W2, rest, o, flag, dbuf, depth + 1, st, s);
+  const int s2 = dc_eig(H2, r2, vals + r, W2, rest, o, flag, dbuf, depth + 1, st, s, leaf);
   if (s2 < 0) return -1;
   // eigenvectors [Q1 W1, Q2 W2]: the eigenvalues above sigma come first
   Gemm v1;
@@ -926,7 +963,8 @@ extern "C" int qdwhp_syev_dc(const double* H, int64_t n, int64_t ldh, double* w,
     QDWHP_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     copy(H, ldh, Hc, n, n, n, s);
     DcStats st;
-    const int sw = dc_eig(Hc, n, w, Wc, mem, o, flag, dbuf, 0, &st, s);
+    const int sw = dc_eig(Hc, n, w, Wc, mem, o, flag, dbuf, 0, &st, s,
+                          std::max<int64_t>(64, qdwhp_tune_get("dc.leaf", 512)));
     if (levels) *levels = st.depth;
     if (sw < 0) return QDWHP_ERR_NOCONV;
     copy(Wc, n, W, ldw, n, n, s);

@@ -92,6 +92,41 @@ def test_eig_rr_split_vs_oracle(n, f, seed, which, kind, replay):
         assert np.max(np.abs(V - r["V"])) < 1e-9
 
 
+@pytest.mark.parametrize("n,f,seed,kind", [(800, 0.2, 25, "uniform"), (900, 0.25, 26, "clustered")])
+def test_eig_rr_second_split_vs_oracle(n, f, seed, kind):
+    """The wanted block of the Rayleigh-Ritz split split once more at the
+    median of its spectrum (the same QDWH split, Jacobi on both halves),
+    forced at small sizes, against the oracle and the planted spectrum."""
+    torch, q = _gpu()
+    A, lam = (eig_uniform if kind == "uniform" else eig_clustered)(n, seed)
+    print(f"eig rr second split n={n} f={f} {kind}", flush=True)
+    r = oracle.eig_partial(A, fraction=f, tol=TOL_LIB)
+    opts = q.default_opts(tol=TOL_LIB)
+    keys = {"rr.split_min": (64, 3000), "rr.split_pct": (100, 85), "rr.split2_min": (64, 0),
+            "rr.split2_pct": (0, 12)}
+    old = {key: q.tune_get(key, d) for key, (_, d) in keys.items()}
+    try:
+        for key, (v, _) in keys.items():
+            q.tune_set(key, v)
+        w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=opts, return_info=True)
+        torch.cuda.synchronize()
+    finally:
+        for key, v in old.items():
+            q.tune_set(key, v)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    k = r["k"]
+    print(f"  k={k} ell={info['ell']} split={info['rr_split']} sweeps={info['jacobi_sweeps']}", flush=True)
+    assert k <= info["rr_split"] < info["ell"]
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+    assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["residual"] < 1e-13, met
+    assert met["orth"] < 1e-12, met
+    if kind == "uniform":
+        assert np.max(np.abs(V - r["V"])) < 1e-9
+
+
 @pytest.mark.timeout(900)
 def test_eig_default_tuning_at_10240_vs_oracle():
     """Default (tuned) settings, nothing forced: n = 10240, top 20% of the
