@@ -9,8 +9,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <limits>
 #include <memory>
+#include <thread>
 #include <vector>
 
 #include "qdwhp.h"
@@ -917,10 +919,49 @@ int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, cons
   rest.take(2 * e2);                        // Wb (Q1, Q2)
   double* W1 = rest.take(r * r);
   double* W2 = rest.take(r2 * r2);
-  const int s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s, leaf);
-  if (s1 < 0) return -1;
-  const int s2 = dc_eig(H2, r2, vals + r, W2, rest, o, flag, dbuf, depth + 1, st, s, leaf);
-  if (s2 < 0) return -1;
+  int s1 = -1, s2 = -1;
+  const bool leaf1 = r <= leaf || depth + 1 >= 24, leaf2 = r2 <= leaf || depth + 1 >= 24;
+  if (leaf1 && leaf2 && !no_alloc_mode() && qdwhp_tune_get("dc.concurrent", 1) != 0) {
+    // Both halves are Jacobi leaves, independent of each other, and each is
+    // bound by the latency of its rounds: the second runs from a host thread
+    // of its own on a helper stream (own scratch), beside the first.
+    Bump rest2 = rest;
+    double* scr1 = rest.take(syev_scratch_doubles(r));
+    rest2.take(syev_scratch_doubles(r));
+    double* scr2 = rest2.take(syev_scratch_doubles(r2));
+    int dev = 0;
+    QDWHP_HIP(hipGetDevice(&dev));
+    AuxLease aux(dev);
+    QDWHP_HIP(hipEventRecord(aux->ready[0], s));          // H2 is ready on s
+    QDWHP_HIP(hipStreamWaitEvent(aux->s, aux->ready[0], 0));
+    std::exception_ptr err2;
+    std::thread th([&] {
+      try {
+        QDWHP_HIP(hipSetDevice(dev));
+        s2 = syev(H2, r2, r2, vals + r, W2, r2, scr2, aux->s);
+      } catch (...) {
+        err2 = std::current_exception();
+      }
+    });
+    std::exception_ptr err1;
+    try {
+      s1 = syev(H1, r, r, vals, W1, r, scr1, s);
+    } catch (...) {
+      err1 = std::current_exception();
+    }
+    th.join();
+    if (err1) std::rethrow_exception(err1);
+    if (err2) std::rethrow_exception(err2);
+    QDWHP_HIP(hipEventRecord(aux->done[0], aux->s));      // s continues after both
+    QDWHP_HIP(hipStreamWaitEvent(s, aux->done[0], 0));
+    st->leaves += 2;
+    if (s1 < 0 || s2 < 0) return -1;
+  } else {
+    s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s, leaf);
+    if (s1 < 0) return -1;
+    s2 = dc_eig(H2, r2, vals + r, W2, rest, o, flag, dbuf, depth + 1, st, s, leaf);
+    if (s2 < 0) return -1;
+  }
   // eigenvectors [Q1 W1, Q2 W2]: the eigenvalues above sigma come first
   Gemm v1;
   v1.M = ell; v1.N = r; v1.K = r; v1.A = Q1; v1.lda = ell; v1.B = W1; v1.ldb = r; v1.C = W; v1.ldc = ell;
