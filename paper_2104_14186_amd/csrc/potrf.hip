@@ -13,7 +13,8 @@
 //      [Z11 Z12; . Z22] gives W11 = chol(Z11), W12 = W11^{-T} Z12,
 //      Z22 <- Z22 - W12^T W12, W22 = chol(Z22) and
 //      W^{-1}_{12} = -W11^{-1} W12 W22^{-1}; 64x64 leaves are factored and
-//      inverted by one workgroup of four waves (below);
+//      inverted by one workgroup of four waves, and a node of at most 128
+//      rows runs its products in two one-workgroup kernels (below);
 //   2. Z^{-1} = W^{-1} W^{-T}, upper tiles only, K starting at the tile column;
 //   3. mirror the upper triangle.
 #include <algorithm>
@@ -202,6 +203,117 @@ __global__ void copy_batched_kernel(CopyChunk c) {
   }
 }
 
+// The recursion's bottom node (m <= 2 NB rows: n1 = NB, n2 = m - NB <= NB)
+// in two one-workgroup kernels instead of four GEMMs and a copy:
+//   node_pre  (after the first leaf):  W12 = W11^{-T} Z12 (into Z12) and
+//             Z22 <- Z22 - W12^T W12 (upper triangle);
+//   node_post (after the second leaf): W^{-1}_{12} = -W11^{-1} (W12 W22^{-1}).
+// The blocks sit in LDS, zero outside their triangles and past n2, and each
+// 64 x 64 product runs on the FP64 matrix cores (wave w owns output column
+// block 16 w, four 16 x 16 tiles, 16 k steps of 4).  The batched recursion
+// runs the same kernels over its members, so both give the same bits.
+struct NodeDesc { double* Z; int64_t ldz; double* Wi; int64_t ldw; int n2; };
+struct NodeChunk { NodeDesc d[LEAF_CHUNK]; };
+constexpr int NL = NB + 1;   // LDS row pitch
+
+// All of a block's loads are issued before the first LDS store (one memory
+// latency instead of one per pass).
+__device__ __forceinline__ void load_block(double (*D)[NL], const double* src, int64_t ld, int rows, int cols,
+                                           bool upper) {
+  constexpr int PER = NB * NB / LW;
+  double v[PER];
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * LW, r = e % NB, c = e / NB;
+    v[p] = (r < rows && c < cols && (!upper || r <= c)) ? src[r + (int64_t)c * ld] : 0.0;
+  }
+#pragma unroll
+  for (int p = 0; p < PER; ++p) {
+    const int e = threadIdx.x + p * LW;
+    D[e % NB][e / NB] = v[p];
+  }
+}
+
+// acc[b] = tile (16 b, 16 w) of op(A) B for 64 x 64 LDS blocks (op = transpose
+// when ta); element r of lane l is row 16 b + l / 16 + 4 r, column
+// 16 w + l % 16 (the v_mfma_f64_16x16x4f64 result layout).
+__device__ __forceinline__ void mm64(const double (*A)[NL], bool ta, const double (*B)[NL], v4d acc[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4, bj = 16 * w;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) acc[b] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    const int k = k0 + lk;
+    const double bv = B[k][bj + li];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const double av = ta ? A[k][16 * b + li] : A[16 * b + li][k];
+      acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[b], 0, 0, 0);
+    }
+  }
+}
+
+__global__ __launch_bounds__(LW) void node_pre_kernel(NodeChunk ch) {
+  __shared__ double A[NB][NL];   // W11^{-1} (upper)
+  __shared__ double B[NB][NL];   // Z12, then W12
+  const NodeDesc d = ch.d[blockIdx.x];
+  const int n2 = d.n2, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = 16 * w + (lane & 15), rq = lane >> 4;
+  load_block(A, d.Wi, d.ldw, NB, NB, true);
+  load_block(B, d.Z + (int64_t)NB * d.ldz, d.ldz, NB, n2, false);
+  __syncthreads();
+  v4d acc[4];
+  mm64(A, true, B, acc);                    // W12 = W11^{-T} Z12
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * b + rq + 4 * r;
+      B[row][col] = acc[b][r];
+      if (col < n2) d.Z[row + (int64_t)(NB + col) * d.ldz] = acc[b][r];
+    }
+  __syncthreads();
+  mm64(B, true, B, acc);                    // W12^T W12
+  double* Z22 = d.Z + NB + (int64_t)NB * d.ldz;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * b + rq + 4 * r;
+      if (row <= col && col < n2) Z22[row + (int64_t)col * d.ldz] -= acc[b][r];
+    }
+}
+
+__global__ __launch_bounds__(LW) void node_post_kernel(NodeChunk ch) {
+  __shared__ double A[NB][NL];   // W11^{-1} (upper)
+  __shared__ double B[NB][NL];   // W12, then W12 W22^{-1}
+  __shared__ double C[NB][NL];   // W22^{-1} (upper)
+  const NodeDesc d = ch.d[blockIdx.x];
+  const int n2 = d.n2, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int col = 16 * w + (lane & 15), rq = lane >> 4;
+  load_block(A, d.Wi, d.ldw, NB, NB, true);
+  load_block(B, d.Z + (int64_t)NB * d.ldz, d.ldz, NB, n2, false);
+  load_block(C, d.Wi + NB + (int64_t)NB * d.ldw, d.ldw, n2, n2, true);
+  __syncthreads();
+  v4d acc[4];
+  mm64(B, false, C, acc);                   // X = W12 W22^{-1}
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B[16 * b + rq + 4 * r][col] = acc[b][r];
+  __syncthreads();
+  mm64(A, false, B, acc);                   // W11^{-1} X
+  double* W12i = d.Wi + (int64_t)NB * d.ldw;
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (col < n2) W12i[(16 * b + rq + 4 * r) + (int64_t)col * d.ldw] = -acc[b][r];
+}
+
 struct Rec {
   double* Z; int64_t ldz; double* Wi; int64_t ldw; double* T; int* flag; hipStream_t s;
 
@@ -210,6 +322,17 @@ struct Rec {
     double* Wo = Wi + o + o * ldw;
     if (m <= NB) {
       chol_inv_leaf<<<1, LW, 0, s>>>(Zo, ldz, Wo, ldw, (int)m, flag);
+      QDWHP_LAUNCH_CHECK();
+      return;
+    }
+    if (m <= 2 * NB) {           // bottom node: leaf, pre, leaf, post
+      NodeChunk nc;
+      nc.d[0] = NodeDesc{Zo, ldz, Wo, ldw, (int)(m - NB)};
+      run(o, NB);
+      node_pre_kernel<<<1, LW, 0, s>>>(nc);
+      QDWHP_LAUNCH_CHECK();
+      run(o + NB, m - NB);
+      node_post_kernel<<<1, LW, 0, s>>>(nc);
       QDWHP_LAUNCH_CHECK();
       return;
     }
@@ -254,7 +377,7 @@ struct Rec {
 // rows: a lopsided split (n2 much smaller than n1, e.g. m = 2 NB + 1) needs
 // less at the top than its first half needs one level down.
 static int64_t rec_t_doubles(int64_t m) {
-  if (m <= NB) return 0;
+  if (m <= 2 * NB) return 0;     // leaves and fused bottom nodes
   const int64_t n1 = NB * cdiv(cdiv(m, NB), 2), n2 = m - n1;
   return std::max(n1 * n2, std::max(rec_t_doubles(n1), rec_t_doubles(n2)));
 }
@@ -293,6 +416,26 @@ struct GroupRec {
         chol_inv_leaf_batched<<<cnt, LW, 0, s>>>(lc);
         QDWHP_LAUNCH_CHECK();
       }
+      return;
+    }
+    if (m <= 2 * NB) {           // bottom node: the standalone recursion's kernels, per member
+      auto node = [&](bool pre) {
+        for (int c0 = 0; c0 < count; c0 += LEAF_CHUNK) {
+          NodeChunk nc;
+          const int cnt = std::min(LEAF_CHUNK, count - c0);
+          for (int q = 0; q < cnt; ++q) {
+            const CholItem& x = it[c0 + q];
+            nc.d[q] = NodeDesc{x.Z + o + o * x.ldz, x.ldz, x.work + o + o * n, n, (int)(m - NB)};
+          }
+          if (pre) node_pre_kernel<<<cnt, LW, 0, s>>>(nc);
+          else node_post_kernel<<<cnt, LW, 0, s>>>(nc);
+          QDWHP_LAUNCH_CHECK();
+        }
+      };
+      run(o, NB);
+      node(true);
+      run(o + NB, m - NB);
+      node(false);
       return;
     }
     const int64_t nblk = cdiv(m, NB);
