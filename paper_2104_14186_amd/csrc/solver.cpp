@@ -890,17 +890,54 @@ int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, cons
   const int64_t r2 = ell - r;
   double* Q1 = Wb;                        // ell x r
   double* Q2 = Wb + ell * r;              // ell x r2
-  double* scratchY = Qb;                  // ell x max(r, r2)
-  double* Gb = Qb + e2;                   // ell x max(r, r2)
-  double* gram = X;                       // r x r (X no longer needed)
-  double* spd2 = spd;
-  projector_basis(C, ell, r, o.seed + 21 + (uint64_t)depth * 2, Q1, Gb, scratchY, gram, spd2, flag, s);
-  projector_basis(Cc, ell, r2, o.seed + 22 + (uint64_t)depth * 2, Q2, Gb, scratchY, gram, spd2, flag, s);
   double* H1 = C;                          // r x r (C no longer needed)
   double* H2 = Cc;                         // r2 x r2
   const double hnorm = std::max(std::fabs(lmax), std::fabs(lmin));
-  const double e1 = restricted(H, ell, Q1, r, H1, scratchY, gram, dbuf, s);
-  const double e2n = restricted(H, ell, Q2, r2, H2, scratchY, gram, dbuf, s);
+  // Each side: its basis, then its block and check (each reads only its own
+  // projector and writes its block over it).  The two sides are independent
+  // and latency bound, so unless it is off ("dc.concurrent" = 0) the second
+  // runs from its own host thread on a helper stream, with scratch of its
+  // own: the Y / G halves of Qb, its Gram after the first in X, its
+  // Cholesky-inversion space after the first's, its diagonal after the
+  // first's in dbuf.  The same kernels on the same data either way.
+  double e1 = 0.0, e2n = 0.0;
+  auto side = [&](const double* Cp, int64_t rr, uint64_t key, double* Qs, double* Hs, double* Y, double* G,
+                  double* gr, double* sp, double* db, hipStream_t st) {
+    projector_basis(Cp, ell, rr, key, Qs, G, Y, gr, sp, flag, st);
+    return restricted(H, ell, Qs, rr, Hs, Y, gr, db, st);
+  };
+  const uint64_t key1 = o.seed + 21 + (uint64_t)depth * 2, key2 = o.seed + 22 + (uint64_t)depth * 2;
+  if (!no_alloc_mode() && qdwhp_tune_get("dc.concurrent", 1) != 0) {
+    int dev = 0;
+    QDWHP_HIP(hipGetDevice(&dev));
+    AuxLease aux(dev);
+    QDWHP_HIP(hipEventRecord(aux->ready[0], s));          // both projectors are ready on s
+    QDWHP_HIP(hipStreamWaitEvent(aux->s, aux->ready[0], 0));
+    std::exception_ptr err2;
+    std::thread th([&] {
+      try {
+        QDWHP_HIP(hipSetDevice(dev));
+        e2n = side(Cc, r2, key2, Q2, H2, Qb + 2 * ell * r, Qb + 2 * ell * r + ell * r2, X + r * r,
+                   spd + spd_inverse_doubles(r), dbuf + r, aux->s);
+      } catch (...) {
+        err2 = std::current_exception();
+      }
+    });
+    std::exception_ptr err1;
+    try {
+      e1 = side(C, r, key1, Q1, H1, Qb, Qb + ell * r, X, spd, dbuf, s);
+    } catch (...) {
+      err1 = std::current_exception();
+    }
+    th.join();
+    if (err1) std::rethrow_exception(err1);
+    if (err2) std::rethrow_exception(err2);
+    QDWHP_HIP(hipEventRecord(aux->done[0], aux->s));
+    QDWHP_HIP(hipStreamWaitEvent(s, aux->done[0], 0));
+  } else {
+    e1 = side(C, r, key1, Q1, H1, Qb, Qb + e2, X, spd, dbuf, s);
+    e2n = side(Cc, r2, key2, Q2, H2, Qb, Qb + e2, X, spd, dbuf, s);
+  }
   QDWHP_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
   QDWHP_HIP(hipStreamSynchronize(s));
   if (hf || !(e1 <= 5e-14 * hnorm) || !(e2n <= 5e-14 * hnorm)) {
