@@ -992,6 +992,7 @@ int dc_eig(const double* H, int64_t ell, double* vals, double* W, Bump mem, cons
     QDWHP_HIP(hipEventRecord(aux->done[0], aux->s));      // s continues after both
     QDWHP_HIP(hipStreamWaitEvent(s, aux->done[0], 0));
     st->leaves += 2;
+    st->depth = std::max(st->depth, depth + 1);   // as the leaves' own calls record it
     if (s1 < 0 || s2 < 0) return -1;
   } else {
     s1 = dc_eig(H1, r, vals, W1, rest, o, flag, dbuf, depth + 1, st, s, leaf);

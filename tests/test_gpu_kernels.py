@@ -280,6 +280,36 @@ def test_dgemm_tile_size_does_not_change_results(m, n, k, ta, tb, upper):
     assert bool((out[0] == out[1]).all())
 
 
+@pytest.mark.parametrize("n,leaf", [(700, 256), (1100, 300)])
+def test_syev_dc_side_by_side_bitwise(n, leaf):
+    """The two sides of a split (bases, blocks, leaf Jacobi solves) run side
+    by side on two streams from two host threads, or one after the other
+    ("dc.concurrent" = 0): the same kernels on the same data, so the
+    results are bitwise equal."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import eig_uniform
+    A, lam = eig_uniform(n, 950 + n)
+    print(f"syev_dc side by side n={n} leaf={leaf}", flush=True)
+    old = (q.tune_get("dc.leaf", 512), q.tune_get("dc.concurrent", 1))
+    out = {}
+    try:
+        q.tune_set("dc.leaf", leaf)
+        for cc in (0, 1):
+            q.tune_set("dc.concurrent", cc)
+            w, W, depth = q.syev_dc(torch.from_numpy(A).cuda())
+            torch.cuda.synchronize()
+            out[cc] = (w.cpu().numpy(), W.cpu().numpy(), depth)
+    finally:
+        q.tune_set("dc.leaf", old[0])
+        q.tune_set("dc.concurrent", old[1])
+    assert out[0][2] >= 1 and out[0][2] == out[1][2]
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    ex = np.sort(lam)[::-1]
+    assert np.max(np.abs(out[1][0] - ex)) / np.abs(lam).max() < 1e-13
+
+
 @pytest.mark.parametrize("n,spec,leaf", [(300, "uniform", 64), (1000, "uniform", 128), (1500, "clustered", 256),
                                          (700, "median_cluster", 128), (900, "uniform", 4096)])
 def test_syev_dc(n, spec, leaf):
