@@ -184,6 +184,16 @@ size_t qdwhp_eig_workspace(int64_t n, double fraction, const qdwhp_opts* opts);
 size_t qdwhp_svd_workspace(int64_t m, int64_t n, int64_t k, const qdwhp_opts* opts);
 
 /*
+ * The number of eigenpairs that qdwhp_eig, qdwhp_eig_noalloc and qdwhp_heig
+ * return for this n and fraction: k = floor(fraction*n + 1/2) clamped to
+ * 1 <= k <= n (Algorithms 1 and 2 take k as given; a fraction of the order
+ * is how the experiments of Sec. 7 state it).  Host only; 0 when n < 1 or
+ * fraction is outside (0, 1], which those calls reject.  Callers size w and
+ * V from it.
+ */
+int64_t qdwhp_eig_count(int64_t n, double fraction);
+
+/*
  * QDWHpartial-EIG (Algorithm 1): the k = floor(fraction*n + 1/2) (1 <= k <= n)
  * largest (which = QDWHP_LARGEST) or smallest (QDWHP_SMALLEST) eigenpairs of
  * the symmetric n x n matrix A.  Only the full matrix is read (both triangles);

@@ -87,6 +87,7 @@ _SIGS = {
     "qdwhp_heig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
                         ctypes.POINTER(Opts), _P, ctypes.POINTER(Info)]),
     "qdwhp_eig_workspace": (_SZ, [_I64, _D, ctypes.POINTER(Opts)]),
+    "qdwhp_eig_count": (_I64, [_I64, _D]),
     "qdwhp_svd_workspace": (_SZ, [_I64, _I64, _I64, ctypes.POINTER(Opts)]),
     "qdwhp_eig": (_I, [_P, _I64, _I64, _D, _I, _P, _P, _I64, _P, _SZ,
                        ctypes.POINTER(Opts), _P, ctypes.POINTER(Info)]),
@@ -231,8 +232,29 @@ def _info_dict(info):
     return info.as_dict()
 
 
+def _count(n, fraction):
+    """k for this n and fraction, as the library computes it."""
+    kk = int(lib().qdwhp_eig_count(n, float(fraction)))
+    if kk < 1:
+        raise ValueError(f"fraction {fraction} outside (0, 1] or n = {n} < 1")
+    return kk
+
+
+def _sym_storage(A):
+    """Column-major storage of the symmetric A.  A dense tensor in either
+    order holds the same matrix (row-major storage of A is column-major
+    storage of A^T = A), so it is passed as it is; other strides are
+    copied."""
+    if A.is_contiguous() or A.t().is_contiguous():
+        return A
+    return A.t().contiguous()
+
+
 def eig(A, fraction=None, k=None, which="largest", opts=None, return_info=False, stream=None):
     """Wanted eigenpairs of the symmetric n x n float64 CUDA tensor A (QDWHpartial-EIG).
+
+    A dense A (either memory order) is read in place, without a copy; A must
+    be symmetric, as the method assumes (its two triangles are both read).
 
     Returns (w, V) with w (k,) most wanted first and V (n, k); with
     return_info=True also the solver report as a dict.
@@ -242,9 +264,9 @@ def eig(A, fraction=None, k=None, which="largest", opts=None, return_info=False,
     assert A.shape == (n, n) and A.dtype == torch.float64 and A.is_cuda
     if fraction is None:
         fraction = float(k) / n
-    kk = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    kk = _count(n, fraction)
     o = opts if opts is not None else default_opts()
-    Acm = A.t().contiguous()
+    Acm = _sym_storage(A)
     nbytes = lib().qdwhp_eig_workspace(n, fraction, ctypes.byref(o))
     ws = _workspace(torch, nbytes, A.device)
     w = torch.empty(kk, dtype=torch.float64, device=A.device)
@@ -267,9 +289,9 @@ def eig_noalloc(A, fraction=None, k=None, which="largest", opts=None, return_inf
     assert A.shape == (n, n) and A.dtype == torch.float64 and A.is_cuda
     if fraction is None:
         fraction = float(k) / n
-    kk = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    kk = _count(n, fraction)
     o = opts if opts is not None else default_opts()
-    Acm = A.t().contiguous()
+    Acm = _sym_storage(A)
     w = torch.empty(kk, dtype=torch.float64, device=A.device)
     Vb = torch.empty((kk, n), dtype=torch.float64, device=A.device)
     info = Info()
@@ -359,7 +381,7 @@ def eig_hermitian(A, fraction, which="largest", opts=None, return_info=False):
     import torch
     n = A.shape[0]
     Ac = A.t().contiguous()                      # column-major, interleaved (re, im)
-    k = min(n, max(1, int(math.floor(fraction * n + 0.5))))
+    k = _count(n, fraction)
     o = opts if opts is not None else default_opts()
     w = torch.empty(k, dtype=torch.float64, device=A.device)
     Vb = torch.empty((k, n), dtype=torch.complex128, device=A.device)

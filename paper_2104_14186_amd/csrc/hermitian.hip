@@ -210,10 +210,7 @@ __global__ __launch_bounds__(PT) void phase_kernel(double* __restrict__ V, int64
   }
 }
 
-int64_t wanted(int64_t n, double fraction) {
-  const int64_t k = (int64_t)std::floor(fraction * (double)n + 0.5);
-  return std::min<int64_t>(n, std::max<int64_t>(1, k));
-}
+int64_t wanted(int64_t n, double fraction) { return qdwhp_eig_count(n, fraction); }
 
 // Workspace: M, w2, V2, the cluster table and a flag, then the real solve's.
 struct HLayout {

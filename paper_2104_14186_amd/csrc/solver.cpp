@@ -1140,14 +1140,20 @@ namespace {
 using qdwhp::SolveState;
 
 // ---- EIG (Algorithm 1) -----------------------------------------------------
+extern "C" int64_t qdwhp_eig_count(int64_t n, double fraction) {
+  if (n < 1 || !(fraction > 0.0) || fraction > 1.0) return 0;
+  const double k = std::floor(fraction * (double)n + 0.5);
+  return k < 1.0 ? 1 : (k >= (double)n ? n : (int64_t)k);
+}
+
 int eig_setup(SolveState& S) {
   const qdwhp_opts& o = S.o;
   if (!(o.tol > 0.0) || !(o.s_eig > 0.0 && o.s_eig < 1.0) || o.eig_iters < 1 || o.eig_iters > 16 ||
       o.zolo_r < 0 || o.zolo_r > kZoloMax)
     return S.ret(-11);
   const int64_t n = S.n;
-  int64_t k = (int64_t)std::floor(S.fraction * (double)n + 0.5);
-  S.k = k = std::min<int64_t>(n, std::max<int64_t>(1, k));
+  const int64_t k = qdwhp_eig_count(n, S.fraction);
+  S.k = k;
   S.info->k = k;
   S.nv = lz_vectors(o);
   S.msteps = lz_steps(o, n);

@@ -52,6 +52,26 @@ def test_eig_vs_oracle(n, f, seed, which):
     assert abs(info["ell"] - r["ell"]) <= 2
 
 
+def test_eig_storage_orders_bitwise():
+    """A symmetric A passed row-major (read in place), as a transposed view
+    (in place) or strided (copied) gives bitwise the same solve, and the
+    count is the library's."""
+    torch, q = _gpu()
+    n, f = 257, 0.15
+    A, lam = eig_uniform(n, 61)
+    At = torch.from_numpy(A).cuda()
+    big = torch.zeros((n, n + 5), dtype=torch.float64, device="cuda")
+    big[:, :n] = At
+    print(f"eig storage orders n={n} f={f}", flush=True)
+    outs = [q.eig(X, fraction=f, opts=q.default_opts(tol=TOL_LIB)) for X in (At, At.t(), big[:, :n])]
+    assert not big[:, :n].is_contiguous()
+    assert outs[0][0].shape[0] == q.lib().qdwhp_eig_count(n, f) == 39
+    for w, V in outs[1:]:
+        assert torch.equal(w, outs[0][0]) and torch.equal(V, outs[0][1])
+    exact = np.sort(lam)[::-1][:39]
+    assert np.max(np.abs(outs[0][0].cpu().numpy() - exact) / np.abs(exact)) < 1e-12
+
+
 @pytest.mark.parametrize("n,f,seed,which,kind,replay", [(800, 0.2, 21, "largest", "uniform", False),
                                                         (700, 0.15, 22, "smallest", "uniform", False),
                                                         (800, 0.2, 23, "largest", "clustered", False),
