@@ -450,6 +450,20 @@ int qdwhp_eig_noalloc(const double* A, int64_t n, int64_t lda, double fraction, 
 
 /* ---- tuning table ------------------------------------------------------ */
 /*
+ * Captured launch sequences (opts->graphs = 1) are kept per key (the
+ * workspace buffers, sizes, step kinds and precision plan of a solve) so
+ * that later solves on the same workspace replay them; they hold device
+ * resources until the process ends.  qdwhp_graphs_clear waits for the
+ * device (hipDeviceSynchronize, so no replay still runs) and destroys them
+ * all; call it after freeing a workspace that solves with graphs used, or
+ * to release the memory.  Returns 0 or QDWHP_ERR_HIP.  Later solves with
+ * graphs = 1 capture again.  qdwhp_graphs_count: the number kept (host
+ * only).  Neither may overlap a solve on another host thread.
+ */
+int qdwhp_graphs_clear(void);
+int64_t qdwhp_graphs_count(void);
+
+/*
  * Named integer parameters read by launch-shape decisions, written by the
  * autotuner (or by hand).  Keys: "gemm.small_tiles" (a GEMM whose 128x128
  * tile count is below this value runs with 64x64 tiles; default 96; GEMMs

@@ -124,6 +124,8 @@ _SIGS = {
     "qdwhp_tune_get": (_I64, [ctypes.c_char_p, _I64]),
     "qdwhp_tune_get_sized": (_I64, [ctypes.c_char_p, _I64, _I64]),
     "qdwhp_tune_clear": (None, []),
+    "qdwhp_graphs_clear": (_I, []),
+    "qdwhp_graphs_count": (_I64, []),
     "qdwhp_profile_begin": (None, []),
     "qdwhp_profile_end": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_I64)]),
 }

@@ -6,12 +6,13 @@
 // parameter block.  The first solve with a given key (workspace buffers,
 // sizes, step kinds, precision plan) records the sequence into a graph;
 // later solves with the same key replay it with one launch.  Entries live
-// until the process ends (executables are never destroyed while a replay
-// might still run); beyond kMaxGraphs keys, sequences run uncaptured.
+// until qdwhp_graphs_clear (which waits for the device first) or the end of
+// the process; beyond kMaxGraphs keys, sequences run uncaptured.
 #include <map>
 #include <mutex>
 #include <vector>
 
+#include "qdwhp.h"
 #include "common.h"
 #include "graphs.h"
 
@@ -68,3 +69,15 @@ size_t graph_count() {
 }
 
 }  // namespace qdwhp
+
+extern "C" int qdwhp_graphs_clear(void) {
+  std::lock_guard<std::mutex> g(qdwhp::mu);
+  if (qdwhp::cache().empty()) return QDWHP_OK;
+  // no replay may still be running when its executable goes
+  if (hipDeviceSynchronize() != hipSuccess) return QDWHP_ERR_HIP;
+  for (auto& e : qdwhp::cache()) (void)hipGraphExecDestroy(e.second);
+  qdwhp::cache().clear();
+  return QDWHP_OK;
+}
+
+extern "C" int64_t qdwhp_graphs_count(void) { return (int64_t)qdwhp::graph_count(); }

@@ -51,6 +51,8 @@ def test_host_only_calls():
     assert q.tune_get("test.key", -1) == 7
     assert q.tune_get("test.absent", 3) == 3
     assert L.qdwhp_eig_workspace(512, 0.1, ctypes.byref(o)) > 512 * 512 * 8
+    # no graph captured yet: clearing touches no device
+    assert L.qdwhp_graphs_count() == 0 and L.qdwhp_graphs_clear() == 0
     # k = floor(fraction n + 1/2) in [1, n]; 0 for arguments the solvers reject
     for n, f, k in ((16384, 0.2, 3277), (16384, 0.01, 164), (7, 0.5, 4), (10, 1e-9, 1), (10, 1.0, 10),
                     (10, 0.0, 0), (10, 1.5, 0), (0, 0.5, 0), (10, float("nan"), 0)):

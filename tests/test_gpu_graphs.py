@@ -73,6 +73,30 @@ def test_eig_graph_replays_equal_eager(precision):
     assert len(kinds) >= 1
 
 
+def test_graphs_clear_then_capture_again():
+    """qdwhp_graphs_clear destroys the kept graphs; the next solve captures
+    again and still equals the uncaptured solve bitwise."""
+    torch = _torch()
+    import paper_2104_14186_amd as q
+    from synthetic import eig_uniform
+    n, f = 300, 0.1
+    print("eig graphs clear", n, f, flush=True)
+    eager = q.default_opts()
+    graph = q.default_opts(graphs=1)
+    nbytes = q.lib().qdwhp_eig_workspace(n, f, ctypes.byref(eager))
+    ws = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device="cuda")
+    A, _ = eig_uniform(n, 34, device=torch.device("cuda"))
+    e = _eig_fixed_ws(q, torch, A, f, eager, ws)
+    g1 = _eig_fixed_ws(q, torch, A, f, graph, ws)
+    assert q.lib().qdwhp_graphs_count() >= 1
+    assert q.lib().qdwhp_graphs_clear() == 0
+    assert q.lib().qdwhp_graphs_count() == 0
+    g2 = _eig_fixed_ws(q, torch, A, f, graph, ws)
+    assert q.lib().qdwhp_graphs_count() >= 1
+    for g in (g1, g2):
+        assert bool((g[0] == e[0]).all()) and bool((g[1] == e[1]).all())
+
+
 def test_svd_graph_replays_equal_eager():
     torch = _torch()
     import paper_2104_14186_amd as q
