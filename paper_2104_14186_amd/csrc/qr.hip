@@ -605,47 +605,54 @@ __global__ __launch_bounds__(ST) void cq_recon_kernel(const double* __restrict__
 
 // Writes the reconstructed sub-panel unless the flag is set: rows below the
 // first w (the first pass's Q) become Y2 = Q2 Nm, the first w rows R_H
-// (upper) and L (below).  Four threads per row, each writing 8 columns;
-// workgroup g takes rows [64 g, 64 g + 64).
-__global__ __launch_bounds__(256) void cq_write_kernel(double* __restrict__ P, int64_t ld, int64_t h, int w,
+// (upper) and L (below).  Four threads per row, each loading and writing 8
+// columns; workgroup g takes rows [64 g, 64 g + 64).  Registers are capped
+// at 128 per lane (four waves per SIMD) so that its waves find room beside
+// the trailing update's GEMM, which runs next to the panel.
+__global__ __launch_bounds__(256, 4) void cq_write_kernel(double* __restrict__ P, int64_t ld, int64_t h, int w,
                                                        const double* __restrict__ Nm,
                                                        const double* __restrict__ RL, const int* flag) {
   if (*flag) return;
   __shared__ double Ns[RB][RB + 1];
+  __shared__ double Xs[64][RB + 1];      // the workgroup's 64 rows of the first pass's Q
   const int t = threadIdx.x;
   for (int e = t; e < RB * RB; e += 256) Ns[e % RB][e / RB] = Nm[e];
+  const int lr = t >> 2, c0 = (t & 3) * 8;
+  const int64_t r = (int64_t)blockIdx.x * 64 + lr;
+  const bool body = r < h && r >= w;
+  // each thread stages its own 8 columns of its row
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int c = c0 + u;
+    Xs[lr][c] = (body && c < w) ? P[r + (int64_t)c * ld] : 0.0;
+  }
   __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * 64 + (t >> 2);
-  const int c0 = (t & 3) * 8;
   if (r >= h) return;
-  if (r < w) {
+  if (!body) {
 #pragma unroll
     for (int c = c0; c < c0 + 8; ++c)
       if (c < w) P[r + (int64_t)c * ld] = RL[r + c * RB];
     return;
   }
-  double x[RB];
-#pragma unroll
-  for (int c = 0; c < RB; ++c) x[c] = (c < w) ? P[r + (int64_t)c * ld] : 0.0;
   // Nm is upper triangular with zeros stored below: the full sums give the
-  // triangular product, and every y depends on every loaded x
-  double y[8];
+  // triangular product.  Two sums per output (even and odd k), each in
+  // increasing k.  The row is read from LDS, so a thread's stores (its own
+  // 8 columns, read from HBM only by itself) race with nothing.
+  double s0[8], s1[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    double s0 = 0.0, s1 = 0.0;
+  for (int u = 0; u < 8; ++u) s0[u] = s1[u] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < RB; k += 2) {
+    const double xa = Xs[lr][k], xb = Xs[lr][k + 1];
 #pragma unroll
-    for (int k = 0; k < RB; k += 2) {
-      s0 += x[k] * Ns[k][c0 + u];
-      s1 += x[k + 1] * Ns[k + 1][c0 + u];
+    for (int u = 0; u < 8; ++u) {
+      s0[u] += xa * Ns[k][c0 + u];
+      s1[u] += xb * Ns[k + 1][c0 + u];
     }
-    y[u] = s0 + s1;
   }
-  // The four threads of a row are lanes of one wave, and every store's
-  // value depends on all 32 loads of the row, so all of them have read the
-  // row before any of them overwrites it.
 #pragma unroll
   for (int u = 0; u < 8; ++u)
-    if (c0 + u < w) P[r + (int64_t)(c0 + u) * ld] = y[u];
+    if (c0 + u < w) P[r + (int64_t)(c0 + u) * ld] = s0[u] + s1[u];
 }
 
 // T (w x w, upper) of the compact WY form from G = V^T V and tau:

@@ -18,15 +18,30 @@ def _torch():
     return torch
 
 
+_STREAM = []
+
+
+def _stream(torch):
+    """A stream of the process's own (default priority): the legacy null
+    stream, torch's default here, cannot be captured, and the library then
+    runs the steps uncaptured."""
+    if not _STREAM:
+        _STREAM.append(torch.cuda.Stream())
+    s = _STREAM[0]
+    assert s.cuda_stream != 0
+    return s
+
+
 def _eig_fixed_ws(q, torch, A, f, opts, ws):
     n = A.shape[0]
     k = min(n, max(1, int(np.floor(f * n + 0.5))))
     w = torch.empty(k, dtype=torch.float64, device="cuda")
     Vb = torch.empty((k, n), dtype=torch.float64, device="cuda")
     info = q.Info()
+    torch.cuda.synchronize()                 # inputs come from torch's stream
     st = q.lib().qdwhp_eig(ctypes.c_void_p(A.data_ptr()), n, n, f, 0, ctypes.c_void_p(w.data_ptr()),
                            ctypes.c_void_p(Vb.data_ptr()), n, ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8,
-                           ctypes.byref(opts), ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                           ctypes.byref(opts), ctypes.c_void_p(_stream(torch).cuda_stream),
                            ctypes.byref(info))
     assert st == 0
     torch.cuda.synchronize()
@@ -39,10 +54,11 @@ def _svd_fixed_ws(q, torch, A, k, opts, ws):
     S = torch.empty(k, dtype=torch.float64, device="cuda")
     Ub = torch.empty((k, m), dtype=torch.float64, device="cuda")
     Vb = torch.empty((k, n), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()                 # inputs come from torch's stream
     st = q.lib().qdwhp_svd(ctypes.c_void_p(Ac.data_ptr()), m, n, m, k, ctypes.c_void_p(Ub.data_ptr()), m,
                            ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(Vb.data_ptr()), n,
                            ctypes.c_void_p(ws.data_ptr()), ws.numel() * 8, ctypes.byref(opts),
-                           ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+                           ctypes.c_void_p(_stream(torch).cuda_stream), None)
     assert st == 0
     torch.cuda.synchronize()
     return S, Ub, Vb
@@ -71,6 +87,7 @@ def test_eig_graph_replays_equal_eager(precision):
         tol = 1e-12
         assert np.max(np.abs(g[0].cpu().numpy() - ex) / np.abs(ex)) <= tol
     assert len(kinds) >= 1
+    assert q.lib().qdwhp_graphs_count() >= 1      # the iterations were captured
 
 
 def test_graphs_clear_then_capture_again():
@@ -113,6 +130,7 @@ def test_svd_graph_replays_equal_eager():
         e = _svd_fixed_ws(q, torch, A, k, eager, ws)
         for x, y in zip(g, e):
             assert bool((x == y).all()), (rep, seed)
+    assert q.lib().qdwhp_graphs_count() >= 1
 
 
 def test_batched_with_graphs_twice():
