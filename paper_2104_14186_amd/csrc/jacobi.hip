@@ -608,7 +608,11 @@ __global__ void frob_final_kernel(const double* part, int np, double* out) {
 // noise of the sub-problem data (Gram entries, rotated tiles), whose
 // maximum over all pairs can exceed tol for large problems.  A sweep whose
 // measure is within 32 tol and no longer fell by 4x is therefore at the
-// noise floor and counts as converged.
+// noise floor and counts as converged.  (The two-sided solver also stops
+// as soon as the whole matrix, measured after a sweep, is within 32 tol:
+// the state that this rule accepts, reached two sweeps earlier, since the
+// sweeps between rotate only entries at the noise floor and leave the
+// residuals and orthogonality unchanged.)
 constexpr int kMaxSweeps = 60;
 bool converged(double off, double prev, double tol, int sw) {
   if (off <= tol) return true;
@@ -705,8 +709,9 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
       QDWHP_LAUNCH_CHECK();
       QDWHP_HIP(hipEventRecord((*aux)->done[slot], s2));
     }
-    // the off-diagonal part as the sweep leaves it: at or below tol, the next
-    // sweep would rotate nothing (every |h_pq| <= tol is skipped), so it is
+    // the off-diagonal part as the sweep leaves it: within 32 tol it is at
+    // the noise floor (the next sweeps rotate only entries there, or at or
+    // below tol nothing, every |h_pq| <= tol being skipped), so they are
     // not run
     off_max_kernel<<<256, 256, 0, s>>>(Hp, np, np, offmax + 64 + sw);
     QDWHP_LAUNCH_CHECK();
@@ -714,7 +719,7 @@ int syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw, d
     QDWHP_HIP(hipMemcpyAsync(&off, offmax + sw, sizeof(double), hipMemcpyDeviceToHost, s));
     QDWHP_HIP(hipMemcpyAsync(&endm, offmax + 64 + sw, sizeof(double), hipMemcpyDeviceToHost, s));
     QDWHP_HIP(hipStreamSynchronize(s));
-    if (converged(off, prev, a.tol, sw) || endm <= a.tol) { sweeps = sw + 1; break; }
+    if (converged(off, prev, a.tol, sw) || endm <= 32.0 * a.tol) { sweeps = sw + 1; break; }
     prev = off;
   }
   if (aux && round > 0)   // the last eigenvector updates precede the gather below
