@@ -234,11 +234,12 @@ def _info_dict(info):
     return info.as_dict()
 
 
-def _count(n, fraction):
-    """k for this n and fraction, as the library computes it."""
+def _count(n, fraction, where="qdwhp_eig"):
+    """k for this n and fraction, as the library computes it; the library's
+    own status for the argument it would reject (n: -2, fraction: -4)."""
     kk = int(lib().qdwhp_eig_count(n, float(fraction)))
     if kk < 1:
-        raise ValueError(f"fraction {fraction} outside (0, 1] or n = {n} < 1")
+        raise QdwhpError(-2 if n < 1 else -4, where)
     return kk
 
 
@@ -383,7 +384,7 @@ def eig_hermitian(A, fraction, which="largest", opts=None, return_info=False):
     import torch
     n = A.shape[0]
     Ac = A.t().contiguous()                      # column-major, interleaved (re, im)
-    k = _count(n, fraction)
+    k = _count(n, fraction, "qdwhp_heig")
     o = opts if opts is not None else default_opts()
     w = torch.empty(k, dtype=torch.float64, device=A.device)
     Vb = torch.empty((k, n), dtype=torch.complex128, device=A.device)

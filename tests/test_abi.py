@@ -57,6 +57,10 @@ def test_host_only_calls():
     for n, f, k in ((16384, 0.2, 3277), (16384, 0.01, 164), (7, 0.5, 4), (10, 1e-9, 1), (10, 1.0, 10),
                     (10, 0.0, 0), (10, 1.5, 0), (0, 0.5, 0), (10, float("nan"), 0)):
         assert L.qdwhp_eig_count(n, f) == k, (n, f)
+    # the binding reports a rejected fraction with the library's status
+    with pytest.raises(q.QdwhpError) as e:
+        q._count(10, 1.5)
+    assert e.value.status == -4
     p = q.Problem()
     p.type, p.m, p.n, p.k = q.PROBLEM_SVD, 300, 200, 10
     assert L.qdwhp_problem_workspace(ctypes.byref(p), ctypes.byref(o)) == L.qdwhp_svd_workspace(300, 200, 10, ctypes.byref(o))
