@@ -15,7 +15,8 @@ namespace qdwhp {
 namespace {
 
 constexpr int LZ_T = 256;
-constexpr int LZ_ROWS = 2048;      // rows per workgroup in the dot/update kernels
+constexpr int LZ_ROWS = 2048;      // up to this n, one workgroup per run does a whole step
+constexpr int LZ_CHUNK = 512;      // rows per workgroup of the partial dot products
 
 __device__ inline void philox_round(uint32_t c[4], uint32_t k0, uint32_t k1) {
   const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
@@ -104,8 +105,8 @@ __global__ __launch_bounds__(LZ_T) void dots_kernel(const double* Q, int64_t n, 
   if (active && !active[run]) return;
   const double* Qr = Q + run * qstride;
   const double* w = W + run * wstride;
-  const int64_t r0 = (int64_t)ch * LZ_ROWS;
-  const int64_t r1 = (r0 + LZ_ROWS < n) ? r0 + LZ_ROWS : n;
+  const int64_t r0 = (int64_t)ch * LZ_CHUNK;
+  const int64_t r1 = (r0 + LZ_CHUNK < n) ? r0 + LZ_CHUNK : n;
   block_dots(Qr, n, r0, r1, w, ncol, red, part + ((int64_t)run * nchunk + ch) * 128);
 }
 
@@ -210,8 +211,8 @@ __device__ inline double gaussian_entry(int64_t r, uint64_t seed, uint64_t strea
 }
 
 // Two passes of classical Gram-Schmidt of w against q_0..q_j by one
-// workgroup (rows r = t + LZ_T i of each thread), in the arithmetic order of
-// dots_kernel / sub_kernel with a single row chunk; d0 (optional) receives
+// workgroup (rows r = t + LZ_T i of each thread), the arithmetic of
+// dots_kernel / sub_kernel over a single row chunk; d0 (optional) receives
 // the first pass's coefficients.
 __device__ inline void cgs2_block(const double* Qr, int64_t n, double* w, int ncol, double* d,
                                   double* red, double* d0) {
@@ -231,7 +232,8 @@ __device__ inline void cgs2_block(const double* Qr, int64_t n, double* w, int nc
 // Everything of Lanczos step j after the operator product, for n <= LZ_ROWS,
 // in one launch (one workgroup per run): re-orthogonalisation, norm, the
 // step bookkeeping of step_kernel, the restart of a run that broke down, and
-// q_{j+1}.  Same results as the multi-launch sequence.
+// q_{j+1}.  The multi-launch sequence, taken above LZ_ROWS, sums its dot
+// products over row chunks of LZ_CHUNK; here they come from one chunk.
 __global__ __launch_bounds__(LZ_T) void step_fused_kernel(double* Q, int64_t n, int64_t qstride, double* W,
                                                           int nv, int m, int j, uint64_t seed, double* dvec,
                                                           double* alpha, double* beta, double* amax,
@@ -347,7 +349,7 @@ __global__ void tridiag_eig_kernel(const double* alpha, const double* beta, int 
 
 int64_t lanczos_doubles(int64_t n, int64_t rows_op, int nv, int m) {
   const int64_t N = (int64_t)nv * m;
-  const int64_t nchunk = cdiv(n > rows_op ? n : rows_op, LZ_ROWS);
+  const int64_t nchunk = cdiv(n > rows_op ? n : rows_op, LZ_CHUNK);
   return n * (int64_t)(m + 1) * nv       // bases
          + 2 * n * nv + rows_op * nv      // w, spare, operator temp
          + 2 * nv * 128 * nchunk          // partials
@@ -365,12 +367,13 @@ void gaussian_fill(double* out, int64_t count, uint64_t seed, uint64_t stream, h
 LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t seed, double* ws,
                       hipStream_t s) {
   const int64_t N = (int64_t)nv * m;
-  const int nchunk = (int)cdiv(n, LZ_ROWS);
+  const int nchunk = (int)cdiv(n, LZ_CHUNK);
+  const bool fused = n <= LZ_ROWS;
   double* Q = ws;                 ws += n * (int64_t)(m + 1) * nv;   // run i: Q + i*n*(m+1)
   double* Wv = ws;                ws += n * nv;
   double* G = ws;                 ws += n * nv;
   double* tmp = ws;               ws += op.rows_tmp * nv;
-  double* part = ws;              ws += 2 * (int64_t)nv * 128 * cdiv(n > op.rows_tmp ? n : op.rows_tmp, LZ_ROWS);
+  double* part = ws;              ws += 2 * (int64_t)nv * 128 * cdiv(n > op.rows_tmp ? n : op.rows_tmp, LZ_CHUNK);
   double* dvec = ws;              ws += nv * 128 * 2;
   double* alpha = ws;             ws += (int64_t)nv * m;
   double* beta = ws;              ws += (int64_t)nv * m;
@@ -401,7 +404,7 @@ LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t se
   for (int j = 0; j < m; ++j) {
     // w = Op q_j for all runs (columns at stride qs)
     op.apply(Q + (int64_t)j * n, qs, Wv, n, tmp, s);
-    if (nchunk == 1) {   // one workgroup per run covers the vector: one launch for the rest
+    if (fused) {   // one workgroup per run covers the vector: one launch for the rest
       step_fused_kernel<<<nv, LZ_T, 0, s>>>(Q, n, qs, Wv, nv, m, j, seed, dvec, alpha, beta, amax, d_active);
       QDWHP_LAUNCH_CHECK();
       continue;
