@@ -286,14 +286,18 @@ __global__ __launch_bounds__(LZ_T) void step_fused_kernel(double* Q, int64_t n, 
 // first and last rows of the eigenvector matrix are carried along: the
 // Gauss-quadrature weight of node i is (first component)^2 (Golub & Welsch)
 // and its Ritz residual is |beta_m| |last component|.
+// The serial QR iteration of one run is a chain of dependent reads and
+// writes of d, e, z0, zl: with lds set they live in LDS (one padded slice
+// per thread), else in the global scratch; the arithmetic is the same.
 __global__ void tridiag_eig_kernel(const double* alpha, const double* beta, int nv, int m,
                                    double* scratch, double* theta, double* weight, double* resid,
-                                   int* fail) {
+                                   int* fail, int lds) {
+  extern __shared__ double sl[];
   if (threadIdx.x == 0) *fail = 0;
   __syncthreads();
   const int run = blockIdx.x * blockDim.x + threadIdx.x;
   if (run >= nv) return;
-  double* d = scratch + (int64_t)run * 4 * m;
+  double* d = lds ? sl + (int64_t)threadIdx.x * (4 * m + 1) : scratch + (int64_t)run * 4 * m;
   double* e = d + m;
   double* z0 = e + m;
   double* zl = z0 + m;
@@ -440,7 +444,11 @@ LanczosResult lanczos(const LanczosOp& op, int64_t n, int nv, int m, uint64_t se
     QDWHP_LAUNCH_CHECK();
   }
   int* d_fail = d_active + nv;
-  tridiag_eig_kernel<<<1, 64, 0, s>>>(alpha, beta, nv, m, tscr, theta, weight, resid, d_fail);
+  // nv <= 64 runs, one thread each; LDS while their slices fit in 64 KiB
+  const size_t tlds = (size_t)nv * (4 * (size_t)m + 1) * sizeof(double);
+  const int use_lds = tlds <= 65536 ? 1 : 0;
+  tridiag_eig_kernel<<<1, 64, use_lds ? tlds : 0, s>>>(alpha, beta, nv, m, tscr, theta, weight, resid, d_fail,
+                                                       use_lds);
   QDWHP_LAUNCH_CHECK();
   std::vector<double> h_a((size_t)N), h_b((size_t)N), th(N), wt(N), rs(N);
   int h_fail = 0;
