@@ -293,8 +293,11 @@ int qdwhp_orgqr(const double* A, int64_t m, int64_t n, int64_t lda,
  * Jacobi (the Rayleigh-Ritz solve of Algorithm 1): on exit w[n] holds the
  * eigenvalues in descending order and W (n x n, ldw >= n) the eigenvectors.
  * H is read only (both triangles).  work: qdwhp_syev_workspace(n) bytes.
- * *sweeps (optional) receives the sweep count; QDWHP_ERR_NOCONV if the
- * stopping rule was not met within 60 sweeps.
+ * Stopping rule, with tol = 2u ||H||_F / sqrt(n): the largest off-diagonal
+ * entry after a sweep is within 32 tol, or the largest seen during a sweep
+ * is at or below tol, or within 32 tol and no longer falling by 4x (the
+ * rounding floor).  *sweeps (optional) receives the sweep count;
+ * QDWHP_ERR_NOCONV if the rule was not met within 60 sweeps.
  */
 size_t qdwhp_syev_workspace(int64_t n);
 int qdwhp_syev(double* H, int64_t n, int64_t ldh, double* w, double* W, int64_t ldw,
