@@ -72,6 +72,26 @@ def test_eig_storage_orders_bitwise():
     assert np.max(np.abs(outs[0][0].cpu().numpy() - exact) / np.abs(exact)) < 1e-12
 
 
+def test_eig_large_lanczos_block_vs_planted():
+    """32 Lanczos runs of 100 steps: the runs' tridiagonal QR works in global
+    scratch (their arrays exceed 64 KiB of LDS) instead of LDS; values and
+    residuals against the planted spectrum and the oracle's."""
+    torch, q = _gpu()
+    n, f = 600, 0.1
+    A, lam = eig_uniform(n, 62)
+    print(f"eig n={n} f={f} lanczos 32 x 100", flush=True)
+    opts = q.default_opts(tol=TOL_LIB, lanczos_vectors=32, lanczos_steps=100)
+    w, V, info = q.eig(torch.from_numpy(A).cuda(), fraction=f, opts=opts, return_info=True)
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    k = info["k"]
+    exact = np.sort(lam)[::-1][:k]
+    assert np.max(np.abs(w - exact) / np.abs(exact)) < 1e-12
+    met = oracle.eig_metrics(A, w, V, exact)
+    assert met["residual"] < 1e-13 and met["orth"] < 1e-12, met
+    r = oracle.eig_partial(A, fraction=f, tol=TOL_LIB)
+    assert np.max(np.abs(w - r["w"]) / np.abs(r["w"])) < 1e-12
+
+
 @pytest.mark.parametrize("n,f,seed,which,kind,replay", [(800, 0.2, 21, "largest", "uniform", False),
                                                         (700, 0.15, 22, "smallest", "uniform", False),
                                                         (800, 0.2, 23, "largest", "clustered", False),
